@@ -1,0 +1,395 @@
+"""Plain, slow, obviously correct CPU FP64 oracle of the sLdG projection sweep.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this module.  It shares no code, header, table or
+constant generator with the HIP library; the two meet only through data
+(seeded inputs, which the tests hand to both sides).
+
+Method (L. Einkemmer, "A mixed precision semi-Lagrangian algorithm and its
+performance on accelerators", arXiv 1603.07008):
+
+* Section II, eq. (1): Cheng-Knorr splitting reduces the Vlasov equation to 1D
+  constant-coefficient advections u_t + a u_x = 0, each solved exactly along
+  characteristics followed by an L2 projection (section II-A).
+* Section II-A: in each cell the solution is a polynomial of degree k written
+  in the Legendre basis, u = sum_j c_j P_j(2(x - x_i)/h); the coefficients
+  follow eq. (cj), c_j = (2j+1)/2 * int_{-1}^{1} u P_j.
+* Section II-A, update rule: the projection of the translated approximant gives
+  c_new[i] = A c[i-s] + B c[i-s-1], with A, B in R^{o x o}, o = k+1, depending
+  only on the fractional part of the displacement.
+* Section II-A (storage of c_0) and section III-A: c_0, the cell mean, is kept
+  in double precision and the higher modes in a narrower format, which keeps
+  the mass conserved to double precision.
+
+Readings of the paper taken here (each one is listed in the design notes):
+* The displacement sigma = a*dt/h is in cells; s = floor(sigma) (the integer
+  part of the CFL number in section II-A, read as floor so that the fractional
+  part alpha lies in [0, 1) for either sign), then alpha is snapped so that
+  alpha + (1 - alpha) == 1 exactly in FP64; an alpha that rounds to 1 is taken
+  as s + 1, alpha = 0.
+* A and B are the exact values of their defining integrals, evaluated here in
+  exact rational arithmetic and rounded once to FP64 (the paper notes that
+  Gauss-Legendre quadrature evaluates them exactly; rational arithmetic gives
+  the same numbers without the quadrature's rounding).
+* The grid is periodic in every dimension; in several dimensions each line
+  (fixed transverse cell) uses the displacement at its transverse cell centre.
+* Mass = (prod h) * sum of c_0 (c_0 is the cell mean).
+"""
+import ctypes
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+
+from . import build as _build
+
+TIERS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        path = _build.build(force=False)
+        lib = ctypes.CDLL(path)
+        lib.oracle_sweep.restype = None
+        lib.oracle_sweep.argtypes = [
+            ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+        lib.oracle_round_tier.restype = ctypes.c_double
+        lib.oracle_round_tier.argtypes = [ctypes.c_double, ctypes.c_int]
+        lib.oracle_round_array.restype = None
+        lib.oracle_round_array.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int]
+        lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_num_threads.argtypes = []
+        _lib = lib
+    return _lib
+
+
+def num_threads():
+    """OpenMP threads the oracle's C sweep runs on."""
+    return _load().oracle_num_threads()
+
+
+# ---------------------------------------------------------------------------
+# Legendre polynomials and the projection matrices (section II-A)
+# ---------------------------------------------------------------------------
+
+def legendre_monomial(j):
+    """Exact monomial coefficients (ascending powers) of P_j on [-1, 1].
+
+    Bonnet's recurrence (n+1) P_{n+1} = (2n+1) x P_n - n P_{n-1}, P_0 = 1,
+    P_1 = x (the Legendre polynomials of section II-A)."""
+    prev, cur = [Fraction(1)], [Fraction(0), Fraction(1)]
+    if j == 0:
+        return prev
+    for nn in range(1, j):
+        xcur = [Fraction(0)] + cur
+        prevp = prev + [Fraction(0)] * (len(xcur) - len(prev))
+        nxt = [(Fraction(2 * nn + 1) * a - Fraction(nn) * b) / (nn + 1)
+               for a, b in zip(xcur, prevp)]
+        prev, cur = cur, nxt
+    return cur
+
+
+def _poly_shift(p, c):
+    """Coefficients of q(x) = p(x - c) (binomial expansion)."""
+    out = [Fraction(0)] * len(p)
+    for m, a in enumerate(p):
+        if a == 0:
+            continue
+        for r in range(m + 1):
+            out[r] += a * math.comb(m, r) * (-c) ** (m - r)
+    return out
+
+
+def _poly_mul(p, q):
+    out = [Fraction(0)] * (len(p) + len(q) - 1)
+    for i, a in enumerate(p):
+        for j, b in enumerate(q):
+            out[i + j] += a * b
+    return out
+
+
+def _poly_integral(p, a, b):
+    """int_a^b p(x) dx, exactly."""
+    tot = Fraction(0)
+    for m, c in enumerate(p):
+        tot += c * (b ** (m + 1) - a ** (m + 1)) / (m + 1)
+    return tot
+
+
+def snap_shift(sigma):
+    """Displacement in cells -> (s, alpha), alpha in [0, 1), alpha + (1-alpha) == 1.
+
+    s is the integer part of the displacement (section II-A, update rule),
+    read as floor."""
+    sigma = float(sigma)
+    s = math.floor(sigma)
+    alpha = sigma - s
+    beta = 1.0 - alpha
+    alpha = 1.0 - beta
+    if alpha >= 1.0:          # sigma just below an integer rounded up
+        s, alpha = s + 1, 0.0
+    return int(s), float(alpha)
+
+
+def ab_exact(alpha, k):
+    """A(alpha), B(alpha) of section II-A's update rule, correctly rounded to FP64.
+
+    For cell i and displacement s + alpha (cells), the translated approximant
+    restricted to cell i comes from cell i-s on xi in [2 alpha - 1, 1] (local
+    coordinate xi - 2 alpha there) and from cell i-s-1 on xi in [-1, 2 alpha - 1]
+    (local coordinate xi - 2 alpha + 2).  Projecting with eq. (cj):
+        A[j][l] = (2j+1)/2 int_{2a-1}^{1}  P_j(xi) P_l(xi - 2a) dxi
+        B[j][l] = (2j+1)/2 int_{-1}^{2a-1} P_j(xi) P_l(xi - 2a + 2) dxi
+    The integrands are polynomials, so the integrals are evaluated exactly in
+    rational arithmetic and rounded once."""
+    a = Fraction(alpha)
+    o = k + 1
+    P = [legendre_monomial(j) for j in range(o)]
+    A = np.zeros((o, o))
+    B = np.zeros((o, o))
+    for l in range(o):
+        pa = _poly_shift(P[l], 2 * a)
+        pb = _poly_shift(P[l], 2 * a - 2)
+        for j in range(o):
+            w = Fraction(2 * j + 1, 2)
+            A[j, l] = float(w * _poly_integral(_poly_mul(P[j], pa), 2 * a - 1, Fraction(1)))
+            B[j, l] = float(w * _poly_integral(_poly_mul(P[j], pb), Fraction(-1), 2 * a - 1))
+    return A, B
+
+
+_ab_cache = {}
+
+
+def line_tables(sigma, k):
+    """Per-line (s, [A; B]) tables for an array of displacements (cells)."""
+    sigma = np.ascontiguousarray(sigma, dtype=np.float64).ravel()
+    o = k + 1
+    s_tab = np.empty(sigma.size, dtype=np.int32)
+    ab_tab = np.empty((sigma.size, 2, o, o), dtype=np.float64)
+    for t, sg in enumerate(sigma):
+        s, alpha = snap_shift(sg)
+        key = (alpha, k)
+        if key not in _ab_cache:
+            _ab_cache[key] = ab_exact(alpha, k)
+        A, B = _ab_cache[key]
+        s_tab[t] = s
+        ab_tab[t, 0] = A
+        ab_tab[t, 1] = B
+    return s_tab, ab_tab
+
+
+# ---------------------------------------------------------------------------
+# Grid helpers
+# ---------------------------------------------------------------------------
+
+def n_modes(ndim, k):
+    return (k + 1) ** ndim
+
+
+def n_cells(ns):
+    return int(np.prod(ns))
+
+
+def line_strides(ns, dep):
+    """Stride of each dimension in a per-line table indexed over the dims in
+    `dep` (dimension 0 fastest), 0 for the other dimensions."""
+    st = np.zeros(len(ns), dtype=np.int64)
+    acc = 1
+    for e in sorted(dep):
+        st[e] = acc
+        acc *= ns[e]
+    return st, acc
+
+
+# ---------------------------------------------------------------------------
+# Sweep (section II-A update rule), via the plain C loops in sweep.c
+# ---------------------------------------------------------------------------
+
+def sweep(state, ns, k, dim, sigma, dep=(), tier="fp64", sel=None):
+    """One sLdG projection sweep along `dim`.
+
+    state  float64 [o^ndim, cells] (mode-major, cells dimension-0 fastest)
+    sigma  displacement in cells per line, indexed over the dims in `dep`
+           (dimension 0 fastest); a scalar when dep is empty
+    tier   storage emulation for modes m != 0 ('fp64', 'fp32', 'bf16', 'fp16')
+    sel    optional int64 array of output cells; then the result is
+           [o^ndim, len(sel)]
+    """
+    ns = [int(v) for v in ns]
+    ndim = len(ns)
+    if dim in dep:
+        raise ValueError("the displacement of a sweep cannot depend on the swept dimension")
+    state = np.ascontiguousarray(state, dtype=np.float64)
+    M, C = n_modes(ndim, k), n_cells(ns)
+    if state.shape != (M, C):
+        raise ValueError(f"state shape {state.shape} != {(M, C)}")
+    stride, ntab = line_strides(ns, dep)
+    sigma = np.atleast_1d(np.asarray(sigma, dtype=np.float64)).ravel()
+    if sigma.size != ntab:
+        raise ValueError(f"need {ntab} displacements, got {sigma.size}")
+    s_tab, ab_tab = line_tables(sigma, k)
+    if sel is None:
+        out = np.empty((M, C))
+        nsel, selp = C, None
+    else:
+        sel = np.ascontiguousarray(sel, dtype=np.int64)
+        out = np.empty((M, sel.size))
+        nsel, selp = sel.size, sel.ctypes.data
+    nsarr = np.asarray(ns, dtype=np.int64)
+    _load().oracle_sweep(ndim, nsarr.ctypes.data, k, dim, stride.ctypes.data,
+                         s_tab.ctypes.data, ab_tab.ctypes.data, TIERS[tier],
+                         state.ctypes.data, out.ctypes.data, nsel, selp)
+    return out
+
+
+def round_tier(x, tier):
+    """Round-to-nearest-even of every element onto the tier's storage format."""
+    x = np.array(x, dtype=np.float64, copy=True)
+    _load().oracle_round_array(x.ctypes.data, x.size, TIERS[tier])
+    return x
+
+
+def to_tier(state, tier):
+    """Emulated storage of a state: mode 0 stays FP64, the others are rounded."""
+    out = np.array(state, dtype=np.float64, copy=True)
+    if tier != "fp64":
+        out[1:] = round_tier(out[1:], tier)
+    return out
+
+
+def run_sequence(state, ns, k, seq, tier="fp64", steps=1):
+    """Apply a list of sweeps (dim, sigma, dep) `steps` times (section II,
+    eq. (1): the split step is a composition of 1D advections)."""
+    for _ in range(steps):
+        for dim, sigma, dep in seq:
+            state = sweep(state, ns, k, dim, sigma, dep, tier)
+    return state
+
+
+# ---------------------------------------------------------------------------
+# Initial projection, eq. (cj)
+# ---------------------------------------------------------------------------
+
+def gauss_legendre(nq):
+    """Gauss-Legendre nodes and weights on [-1, 1] (library routine)."""
+    return np.polynomial.legendre.leggauss(nq)
+
+
+def legendre_values(k, xi):
+    """P_0..P_k at points xi (Bonnet's recurrence in FP64), shape [k+1, len(xi)]."""
+    xi = np.asarray(xi, dtype=np.float64)
+    out = np.zeros((k + 1,) + xi.shape)
+    out[0] = 1.0
+    if k >= 1:
+        out[1] = xi
+    for nn in range(1, k):
+        out[nn + 1] = ((2 * nn + 1) * xi * out[nn] - nn * out[nn - 1]) / (nn + 1)
+    return out
+
+
+def project_1d(f, n, lo, hi, k, nq=None):
+    """Eq. (cj) on a 1D grid with an nq-point Gauss-Legendre rule (default k+1).
+    Returns [k+1, n]."""
+    nq = k + 1 if nq is None else nq
+    xg, wg = gauss_legendre(nq)
+    h = (hi - lo) / n
+    centres = lo + (np.arange(n) + 0.5) * h
+    x = centres[None, :] + 0.5 * h * xg[:, None]              # [nq, n]
+    fx = np.asarray(f(x), dtype=np.float64)
+    P = legendre_values(k, xg)                                 # [o, nq]
+    coef = np.empty((k + 1, n))
+    for j in range(k + 1):
+        coef[j] = (2 * j + 1) / 2.0 * np.sum(wg[:, None] * P[j][:, None] * fx, axis=0)
+    return coef
+
+
+def project_separable(terms, ns, los, his, k, nq=None):
+    """Eq. (cj) in several dimensions for f = sum_t prod_e f_{t,e}(x_e).
+
+    A tensor Gauss rule applied to a product function factorises, so the
+    tensor-product coefficients are the outer product of the 1D ones."""
+    ndim = len(ns)
+    M, C = n_modes(ndim, k), n_cells(ns)
+    out = np.zeros((M, C))
+    for term in terms:
+        c1 = [project_1d(term[e], ns[e], los[e], his[e], k, nq) for e in range(ndim)]
+        # mode index j_0 fastest, cell index i_0 fastest -> build with reversed axes
+        t = c1[ndim - 1]
+        for e in range(ndim - 2, -1, -1):
+            # t: [o^(ndim-1-e), cells_hi]; prepend dim e as the faster index
+            t = (t[:, None, :, None] * c1[e][None, :, None, :]).reshape(
+                t.shape[0] * (k + 1), t.shape[1] * ns[e])
+        out += t
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Diagnostics
+# ---------------------------------------------------------------------------
+
+def cell_volume(ns, los, his):
+    return float(np.prod([(his[e] - los[e]) / ns[e] for e in range(len(ns))]))
+
+
+def mass(state, ns, los, his):
+    """Total mass = (prod h) * sum of the cell means c_0 (section II-A: c_0 is
+    the mass of the cell up to the factor h), summed exactly (math.fsum)."""
+    return cell_volume(ns, los, his) * math.fsum(np.asarray(state[0], dtype=np.float64).tolist())
+
+
+def mass_sum(mass_plane):
+    """Exactly rounded sum of a mass array."""
+    return math.fsum(np.asarray(mass_plane, dtype=np.float64).ravel().tolist())
+
+
+def mode_weights(ndim, k):
+    """Integral over a cell of (prod_e P_{j_e})^2 divided by the cell volume,
+    prod_e 1/(2 j_e + 1), for every mode id m = j_0 + o*(j_1 + ...)."""
+    o = k + 1
+    w = np.ones(o ** ndim)
+    for m in range(o ** ndim):
+        for e in range(ndim):
+            j = (m // o ** e) % o
+            w[m] /= 2 * j + 1
+    return w
+
+
+def weighted_l2_sq(state, ns, los, his):
+    """||u_h||_{L2}^2 = (prod h) * sum_cells sum_m c_m^2 prod_e 1/(2 j_e + 1)."""
+    ndim = len(ns)
+    k = round(state.shape[0] ** (1.0 / ndim)) - 1
+    w = mode_weights(ndim, k)
+    return cell_volume(ns, los, his) * float(np.sum(w[:, None] * np.asarray(state) ** 2))
+
+
+def eval_1d(coef, n, lo, hi, x):
+    """Evaluate a 1D piecewise Legendre expansion [k+1, n] at points x (periodic)."""
+    k = coef.shape[0] - 1
+    h = (hi - lo) / n
+    y = (np.asarray(x, dtype=np.float64) - lo) / h
+    i = np.floor(y).astype(np.int64)
+    xi = 2.0 * (y - i) - 1.0
+    i = np.mod(i, n)
+    P = legendre_values(k, xi)
+    return np.sum(coef[:, i] * P, axis=0)
+
+
+def l2_error_1d(coef, n, lo, hi, f, nq=None):
+    """||u_h - f||_{L2} on a 1D periodic grid with an nq-point Gauss rule per
+    cell (default k+4)."""
+    k = coef.shape[0] - 1
+    nq = k + 4 if nq is None else nq
+    xg, wg = gauss_legendre(nq)
+    h = (hi - lo) / n
+    centres = lo + (np.arange(n) + 0.5) * h
+    x = centres[None, :] + 0.5 * h * xg[:, None]
+    P = legendre_values(k, xg)                      # [o, nq]
+    uh = np.einsum("jq,jn->qn", P, coef)
+    err = uh - f(x)
+    return math.sqrt(0.5 * h * float(np.sum(wg[:, None] * err ** 2)))
