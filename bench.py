@@ -1,0 +1,259 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X sLdG projection sweep.
+
+Workload: the 4D split-advection problem (x1, x2, v1, v2), 48^4 cells, degree
+k = 2 (81 Legendre coefficients per cell, ~430M coefficients), periodic,
+seeded synthetic coefficients with the magnitude profile of smooth Vlasov
+data and the displacement fields of the 4D Vlasov configuration (x-shifts
+v*dt/2, v-shifts E(x1,x2)*dt with a seeded smooth E).  One step = one split
+step X1(dt/2) X2(dt/2) V1(dt) V2(dt) X1(dt/2) X2(dt/2) (six sweeps, the
+per-line shift tables of each sweep, ping-pong buffers) plus the compensated
+mass reduction, i.e. every stage of the hot path.  Inputs are resident in HBM
+before timing starts.
+
+Metric: coefficient updates per second (each coefficient of the grid is
+rewritten once per sweep), with the achieved HBM bandwidth of the dominant
+sweep kernel against the 8 TB/s peak, the FP64 and BF16 tiers timed on the
+same data for the mixed-vs-FP64 speedup, and the CPU oracle timed on a
+sampled subset of the same step as the baseline.  Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TIER_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}
+ARITH = {"fp64": "f64", "fp32": "f64", "bf16": "f32", "fp16": "f32"}
+KERNEL_SOURCES = ["paper_1603_07008_amd/csrc/sldg_kernels.hip", "paper_1603_07008_amd/csrc/ab_poly.h",
+                  "paper_1603_07008_amd/csrc/sldg_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_vlasov4d_48_k2_fp32.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def state_bytes(cells, modes, tier):
+    return cells * (8 + TIER_BYTES[tier] * (modes - 1))
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    if it was taken on the current kernel sources (else None)."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    ent = rec.get("kernels", {}).get(kernel)
+    return None if ent is None else ent.get("bytes_per_launch")
+
+
+def run_tier(sl, torch, prob, tier, init, steps, warmup):
+    """Time `steps` split steps (after `warmup`) of `prob` in `tier`."""
+    p = sl.Plan(prob.ns, prob.k, tier)
+    mass0, hi0 = init
+    s0 = (mass0.clone(), hi0.to(sl.hi_dtype(tier), copy=True).contiguous())
+    s1 = p.empty_state()
+    seq = [(sw.dim, sw.dep_mask, torch.from_numpy(sw.sigma).cuda()) for sw in prob.seq]
+    mout = torch.zeros(2, dtype=torch.float64, device="cuda")
+    bufs = [s0, s1]
+    cur = 0
+
+    def step():
+        nonlocal cur
+        res = p.split_steps(seq, 1, bufs[cur], bufs[1 - cur])
+        cur = cur if res == 0 else 1 - cur
+        p.mass_device(bufs[cur][0], mout)
+
+    m_start = p.mass(bufs[cur][0])
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    p.timing_enable(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    p.timing_enable(False)
+    kern = {
+        "sweep_contig": p.timing_read(-1),
+        "sweep_strided": p.timing_read(-2),
+    }
+    per_dim = {d: p.timing_read(d) for d in range(prob.ndim)}
+    m_end = p.mass(bufs[cur][0])
+    drift = abs((m_end[0] + m_end[1]) - (m_start[0] + m_start[1])) / abs(m_start[0] + m_start[1])
+    final = bufs[cur]
+    return {"plan": p, "ms_per_step": ms, "kernels": kern, "per_dim": per_dim,
+            "mass_drift": drift, "final": final}
+
+
+def cpu_baseline(prob, tier, seconds, seed):
+    """The CPU oracle timed on a sampled subset of one split step: the full
+    4D state in host memory, every sweep of the step computed for a random
+    sample of output cells (all 81 coefficients of each)."""
+    import numpy as np
+    from oracle import sldg_oracle as O
+    from paper_1603_07008_amd import inputs
+    t0 = time.time()
+    state = O.to_tier(inputs.random_coefficients(prob.ndim, prob.k, prob.cells, seed=seed), tier)
+    log(f"cpu_baseline: host state ready in {time.time() - t0:.1f}s")
+    rng = np.random.default_rng(seed + 1)
+    # warm the A/B cache of the oracle, then calibrate the sample size
+    for sw in prob.seq:
+        O.line_tables(sw.sigma, prob.k)
+    probe = np.sort(rng.choice(prob.cells, 4096, replace=False))
+    t0 = time.perf_counter()
+    for sw in prob.seq:
+        O.sweep(state, prob.ns, prob.k, sw.dim, sw.sigma, sw.dep, tier, sel=probe)
+    dt = time.perf_counter() - t0
+    nsel = int(min(prob.cells, max(4096, 4096 * seconds / max(dt, 1e-6))))
+    sel = np.sort(rng.choice(prob.cells, nsel, replace=False))
+    t0 = time.perf_counter()
+    for sw in prob.seq:
+        O.sweep(state, prob.ns, prob.k, sw.dim, sw.sigma, sw.dep, tier, sel=sel)
+    dt = time.perf_counter() - t0
+    updates = nsel * prob.modes * len(prob.seq)
+    return {"value": updates / dt, "unit": "coeff-updates/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"one split step (6 sweeps) of the {prob.ns} k={prob.k} {tier}-mode "
+                      f"workload on the full host state, evaluated for {nsel} randomly sampled "
+                      f"output cells x {prob.modes} coefficients ({updates} coefficient updates, "
+                      f"{dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--tier", default="fp32", choices=list(TIER_BYTES))
+    ap.add_argument("--n", type=int, default=48, help="cells per dimension of the 4D grid")
+    ap.add_argument("--compare", default="fp64,bf16",
+                    help="other tiers timed on the same data (for the speedup)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=1603)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU decomposition is a design note, not an implementation)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1603_07008_amd as sl
+    from paper_1603_07008_amd import inputs
+
+    if not torch.cuda.is_available():
+        print("bench.py: no HIP device", file=sys.stderr)
+        sys.exit(1)
+    sl.lib()
+    prob = inputs.vlasov_4d(n=args.n)
+    cells, modes = prob.cells, prob.modes
+    log(f"bench: {prob.name} {prob.ns} k={prob.k}: {cells} cells x {modes} coefficients")
+    mass0, hi0 = inputs.random_coefficients_device(prob.ndim, prob.k, cells, seed=args.seed)
+    torch.cuda.synchronize()
+
+    tiers = [args.tier] + [t for t in args.compare.split(",") if t and t != args.tier]
+    results = {}
+    for t in tiers:
+        log(f"bench: timing tier {t}")
+        results[t] = run_tier(sl, torch, prob, t, (mass0, hi0), args.steps, args.warmup)
+        log(f"bench: {t}: {results[t]['ms_per_step']:.3f} ms/step")
+
+    main_r = results[args.tier]
+    ms = main_r["ms_per_step"]
+    updates_per_step = len(prob.seq) * cells * modes
+    value = updates_per_step / (ms * 1e-3)
+
+    # roofline of the dominant sweep kernel (largest total time)
+    sbytes = state_bytes(cells, modes, args.tier)
+    launch_bytes = 2 * sbytes                          # every coefficient read once, written once
+    kname, (nl, tot) = max(main_r["kernels"].items(), key=lambda kv: kv[1][1])
+    avg_ms = tot / max(nl, 1)
+    achieved = launch_bytes / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(kname)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": kname, "launches": nl,
+                "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": launch_bytes}
+
+    names = {0: "X1", 1: "X2", 2: "V1", 3: "V2"}
+    per_sweep = {}
+    for d, (n, tot_d) in main_r["per_dim"].items():
+        if n:
+            a = tot_d / n
+            per_sweep[names.get(d, str(d))] = {
+                "avg_ms": round(a, 4), "GB/s": round(launch_bytes / (a * 1e-3) / 1e9, 1),
+                "frac_hbm_peak": round(launch_bytes / (a * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    # mixed vs FP64: speedup and the error of the mixed run against the FP64 run
+    tiers_out = {}
+    ref = results.get("fp64")
+    for t, r in results.items():
+        ent = {"ms_per_step": round(r["ms_per_step"], 4),
+               "coeff_updates_per_s": updates_per_step / (r["ms_per_step"] * 1e-3),
+               "bytes_per_update": round(2 * state_bytes(cells, modes, t) / (cells * modes), 3),
+               "mass_drift_rel": r["mass_drift"]}
+        if ref is not None:
+            ent["speedup_vs_fp64"] = round(ref["ms_per_step"] / r["ms_per_step"], 3)
+            if t != "fp64":
+                fm, fh = r["final"]
+                rm, rh = ref["final"]
+                num = torch.sum((fm - rm) ** 2) + torch.sum((fh.double() - rh) ** 2)
+                den = torch.sum(rm ** 2) + torch.sum(rh ** 2)
+                ent["rel_l2_vs_fp64_gpu_run"] = float(torch.sqrt(num / den))
+        tiers_out[t] = ent
+
+    out = {
+        "metric": "coefficient updates/s (and % of HBM peak per sweep); mixed vs FP64",
+        "value": value,
+        "unit": "coeff-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": ARITH[args.tier],
+        "data": "synthetic (seeded random coefficients, Vlasov magnitude profile; seeded shift fields)",
+        "config": {"workload": f"vlasov-4d split step, {args.n}^4 cells, k=2, 81 coeffs/cell, "
+                               f"6 sweeps + mass per step",
+                   "storage": f"mass f64 + modes {args.tier}", "parallelism": "single GPU"},
+        "roofline": roofline,
+        "per_sweep": per_sweep,
+        "tiers": tiers_out,
+    }
+    if not args.no_cpu_baseline:
+        log("bench: timing the CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(prob, args.tier, args.cpu_seconds, args.seed)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

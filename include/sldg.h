@@ -1,0 +1,176 @@
+/*
+ * sldg.h -- C ABI of libsldg, the MI355X (gfx950) projection sweep of the
+ * mixed-precision semi-Lagrangian discontinuous Galerkin (sLdG) method
+ * (L. Einkemmer, "A mixed precision semi-Lagrangian algorithm and its
+ * performance on accelerators", arXiv 1603.07008).
+ *
+ * Data model (section II-A).  A periodic tensor grid of ndim dimensions,
+ * ncells[0] x ... x ncells[ndim-1] cells, dimension 0 fastest:
+ *     cell id = i_0 + N_0 * (i_1 + N_1 * (i_2 + ...)).
+ * In each cell the solution is a polynomial of degree k in every variable,
+ * stored as tensor-product Legendre coefficients, o = k + 1 per dimension:
+ *     mode id m = j_0 + o * (j_1 + o * (j_2 + ...)),  0 <= j_e <= k.
+ * Mode 0 is the cell mean (the mass mode).  The state is split in two arrays:
+ *     mass : double [cells]                 mode 0, always FP64
+ *     hi   : T      [o^ndim - 1][cells]     modes 1 .. o^ndim-1, mode-major
+ * where T is the storage type of the plan's tier: double (FP64 tier), float
+ * (FP32 tier), bfloat16 or IEEE half (BF16 / FP16 tiers; raw 16-bit words).
+ * Keeping the mass mode in FP64 while the others are narrower is the paper's
+ * mixed-precision scheme (section II-A, the paragraph on the storage of c_0;
+ * section III-A); it conserves the total mass to FP64 rounding.
+ *
+ * All state pointers are device pointers (HIP device memory) owned by the
+ * caller.  A plan owns only small device tables.  Functions never abort: they
+ * return a status, and sldg_last_error() holds a thread-local detail string.
+ */
+#ifndef SLDG_H
+#define SLDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sldg_plan_s* sldg_plan_t;
+
+typedef enum {
+    SLDG_OK = 0,
+    SLDG_ERR_ARG = 1,          /* null pointer, bad dimension, bad mask, bad size */
+    SLDG_ERR_ALIAS = 2,        /* an output buffer overlaps an input or another output */
+    SLDG_ERR_UNSUPPORTED = 3,  /* degree or tier without a compiled kernel, grid too large */
+    SLDG_ERR_NOMEM = 4,        /* device allocation of the plan's tables failed */
+    SLDG_ERR_DEVICE = 5        /* a HIP call or kernel launch failed */
+} sldg_status;
+
+typedef enum {
+    SLDG_TIER_FP64 = 0,        /* all modes FP64, FP64 arithmetic */
+    SLDG_TIER_FP32 = 1,        /* mass FP64; other modes FP32 storage, FP64 arithmetic */
+    SLDG_TIER_BF16 = 2,        /* mass FP64 (FP64 update); other modes bfloat16, FP32 arithmetic */
+    SLDG_TIER_FP16 = 3         /* mass FP64 (FP64 update); other modes IEEE half, FP32 arithmetic */
+} sldg_tier;
+
+/*
+ * Create a plan for a grid and a storage tier (section II-A).
+ *   plan      out: the new plan (NULL on error)
+ *   ndim      1..6
+ *   ncells    host array [ndim], cells per dimension (>= 1), dimension 0
+ *             fastest; the total cell count must be below 2^31
+ *   k         polynomial degree per dimension, 1..3
+ *   tier      storage tier of the modes other than the cell mean
+ *   stream    hipStream_t every later call of this plan is enqueued on
+ *             (NULL = the null stream)
+ * Allocates the plan's device tables (per-line shift/matrix table and the
+ * mass-reduction scratch) on the current device.  Errors: SLDG_ERR_ARG,
+ * SLDG_ERR_UNSUPPORTED, SLDG_ERR_NOMEM, SLDG_ERR_DEVICE.
+ */
+sldg_status sldg_plan(sldg_plan_t* plan, int ndim, const int64_t* ncells, int k,
+                      sldg_tier tier, void* stream);
+
+/* Release a plan (synchronises its stream first).  NULL is a no-op. */
+void sldg_plan_destroy(sldg_plan_t plan);
+
+/* Change the stream later calls of the plan are enqueued on. */
+sldg_status sldg_plan_set_stream(sldg_plan_t plan, void* stream);
+
+/*
+ * Per-line shift tables (section II-A, update rule and the remark that the
+ * matrices are precomputed once per step).  For each displacement sigma[t]
+ * (cells, FP64) computes s = floor(sigma) and alpha = sigma - s in [0, 1),
+ * snapped so that alpha + (1 - alpha) == 1 exactly, and the projection
+ * matrices A(alpha), B(alpha) of degree k with the exact mass row
+ * (A_00 = 1 - alpha, B_00 = alpha, B_0l = -A_0l).  A fractional part that
+ * rounds to 1 is taken as s + 1, alpha = 0.
+ *   n        number of displacements
+ *   sigma    device double [n]
+ *   s_out    device int32 [n]: s reduced modulo `period` into [0, period)
+ *            (period >= 1; pass the length of the swept dimension)
+ *   ab_out   device double [n][2][k+1][k+1]: A then B, row-major [j][l]
+ * Asynchronous on the plan's stream.  Non-finite sigma yields NaN matrices.
+ */
+sldg_status sldg_line_tables(sldg_plan_t plan, int64_t n, int64_t period,
+                             const double* sigma, int32_t* s_out, double* ab_out);
+
+/*
+ * One out-of-place projection sweep along dimension `dim` (section II-A,
+ * update rule; section II eq. (1) for the splitting into 1D advections):
+ *     out[i] = A(alpha) in[i - s] + B(alpha) in[i - s - 1]
+ * along dim, for every mode index j_dim, with the other mode indices as
+ * spectators, periodic in dim.
+ *   dim       swept dimension, 0..ndim-1
+ *   shift     device double: displacement in cells (a * dt / h_dim) per line,
+ *             indexed row-major over the dimensions in dep_mask, lowest
+ *             dimension fastest, and broadcast over the other dimensions
+ *             (dep_mask = 0: a single value)
+ *   dep_mask  bit e set if the displacement depends on dimension e; must not
+ *             contain dim
+ *   in_mass, in_hi    input state (see the data model above)
+ *   out_mass, out_hi  output state; must not overlap any input or each other
+ * The mass mode's new value is computed entirely in FP64 from the promoted
+ * inputs; the other modes are rounded to nearest even on store.  Allocates
+ * nothing, does not synchronise; asynchronous on the plan's stream.
+ * Errors: SLDG_ERR_ARG, SLDG_ERR_ALIAS, SLDG_ERR_DEVICE.
+ */
+sldg_status sldg_advect_dim(sldg_plan_t plan, int dim, const double* shift,
+                            uint32_t dep_mask, const double* in_mass,
+                            const void* in_hi, double* out_mass, void* out_hi);
+
+/* One sweep of a split step: dimension, dependence mask, device displacements. */
+typedef struct {
+    int dim;
+    uint32_t dep_mask;
+    const double* shift;
+} sldg_sweep_desc;
+
+/*
+ * A split time step applied nsteps times (section II: the Vlasov equation is
+ * split into a sequence of 1D advections).  Each step applies the nseq
+ * sweeps of `seq` in order; sweep number q (counting over all steps) reads
+ * buffer q % 2 and writes buffer (q + 1) % 2, so the result lands in buffer
+ * (nsteps * nseq) % 2, which is also returned in *result_buffer.
+ * Buffers 0 and 1 must not overlap.  Asynchronous on the plan's stream.
+ */
+sldg_status sldg_split_steps(sldg_plan_t plan, const sldg_sweep_desc* seq, int nseq,
+                             int nsteps, double* mass0, void* hi0, double* mass1,
+                             void* hi1, int* result_buffer);
+
+/*
+ * Sum of the mass array, mass[0] + ... + mass[cells-1], as an unevaluated
+ * double-double out[0] + out[1] (|out[1]| <= ulp(out[0])/2), with a
+ * deterministic reduction order (section II-A: c_0 carries the mass; section
+ * III-A measures its conservation).  The physical mass is this sum times the
+ * cell volume, which the caller applies.  `out` is host memory; the call
+ * synchronises the plan's stream.
+ */
+sldg_status sldg_mass(sldg_plan_t plan, const double* mass, double out[2]);
+
+/*
+ * The same double-double sum written to device memory out_dev[2] (hi, lo),
+ * asynchronously on the plan's stream, without synchronising; for use inside
+ * a stream of sweeps (and under stream capture).
+ */
+sldg_status sldg_mass_device(sldg_plan_t plan, const double* mass, double* out_dev);
+
+/*
+ * Kernel timing.  While enabled, every sweep kernel launch of the plan is
+ * bracketed by a pair of HIP events recorded on the plan's stream (the line
+ * table kernel is outside the pair), up to 4096 launches after enabling.
+ * sldg_timing_enable(plan, 1) clears earlier records; (plan, 0) stops.
+ * sldg_timing_read synchronises the plan's stream and returns, for launches
+ * of the sweep along `dim` (dim = -1: along dimension 0; dim = -2: along
+ * any dimension > 0), their count and the sum of their durations in ms.
+ */
+sldg_status sldg_timing_enable(sldg_plan_t plan, int enable);
+sldg_status sldg_timing_read(sldg_plan_t plan, int dim, int64_t* launches, double* total_ms);
+
+/* Bytes of one state's `hi` array for this plan, (o^ndim - 1) * cells * sizeof(T). */
+int64_t sldg_hi_bytes(sldg_plan_t plan);
+
+const char* sldg_status_string(sldg_status s);
+const char* sldg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLDG_H */

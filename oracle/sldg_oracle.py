@@ -211,7 +211,7 @@ def line_strides(ns, dep):
 # Sweep (section II-A update rule), via the plain C loops in sweep.c
 # ---------------------------------------------------------------------------
 
-def sweep(state, ns, k, dim, sigma, dep=(), tier="fp64", sel=None):
+def sweep(state, ns, k, dim, sigma, dep=(), tier="fp64", sel=None, absolute=False):
     """One sLdG projection sweep along `dim`.
 
     state  float64 [o^ndim, cells] (mode-major, cells dimension-0 fastest)
@@ -220,6 +220,9 @@ def sweep(state, ns, k, dim, sigma, dep=(), tier="fp64", sel=None):
     tier   storage emulation for modes m != 0 ('fp64', 'fp32', 'bf16', 'fp16')
     sel    optional int64 array of output cells; then the result is
            [o^ndim, len(sel)]
+    absolute  use |A|, |B| and |state| (no rounding): gives the magnitude
+           sum_l |A_jl x_l| + |B_jl y_l| of every output, which bounds the
+           rounding error of any evaluation order of the update
     """
     ns = [int(v) for v in ns]
     ndim = len(ns)
@@ -234,6 +237,10 @@ def sweep(state, ns, k, dim, sigma, dep=(), tier="fp64", sel=None):
     if sigma.size != ntab:
         raise ValueError(f"need {ntab} displacements, got {sigma.size}")
     s_tab, ab_tab = line_tables(sigma, k)
+    if absolute:
+        ab_tab = np.abs(ab_tab)
+        state = np.abs(state)
+        tier = "fp64"
     if sel is None:
         out = np.empty((M, C))
         nsel, selp = C, None

@@ -1,0 +1,289 @@
+"""MI355X-native mixed-precision sLdG projection sweep (arXiv 1603.07008).
+
+Thin ctypes binding of libsldg.so (C ABI in include/sldg.h).  The functions
+here only marshal arguments (device pointers of torch tensors, the current HIP
+stream) and check buffer sizes; every step of the sweep runs in the library's
+HIP kernels.  There is no CPU fallback: without the built library every call
+raises.
+"""
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsldg.so")
+
+SLDG_OK, SLDG_ERR_ARG, SLDG_ERR_ALIAS, SLDG_ERR_UNSUPPORTED, SLDG_ERR_NOMEM, SLDG_ERR_DEVICE = range(6)
+TIERS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
+TIER_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}
+
+EXPORTS = ("sldg_plan", "sldg_plan_destroy", "sldg_plan_set_stream", "sldg_line_tables",
+           "sldg_advect_dim", "sldg_split_steps", "sldg_mass", "sldg_hi_bytes",
+           "sldg_status_string", "sldg_last_error", "sldg_timing_enable", "sldg_timing_read",
+           "sldg_mass_device")
+
+
+class SldgError(RuntimeError):
+    def __init__(self, status, where, detail):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({detail})")
+
+
+class SweepDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("dep_mask", ctypes.c_uint32), ("shift", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libsldg.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libsldg.so is not built ({LIB_PATH}); run paper_1603_07008_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, u32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_uint32
+    L.sldg_plan.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(i64), i32, i32, vp]
+    L.sldg_plan.restype = i32
+    L.sldg_plan_destroy.argtypes = [vp]
+    L.sldg_plan_destroy.restype = None
+    L.sldg_plan_set_stream.argtypes = [vp, vp]
+    L.sldg_plan_set_stream.restype = i32
+    L.sldg_line_tables.argtypes = [vp, i64, i64, vp, vp, vp]
+    L.sldg_line_tables.restype = i32
+    L.sldg_advect_dim.argtypes = [vp, i32, vp, u32, vp, vp, vp, vp]
+    L.sldg_advect_dim.restype = i32
+    L.sldg_split_steps.argtypes = [vp, ctypes.POINTER(SweepDesc), i32, i32, vp, vp, vp, vp,
+                                   ctypes.POINTER(i32)]
+    L.sldg_split_steps.restype = i32
+    L.sldg_mass.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
+    L.sldg_mass.restype = i32
+    L.sldg_hi_bytes.argtypes = [vp]
+    L.sldg_hi_bytes.restype = i64
+    L.sldg_mass_device.argtypes = [vp, vp, vp]
+    L.sldg_mass_device.restype = i32
+    L.sldg_timing_enable.argtypes = [vp, i32]
+    L.sldg_timing_enable.restype = i32
+    L.sldg_timing_read.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
+    L.sldg_timing_read.restype = i32
+    L.sldg_status_string.argtypes = [i32]
+    L.sldg_status_string.restype = ctypes.c_char_p
+    L.sldg_last_error.argtypes = []
+    L.sldg_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def status_string(status):
+    return lib().sldg_status_string(int(status)).decode()
+
+
+def last_error():
+    return lib().sldg_last_error().decode()
+
+
+def _check(status, where):
+    if status != SLDG_OK:
+        raise SldgError(status, where, last_error())
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _current_stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def hi_dtype(tier):
+    import torch
+    return {"fp64": torch.float64, "fp32": torch.float32, "bf16": torch.bfloat16,
+            "fp16": torch.float16}[tier]
+
+
+class Plan:
+    """A grid + degree + storage tier (sldg_plan).  Calls are enqueued on the
+    HIP stream given at creation (default: torch's current stream)."""
+
+    def __init__(self, ncells, k, tier="fp32", stream=None):
+        self.ncells = tuple(int(n) for n in ncells)
+        self.ndim = len(self.ncells)
+        self.k = int(k)
+        self.tier = tier
+        self.cells = 1
+        for n in self.ncells:
+            self.cells *= n
+        self.modes = (self.k + 1) ** self.ndim
+        if tier not in TIERS:
+            raise ValueError(f"unknown tier {tier!r}")
+        self.stream = _current_stream() if stream is None else stream
+        h = ctypes.c_void_p()
+        arr = (ctypes.c_int64 * self.ndim)(*self.ncells)
+        _check(lib().sldg_plan(ctypes.byref(h), self.ndim, arr, self.k, TIERS[tier],
+                               ctypes.c_void_p(self.stream)), "sldg_plan")
+        self._h = h
+
+    # -- helpers -----------------------------------------------------------
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("plan destroyed")
+        return self._h
+
+    def hi_bytes(self):
+        return int(lib().sldg_hi_bytes(self.handle))
+
+    def empty_state(self, device="cuda"):
+        """Uninitialised (mass, hi) device tensors of this plan's layout."""
+        import torch
+        mass = torch.empty(self.cells, dtype=torch.float64, device=device)
+        hi = torch.empty((self.modes - 1, self.cells), dtype=hi_dtype(self.tier), device=device)
+        return mass, hi
+
+    def _check_state(self, mass, hi, what):
+        import torch
+        if not isinstance(mass, torch.Tensor) or not isinstance(hi, torch.Tensor):
+            raise TypeError(f"{what}: state buffers must be torch tensors")
+        if not (mass.is_cuda and hi.is_cuda):
+            raise ValueError(f"{what}: state buffers must be device tensors")
+        if mass.dtype != torch.float64 or not mass.is_contiguous() or mass.numel() < self.cells:
+            raise ValueError(f"{what}: mass must be contiguous float64 with >= {self.cells} elements")
+        if hi.dtype != hi_dtype(self.tier) or not hi.is_contiguous() or \
+                hi.numel() * hi.element_size() < self.hi_bytes():
+            raise ValueError(f"{what}: hi must be contiguous {hi_dtype(self.tier)} of "
+                             f"{self.hi_bytes()} bytes")
+
+    def _check_shift(self, shift, dep_mask, what):
+        import torch
+        need = 1
+        for e in range(self.ndim):
+            if dep_mask >> e & 1:
+                need *= self.ncells[e]
+        if not isinstance(shift, torch.Tensor) or not shift.is_cuda or \
+                shift.dtype != torch.float64 or not shift.is_contiguous() or shift.numel() < need:
+            raise ValueError(f"{what}: shift must be a contiguous float64 device tensor of "
+                             f">= {need} elements")
+
+    # -- C entry points ----------------------------------------------------
+    def set_stream(self, stream):
+        self.stream = stream
+        _check(lib().sldg_plan_set_stream(self.handle, ctypes.c_void_p(stream)), "sldg_plan_set_stream")
+
+    def line_tables(self, sigma, period, s_out=None, ab_out=None):
+        """(s mod period, [A; B]) per displacement (sldg_line_tables)."""
+        import torch
+        n = sigma.numel()
+        if sigma.dtype != torch.float64 or not sigma.is_cuda or not sigma.is_contiguous():
+            raise ValueError("sigma must be a contiguous float64 device tensor")
+        o = self.k + 1
+        if s_out is None:
+            s_out = torch.empty(n, dtype=torch.int32, device=sigma.device)
+        if ab_out is None:
+            ab_out = torch.empty((n, 2, o, o), dtype=torch.float64, device=sigma.device)
+        if s_out.numel() < n or ab_out.numel() < n * 2 * o * o:
+            raise ValueError("output tables too small")
+        _check(lib().sldg_line_tables(self.handle, n, int(period), _ptr(sigma), _ptr(s_out),
+                                      _ptr(ab_out)), "sldg_line_tables")
+        return s_out, ab_out
+
+    def advect_dim(self, dim, shift, dep_mask, in_mass, in_hi, out_mass, out_hi):
+        """One projection sweep along `dim` (sldg_advect_dim)."""
+        self._check_shift(shift, dep_mask, "advect_dim")
+        self._check_state(in_mass, in_hi, "advect_dim input")
+        self._check_state(out_mass, out_hi, "advect_dim output")
+        _check(lib().sldg_advect_dim(self.handle, int(dim), _ptr(shift), int(dep_mask),
+                                     _ptr(in_mass), _ptr(in_hi), _ptr(out_mass), _ptr(out_hi)),
+               "sldg_advect_dim")
+
+    def split_steps(self, seq, nsteps, state0, state1):
+        """Apply the sweeps `seq` [(dim, dep_mask, shift tensor), ...] nsteps
+        times, ping-ponging between state0 and state1 (sldg_split_steps).
+        Returns the index (0 or 1) of the state that holds the result."""
+        descs = (SweepDesc * max(1, len(seq)))()
+        for q, (dim, mask, shift) in enumerate(seq):
+            self._check_shift(shift, mask, "split_steps")
+            descs[q] = SweepDesc(int(dim), int(mask), _ptr(shift))
+        self._check_state(*state0, "split_steps state0")
+        self._check_state(*state1, "split_steps state1")
+        res = ctypes.c_int(-1)
+        _check(lib().sldg_split_steps(self.handle, descs, len(seq), int(nsteps),
+                                      _ptr(state0[0]), _ptr(state0[1]), _ptr(state1[0]),
+                                      _ptr(state1[1]), ctypes.byref(res)), "sldg_split_steps")
+        return res.value
+
+    def mass(self, mass):
+        """Sum of the mass array as a double-double (hi, lo) (sldg_mass);
+        synchronises the plan's stream."""
+        import torch
+        if mass.dtype != torch.float64 or not mass.is_cuda or not mass.is_contiguous() or \
+                mass.numel() < self.cells:
+            raise ValueError("mass must be a contiguous float64 device tensor")
+        out = (ctypes.c_double * 2)()
+        _check(lib().sldg_mass(self.handle, _ptr(mass), out), "sldg_mass")
+        return out[0], out[1]
+
+    def mass_device(self, mass, out):
+        """Double-double mass sum into the device tensor out[2] (sldg_mass_device);
+        asynchronous."""
+        import torch
+        if mass.dtype != torch.float64 or not mass.is_cuda or not mass.is_contiguous() or \
+                mass.numel() < self.cells:
+            raise ValueError("mass must be a contiguous float64 device tensor")
+        if out.dtype != torch.float64 or not out.is_cuda or out.numel() < 2:
+            raise ValueError("out must be a float64 device tensor of >= 2 elements")
+        _check(lib().sldg_mass_device(self.handle, _ptr(mass), _ptr(out)), "sldg_mass_device")
+
+    def timing_enable(self, enable=True):
+        """Bracket every later sweep kernel with HIP events (sldg_timing_enable)."""
+        _check(lib().sldg_timing_enable(self.handle, 1 if enable else 0), "sldg_timing_enable")
+
+    def timing_read(self, dim):
+        """(launches, total ms) of the timed sweep kernels along `dim`
+        (-1: dimension 0, -2: dimensions > 0) (sldg_timing_read)."""
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        _check(lib().sldg_timing_read(self.handle, int(dim), ctypes.byref(n), ctypes.byref(ms)),
+               "sldg_timing_read")
+        return n.value, ms.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().sldg_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# Function names of the C ABI, for callers that prefer them.
+def plan(ncells, k, tier="fp32", stream=None):
+    return Plan(ncells, k, tier, stream)
+
+
+def plan_destroy(p):
+    p.close()
+
+
+def advect_dim(p, dim, shift, dep_mask, in_mass, in_hi, out_mass, out_hi):
+    p.advect_dim(dim, shift, dep_mask, in_mass, in_hi, out_mass, out_hi)
+
+
+def split_steps(p, seq, nsteps, state0, state1):
+    return p.split_steps(seq, nsteps, state0, state1)
+
+
+def mass(p, mass_plane):
+    return p.mass(mass_plane)
+
+
+def line_tables(p, sigma, period):
+    return p.line_tables(sigma, period)

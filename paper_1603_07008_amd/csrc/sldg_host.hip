@@ -1,0 +1,410 @@
+// Host side of libsldg: the C ABI declared in include/sldg.h -- plans,
+// argument validation, per-line tables and kernel launches for the sLdG
+// projection sweep (L. Einkemmer, arXiv 1603.07008, section II-A).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "sldg.h"
+#include "sldg_internal.h"
+
+using namespace sldg;
+
+struct sldg_plan_s {
+  int ndim;
+  int64_t n[kMaxDim];
+  int k, o;
+  sldg_tier tier;
+  hipStream_t stream;
+  int device;
+  int64_t cells;
+  int64_t modes;          // o^ndim
+  int64_t hi_bytes;
+  int64_t table_cap;      // entries of the per-line table
+  int32_t* d_s;
+  double* d_ab;
+  int mass_nblocks;
+  double* d_mass_part;    // [2 * mass_nblocks]
+  double* d_mass_out;     // [2]
+  double* h_mass_out;     // pinned [2]
+  int32_t target_threads; // strided sweep: threads to aim for when chunking
+  // kernel timing (sldg_timing_*)
+  bool timing;
+  int ntimed;
+  hipEvent_t ev[2 * 4096];
+  int ev_dim[4096];
+  int nev_created;
+};
+
+namespace {
+
+constexpr int kMaxTimed = 4096;
+thread_local char g_err[512] = "";
+
+sldg_status fail(sldg_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+sldg_status ok() {
+  g_err[0] = '\0';
+  return SLDG_OK;
+}
+
+int64_t elem_size(sldg_tier t) {
+  switch (t) {
+    case SLDG_TIER_FP64: return 8;
+    case SLDG_TIER_FP32: return 4;
+    case SLDG_TIER_BF16: return 2;
+    case SLDG_TIER_FP16: return 2;
+  }
+  return 0;
+}
+
+bool overlap(const void* a, int64_t na, const void* b, int64_t nb) {
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+// Checks of one sweep's arguments that need no device.
+sldg_status check_sweep(const sldg_plan_s* p, int dim, const double* shift, uint32_t dep_mask,
+                        const double* in_mass, const void* in_hi, const double* out_mass,
+                        const void* out_hi) {
+  if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
+  if (dim < 0 || dim >= p->ndim)
+    return fail(SLDG_ERR_ARG, "dim %d out of range [0, %d)", dim, p->ndim);
+  if (dep_mask >> p->ndim)
+    return fail(SLDG_ERR_ARG, "dep_mask 0x%x names dimensions beyond ndim=%d", dep_mask, p->ndim);
+  if (dep_mask & (1u << dim))
+    return fail(SLDG_ERR_ARG, "dep_mask 0x%x contains the swept dimension %d", dep_mask, dim);
+  if (!shift || !in_mass || !in_hi || !out_mass || !out_hi)
+    return fail(SLDG_ERR_ARG, "null state or shift pointer");
+  const int64_t mb = p->cells * 8, hb = p->hi_bytes;
+  const void* ins[2] = {in_mass, in_hi};
+  const int64_t insz[2] = {mb, hb};
+  const void* outs[2] = {out_mass, out_hi};
+  const int64_t outsz[2] = {mb, hb};
+  for (int i = 0; i < 2; ++i)
+    for (int o = 0; o < 2; ++o)
+      if (overlap(ins[i], insz[i], outs[o], outsz[o]))
+        return fail(SLDG_ERR_ALIAS, "output buffer overlaps an input buffer");
+  if (overlap(out_mass, mb, out_hi, hb))
+    return fail(SLDG_ERR_ALIAS, "out_mass overlaps out_hi");
+  int64_t sb = 8;
+  for (int e = 0; e < p->ndim; ++e)
+    if (dep_mask & (1u << e)) sb *= p->n[e];
+  if (overlap(shift, sb, out_mass, mb) || overlap(shift, sb, out_hi, hb))
+    return fail(SLDG_ERR_ALIAS, "shift overlaps an output buffer");
+  return SLDG_OK;
+}
+
+// Describe the sweep along dim for the kernels (everything but the buffers).
+void describe(const sldg_plan_s* p, int dim, uint32_t dep_mask, SweepArgs& a, int64_t& ntab) {
+  int64_t P = 1, Q = 1;
+  for (int e = 0; e < dim; ++e) P *= p->n[e];
+  for (int e = dim + 1; e < p->ndim; ++e) Q *= p->n[e];
+  a.cells = p->cells;
+  a.P = (int32_t)P;
+  a.N = (int32_t)p->n[dim];
+  a.Q = (int32_t)Q;
+  int64_t ms = 1;
+  for (int e = 0; e < dim; ++e) ms *= p->o;
+  a.mstride = (int32_t)ms;
+  a.nspec = (int32_t)(p->modes / p->o);
+  // table over the dependent dims, lowest fastest
+  LineMap m{};
+  int64_t str = 1, div_lo = 1, div_hi = 1;
+  for (int e = 0; e < p->ndim; ++e) {
+    if (e == dim) continue;
+    const bool below = e < dim;
+    if (dep_mask & (1u << e)) {
+      if (below) {
+        m.lo_div[m.nlo] = (int32_t)div_lo;
+        m.lo_mod[m.nlo] = (int32_t)p->n[e];
+        m.lo_str[m.nlo] = (int32_t)str;
+        ++m.nlo;
+      } else {
+        m.hi_div[m.nhi] = (int32_t)div_hi;
+        m.hi_mod[m.nhi] = (int32_t)p->n[e];
+        m.hi_str[m.nhi] = (int32_t)str;
+        ++m.nhi;
+      }
+      str *= p->n[e];
+    }
+    if (below) div_lo *= p->n[e];
+    else div_hi *= p->n[e];
+  }
+  a.map = m;
+  ntab = str;
+  // strided sweep: split the swept dimension into chunks until the launch
+  // has enough threads to cover the chip
+  if (dim > 0) {
+    const int64_t base = P * Q * a.nspec;
+    int64_t nch = (p->target_threads + base - 1) / base;
+    nch = std::max<int64_t>(1, std::min<int64_t>(nch, a.N));
+    const int64_t len = (a.N + nch - 1) / nch;
+    a.chunk = (int32_t)len;
+    a.nchunk = (int32_t)((a.N + len - 1) / len);
+  } else {
+    a.chunk = a.N;
+    a.nchunk = 1;
+  }
+}
+
+sldg_status device_error(hipError_t e, const char* what) {
+  return fail(SLDG_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void free_plan(sldg_plan_s* p) {
+  if (!p) return;
+  for (int q = 0; q < p->nev_created; ++q) (void)hipEventDestroy(p->ev[q]);
+  if (p->d_s) (void)hipFree(p->d_s);
+  if (p->d_ab) (void)hipFree(p->d_ab);
+  if (p->d_mass_part) (void)hipFree(p->d_mass_part);
+  if (p->d_mass_out) (void)hipFree(p->d_mass_out);
+  if (p->h_mass_out) (void)hipHostFree(p->h_mass_out);
+  delete p;
+}
+
+sldg_status run_sweep(sldg_plan_s* p, int dim, const double* shift, uint32_t dep_mask,
+                      const double* in_mass, const void* in_hi, double* out_mass, void* out_hi) {
+  SweepArgs a{};
+  int64_t ntab = 0;
+  describe(p, dim, dep_mask, a, ntab);
+  if (ntab > p->table_cap)
+    return fail(SLDG_ERR_ARG, "line table of %lld entries exceeds the plan's %lld",
+                (long long)ntab, (long long)p->table_cap);
+  hipError_t e = launch_line_tables(p->k, ntab, p->n[dim], shift, p->d_s, p->d_ab, p->stream);
+  if (e != hipSuccess) return device_error(e, "line-table launch");
+  a.in_mass = in_mass;
+  a.in_hi = in_hi;
+  a.out_mass = out_mass;
+  a.out_hi = out_hi;
+  a.s_tab = p->d_s;
+  a.ab_tab = p->d_ab;
+  const bool timed = p->timing && p->ntimed < kMaxTimed;
+  if (timed) {
+    const int i = p->ntimed;
+    if (2 * i + 1 >= p->nev_created) {
+      for (int q = p->nev_created; q < 2 * i + 2; ++q) {
+        e = hipEventCreate(&p->ev[q]);
+        if (e != hipSuccess) return device_error(e, "hipEventCreate");
+        p->nev_created = q + 1;
+      }
+    }
+    e = hipEventRecord(p->ev[2 * i], p->stream);
+    if (e != hipSuccess) return device_error(e, "hipEventRecord");
+  }
+  e = launch_sweep(p->k, (int)p->tier, dim, a, p->stream);
+  if (e != hipSuccess) return device_error(e, "sweep launch");
+  if (timed) {
+    const int i = p->ntimed;
+    e = hipEventRecord(p->ev[2 * i + 1], p->stream);
+    if (e != hipSuccess) return device_error(e, "hipEventRecord");
+    p->ev_dim[i] = dim;
+    p->ntimed = i + 1;
+  }
+  return SLDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sldg_status_string(sldg_status s) {
+  switch (s) {
+    case SLDG_OK: return "ok";
+    case SLDG_ERR_ARG: return "invalid argument";
+    case SLDG_ERR_ALIAS: return "output overlaps input";
+    case SLDG_ERR_UNSUPPORTED: return "unsupported configuration";
+    case SLDG_ERR_NOMEM: return "out of device memory";
+    case SLDG_ERR_DEVICE: return "device error";
+  }
+  return "unknown status";
+}
+
+const char* sldg_last_error(void) { return g_err; }
+
+sldg_status sldg_plan(sldg_plan_t* out, int ndim, const int64_t* ncells, int k, sldg_tier tier,
+                      void* stream) {
+  if (!out) return fail(SLDG_ERR_ARG, "plan out-pointer is NULL");
+  *out = nullptr;
+  if (ndim < 1 || ndim > kMaxDim) return fail(SLDG_ERR_ARG, "ndim %d not in [1, %d]", ndim, kMaxDim);
+  if (!ncells) return fail(SLDG_ERR_ARG, "ncells is NULL");
+  if (k < 1 || k > 3) return fail(SLDG_ERR_UNSUPPORTED, "degree k=%d not in [1, 3]", k);
+  if ((int)tier < 0 || (int)tier > 3) return fail(SLDG_ERR_UNSUPPORTED, "tier %d unknown", (int)tier);
+  int64_t cells = 1, min_n = INT64_MAX;
+  for (int e = 0; e < ndim; ++e) {
+    if (ncells[e] < 1) return fail(SLDG_ERR_ARG, "ncells[%d] = %lld < 1", e, (long long)ncells[e]);
+    if (ncells[e] >= (1LL << 31))
+      return fail(SLDG_ERR_UNSUPPORTED, "ncells[%d] too large", e);
+    cells *= ncells[e];
+    if (cells >= (1LL << 31))
+      return fail(SLDG_ERR_UNSUPPORTED, "grid of >= 2^31 cells is not supported");
+    min_n = std::min(min_n, ncells[e]);
+  }
+  sldg_plan_s* p = new (std::nothrow) sldg_plan_s();
+  if (!p) return fail(SLDG_ERR_NOMEM, "host allocation failed");
+  p->ndim = ndim;
+  for (int e = 0; e < ndim; ++e) p->n[e] = ncells[e];
+  p->k = k;
+  p->o = k + 1;
+  p->tier = tier;
+  p->stream = static_cast<hipStream_t>(stream);
+  p->cells = cells;
+  p->modes = 1;
+  for (int e = 0; e < ndim; ++e) p->modes *= p->o;
+  p->hi_bytes = (p->modes - 1) * cells * elem_size(tier);
+  p->table_cap = cells / min_n;     // the most lines any sweep can have
+  p->target_threads = 256 * 256 * 4;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    free_plan(p);
+    return device_error(e, "hipGetDevice");
+  }
+  const int64_t o2 = (int64_t)p->o * p->o;
+  e = hipMalloc(&p->d_s, sizeof(int32_t) * p->table_cap);
+  if (e == hipSuccess) e = hipMalloc(&p->d_ab, sizeof(double) * 2 * o2 * p->table_cap);
+  p->mass_nblocks = mass_blocks(cells);
+  if (e == hipSuccess) e = hipMalloc(&p->d_mass_part, sizeof(double) * 2 * p->mass_nblocks);
+  if (e == hipSuccess) e = hipMalloc(&p->d_mass_out, sizeof(double) * 2);
+  if (e == hipSuccess) e = hipHostMalloc(&p->h_mass_out, sizeof(double) * 2, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    const bool nomem = (e == hipErrorOutOfMemory);
+    free_plan(p);
+    (void)hipGetLastError();
+    return nomem ? fail(SLDG_ERR_NOMEM, "plan tables: %s", hipGetErrorString(e))
+                 : device_error(e, "plan tables");
+  }
+  *out = p;
+  return ok();
+}
+
+void sldg_plan_destroy(sldg_plan_t p) {
+  if (!p) return;
+  (void)hipStreamSynchronize(p->stream);
+  free_plan(p);
+}
+
+sldg_status sldg_plan_set_stream(sldg_plan_t p, void* stream) {
+  if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
+  p->stream = static_cast<hipStream_t>(stream);
+  return ok();
+}
+
+int64_t sldg_hi_bytes(sldg_plan_t p) { return p ? p->hi_bytes : -1; }
+
+sldg_status sldg_timing_enable(sldg_plan_t p, int enable) {
+  if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
+  p->timing = enable != 0;
+  if (p->timing) p->ntimed = 0;
+  return ok();
+}
+
+sldg_status sldg_timing_read(sldg_plan_t p, int dim, int64_t* launches, double* total_ms) {
+  if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
+  if (!launches || !total_ms) return fail(SLDG_ERR_ARG, "null output pointer");
+  if (dim < -2 || dim >= p->ndim) return fail(SLDG_ERR_ARG, "dim %d out of range", dim);
+  hipError_t e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return device_error(e, "hipStreamSynchronize");
+  int64_t n = 0;
+  double tot = 0.0;
+  for (int i = 0; i < p->ntimed; ++i) {
+    const int d = p->ev_dim[i];
+    const bool match = (dim >= 0) ? (d == dim) : (dim == -1 ? d == 0 : d > 0);
+    if (!match) continue;
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, p->ev[2 * i], p->ev[2 * i + 1]);
+    if (e != hipSuccess) return device_error(e, "hipEventElapsedTime");
+    ++n;
+    tot += ms;
+  }
+  *launches = n;
+  *total_ms = tot;
+  return ok();
+}
+
+sldg_status sldg_line_tables(sldg_plan_t p, int64_t n, int64_t period, const double* sigma,
+                             int32_t* s_out, double* ab_out) {
+  if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
+  if (n < 0 || period < 1) return fail(SLDG_ERR_ARG, "n=%lld period=%lld", (long long)n, (long long)period);
+  if (n > 0 && (!sigma || !s_out || !ab_out)) return fail(SLDG_ERR_ARG, "null pointer");
+  if (period >= (1LL << 31)) return fail(SLDG_ERR_ARG, "period too large");
+  hipError_t e = launch_line_tables(p->k, n, period, sigma, s_out, ab_out, p->stream);
+  if (e != hipSuccess) return device_error(e, "line-table launch");
+  return ok();
+}
+
+sldg_status sldg_advect_dim(sldg_plan_t p, int dim, const double* shift, uint32_t dep_mask,
+                            const double* in_mass, const void* in_hi, double* out_mass,
+                            void* out_hi) {
+  sldg_status st = check_sweep(p, dim, shift, dep_mask, in_mass, in_hi, out_mass, out_hi);
+  if (st != SLDG_OK) return st;
+  st = run_sweep(p, dim, shift, dep_mask, in_mass, in_hi, out_mass, out_hi);
+  return st == SLDG_OK ? ok() : st;
+}
+
+sldg_status sldg_split_steps(sldg_plan_t p, const sldg_sweep_desc* seq, int nseq, int nsteps,
+                             double* mass0, void* hi0, double* mass1, void* hi1,
+                             int* result_buffer) {
+  if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
+  if (nseq < 0 || nsteps < 0 || (nseq > 0 && !seq))
+    return fail(SLDG_ERR_ARG, "bad sweep sequence (nseq=%d nsteps=%d)", nseq, nsteps);
+  double* m[2] = {mass0, mass1};
+  void* h[2] = {hi0, hi1};
+  // validate every sweep against both directions before launching anything
+  for (int q = 0; q < nseq; ++q) {
+    for (int b = 0; b < 2; ++b) {
+      sldg_status st = check_sweep(p, seq[q].dim, seq[q].shift, seq[q].dep_mask, m[b], h[b],
+                                   m[1 - b], h[1 - b]);
+      if (st != SLDG_OK) return st;
+    }
+  }
+  int cur = 0;
+  for (int n = 0; n < nsteps; ++n) {
+    for (int q = 0; q < nseq; ++q) {
+      sldg_status st = run_sweep(p, seq[q].dim, seq[q].shift, seq[q].dep_mask, m[cur], h[cur],
+                                 m[1 - cur], h[1 - cur]);
+      if (st != SLDG_OK) return st;
+      cur = 1 - cur;
+    }
+  }
+  if (result_buffer) *result_buffer = cur;
+  return ok();
+}
+
+sldg_status sldg_mass_device(sldg_plan_t p, const double* mass, double* out_dev) {
+  if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
+  if (!mass || !out_dev) return fail(SLDG_ERR_ARG, "null pointer");
+  if (overlap(out_dev, 16, mass, p->cells * 8))
+    return fail(SLDG_ERR_ALIAS, "out_dev overlaps the mass array");
+  hipError_t e = launch_mass(mass, p->cells, p->d_mass_part, p->mass_nblocks, out_dev, p->stream);
+  if (e != hipSuccess) return device_error(e, "mass launch");
+  return ok();
+}
+
+sldg_status sldg_mass(sldg_plan_t p, const double* mass, double out[2]) {
+  if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
+  if (!mass || !out) return fail(SLDG_ERR_ARG, "null pointer");
+  hipError_t e = launch_mass(mass, p->cells, p->d_mass_part, p->mass_nblocks, p->d_mass_out,
+                             p->stream);
+  if (e != hipSuccess) return device_error(e, "mass launch");
+  e = hipMemcpyAsync(p->h_mass_out, p->d_mass_out, sizeof(double) * 2, hipMemcpyDeviceToHost,
+                     p->stream);
+  if (e != hipSuccess) return device_error(e, "mass copy");
+  e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return device_error(e, "mass synchronize");
+  out[0] = p->h_mass_out[0];
+  out[1] = p->h_mass_out[1];
+  return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,50 @@
+// Internal interface between the host library and the HIP kernels of libsldg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sldg {
+
+constexpr int kMaxDim = 6;
+
+// Maps a line (a fixed transverse cell) to its entry in the per-line table.
+// The table is indexed over the dimensions the displacement depends on,
+// lowest dimension fastest.  A line is identified by two flattened indices:
+// `lo` over the dimensions below the swept one and `hi` over those above it.
+// Entry = sum over dependent dims e of ((idx / div_e) % mod_e) * str_e, where
+// idx is lo or hi depending on the side of e.
+struct LineMap {
+  int nlo, nhi;
+  int32_t lo_div[kMaxDim], lo_mod[kMaxDim], lo_str[kMaxDim];
+  int32_t hi_div[kMaxDim], hi_mod[kMaxDim], hi_str[kMaxDim];
+};
+
+struct SweepArgs {
+  const double* in_mass;
+  const void* in_hi;
+  double* out_mass;
+  void* out_hi;
+  const int32_t* s_tab;   // per table entry: s mod N, in [0, N)
+  const double* ab_tab;   // per table entry: A then B, (k+1)^2 each, row-major
+  int64_t cells;          // cells of the grid (plane length)
+  int32_t P;              // product of the extents below the swept dim (row stride)
+  int32_t N;              // extent of the swept dim
+  int32_t Q;              // product of the extents above the swept dim
+  int32_t mstride;        // (k+1)^dim: mode-id distance between j_dim and j_dim+1
+  int32_t nspec;          // (k+1)^(ndim-1) spectator mode tuples
+  int32_t nchunk;         // strided sweep: chunks along the swept dim
+  int32_t chunk;          // strided sweep: rows per chunk
+  LineMap map;
+};
+
+// Launchers (defined in sldg_kernels.hip).  All return hipGetLastError().
+hipError_t launch_line_tables(int k, int64_t n, int64_t period, const double* sigma,
+                              int32_t* s_out, double* ab_out, hipStream_t st);
+hipError_t launch_sweep(int k, int tier, int dim, const SweepArgs& a, hipStream_t st);
+hipError_t launch_mass(const double* mass, int64_t n, double* partial, int nblocks,
+                       double* result, hipStream_t st);
+
+int mass_blocks(int64_t n);
+
+}  // namespace sldg

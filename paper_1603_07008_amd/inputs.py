@@ -164,3 +164,20 @@ def random_displacements(n, lo, hi, seed=0):
     """Seeded uniform displacements in [lo, hi) cells."""
     rng = np.random.default_rng(seed)
     return rng.uniform(lo, hi, size=n)
+
+
+def random_coefficients_device(ndim, k, cells, seed=0, scale0=0.15, decay=0.05, device="cuda"):
+    """The recipe of random_coefficients drawn on the device with torch's
+    seeded generator (for grids too large to draw on the host quickly).
+    Returns float64 mass [cells] and float64 higher modes [o^ndim - 1, cells]."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    o = k + 1
+    M = o ** ndim
+    mass = scale0 * (1.0 + 0.1 * torch.randn(cells, generator=g, device=device, dtype=torch.float64))
+    hi = torch.empty((M - 1, cells), device=device, dtype=torch.float64)
+    for m in range(1, M):
+        js = sum((m // o ** e) % o for e in range(ndim))
+        hi[m - 1].normal_(0.0, scale0 * decay ** js, generator=g)
+    return mass, hi

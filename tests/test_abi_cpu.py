@@ -1,0 +1,75 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/sldg.h declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1603_07008_amd as sl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "sldg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sldg_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(sl.LIB_PATH):
+        from paper_1603_07008_amd import build
+        build.build(force=False)
+    return sl.lib()
+
+
+def test_exports_every_declared_function(L):
+    names = _declared()
+    assert set(names) == set(sl.EXPORTS), names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _plan(L, ndim, ncells, k, tier):
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_int64 * max(1, len(ncells)))(*ncells) if ncells is not None else None
+    return L.sldg_plan(ctypes.byref(h), ndim, arr, k, tier, None), h
+
+
+def test_plan_rejects_bad_arguments_before_the_device(L):
+    assert L.sldg_plan(None, 1, None, 2, 1, None) == sl.SLDG_ERR_ARG
+    st, h = _plan(L, 0, [4], 2, 1)
+    assert st == sl.SLDG_ERR_ARG and h.value is None
+    st, _ = _plan(L, 7, [4] * 7, 2, 1)
+    assert st == sl.SLDG_ERR_ARG
+    st, _ = _plan(L, 1, None, 2, 1)
+    assert st == sl.SLDG_ERR_ARG
+    st, _ = _plan(L, 1, [4], 4, 1)
+    assert st == sl.SLDG_ERR_UNSUPPORTED and "degree" in sl.last_error()
+    st, _ = _plan(L, 1, [4], 0, 1)
+    assert st == sl.SLDG_ERR_UNSUPPORTED
+    st, _ = _plan(L, 1, [4], 2, 9)
+    assert st == sl.SLDG_ERR_UNSUPPORTED
+    st, _ = _plan(L, 2, [4, 0], 2, 1)
+    assert st == sl.SLDG_ERR_ARG
+    st, _ = _plan(L, 2, [1 << 16, 1 << 16], 2, 1)
+    assert st == sl.SLDG_ERR_UNSUPPORTED
+
+
+def test_calls_on_a_null_plan(L):
+    assert L.sldg_advect_dim(None, 0, None, 0, None, None, None, None) == sl.SLDG_ERR_ARG
+    out = (ctypes.c_double * 2)()
+    assert L.sldg_mass(None, None, out) == sl.SLDG_ERR_ARG
+    assert L.sldg_split_steps(None, None, 0, 0, None, None, None, None, None) == sl.SLDG_ERR_ARG
+    assert L.sldg_line_tables(None, 0, 1, None, None, None) == sl.SLDG_ERR_ARG
+    assert L.sldg_plan_set_stream(None, None) == sl.SLDG_ERR_ARG
+    assert L.sldg_hi_bytes(None) == -1
+    L.sldg_plan_destroy(None)
+
+
+def test_status_strings(L):
+    for st in range(6):
+        assert sl.status_string(st)
+    assert sl.status_string(99) == "unknown status"
