@@ -141,66 +141,82 @@ __device__ __forceinline__ int32_t table_index(const LineMap& m, int32_t lo, int
 }
 
 // ---------------------------------------------------------------------------
-// The per-cell update for one spectator tuple: o outputs from the o modes of
-// the two source cells.  MASS: the tuple contains the cell mean (mode 0); its
-// output is computed in FP64 from the exactly widened inputs.
+// Raw storage of one cell's o modes (along the swept dimension) and the
+// arithmetic on it.  Values stay in their storage type in registers and are
+// widened exactly when used.
 // ---------------------------------------------------------------------------
 
 template <int K, int TIER, bool MASS>
-struct Cell {
+struct Raw {
+  static constexpr int O = K + 1;
+  using T = typename Tier<TIER>::T;
+  double m;   // mode j = 0 when MASS
+  T h[O];     // modes (h[0] unused when MASS)
+};
+
+template <int K, int TIER, bool MASS>
+struct Mat {
   static constexpr int O = K + 1;
   using T = typename Tier<TIER>::T;
   using Acc = typename Tier<TIER>::Acc;
+  double Ad[O], Bd[O];         // mass row in FP64 (used when MASS)
+  Acc Aa[O][O], Ba[O][O];      // all rows in the arithmetic type
 
-  const T* in[O];      // planes of the input modes j_dim = 0..k (in[0] unused if MASS)
-  T* out[O];
-  const double* in_mass;
-  double* out_mass;
-  double Ad[O][O], Bd[O][O];   // FP64 matrices (mass row and FP64 arithmetic)
-  Acc Aa[O][O], Ba[O][O];      // matrices in the arithmetic type
-
-  __device__ __forceinline__ void load_matrices(const double* ab) {
+  __device__ __forceinline__ void load(const double* ab) {
 #pragma unroll
     for (int j = 0; j < O; ++j)
 #pragma unroll
       for (int l = 0; l < O; ++l) {
-        Ad[j][l] = ab[j * O + l];
-        Bd[j][l] = ab[O * O + j * O + l];
-        Aa[j][l] = (Acc)Ad[j][l];
-        Ba[j][l] = (Acc)Bd[j][l];
+        Aa[j][l] = (Acc)ab[j * O + l];
+        Ba[j][l] = (Acc)ab[O * O + j * O + l];
       }
-  }
-
-  // Load the o modes of cell c as exact FP64 values.
-  __device__ __forceinline__ void load(int64_t c, double (&v)[O]) const {
 #pragma unroll
     for (int l = 0; l < O; ++l) {
-      if (MASS && l == 0) v[l] = in_mass[c];
-      else v[l] = widen(in[l][c]);
+      Ad[l] = ab[l];
+      Bd[l] = ab[O * O + l];
     }
   }
 
-  __device__ __forceinline__ void update_store(int64_t c, const double (&x)[O],
-                                               const double (&y)[O]) const {
-#pragma unroll
-    for (int j = 0; j < O; ++j) {
-      if (MASS && j == 0) {
-        double acc = 0.0;
-#pragma unroll
-        for (int l = 0; l < O; ++l) acc = fma(Ad[0][l], x[l], acc);
-#pragma unroll
-        for (int l = 0; l < O; ++l) acc = fma(Bd[0][l], y[l], acc);
-        out_mass[c] = acc;
-      } else {
-        Acc acc = 0;
-#pragma unroll
-        for (int l = 0; l < O; ++l) acc = fma(Aa[j][l], (Acc)x[l], acc);
-#pragma unroll
-        for (int l = 0; l < O; ++l) acc = fma(Ba[j][l], (Acc)y[l], acc);
-        out[j][c] = narrow<T>(acc);
-      }
-    }
+  __device__ __forceinline__ static double wide(const Raw<K, TIER, MASS>& r, int l) {
+    return (MASS && l == 0) ? r.m : widen(r.h[l]);
   }
+  __device__ __forceinline__ static Acc acc_of(const Raw<K, TIER, MASS>& r, int l) {
+    if (MASS && l == 0) return (Acc)r.m;
+    if constexpr (sizeof(Acc) == 8) return widen(r.h[l]);
+    else return (Acc)r.h[l];
+  }
+
+  // Output mode j of the update from the two source cells x (cell i-s) and
+  // y (cell i-s-1).  The mass row of a MASS tuple is FP64 throughout.
+  __device__ __forceinline__ double mass_out(const Raw<K, TIER, MASS>& x,
+                                             const Raw<K, TIER, MASS>& y) const {
+    double acc = 0.0;
+#pragma unroll
+    for (int l = 0; l < O; ++l) acc = fma(Ad[l], wide(x, l), acc);
+#pragma unroll
+    for (int l = 0; l < O; ++l) acc = fma(Bd[l], wide(y, l), acc);
+    return acc;
+  }
+  __device__ __forceinline__ T hi_out(int j, const Raw<K, TIER, MASS>& x,
+                                      const Raw<K, TIER, MASS>& y) const {
+    Acc acc = 0;
+#pragma unroll
+    for (int l = 0; l < O; ++l) acc = fma(Aa[j][l], acc_of(x, l), acc);
+#pragma unroll
+    for (int l = 0; l < O; ++l) acc = fma(Ba[j][l], acc_of(y, l), acc);
+    return narrow<T>(acc);
+  }
+};
+
+// Plane pointers of one spectator tuple: mode m0 + l*mstride for l = 0..k.
+template <int K, int TIER, bool MASS>
+struct Planes {
+  static constexpr int O = K + 1;
+  using T = typename Tier<TIER>::T;
+  const T* in[O];
+  T* out[O];
+  const double* in_mass;
+  double* out_mass;
 
   __device__ __forceinline__ void bind(const SweepArgs& a, int64_t m0, int32_t mstride) {
     const T* hin = reinterpret_cast<const T*>(a.in_hi);
@@ -215,10 +231,23 @@ struct Cell {
     in_mass = a.in_mass;
     out_mass = a.out_mass;
   }
+  __device__ __forceinline__ void load(int64_t c, Raw<K, TIER, MASS>& r) const {
+    if (MASS) r.m = in_mass[c];
+#pragma unroll
+    for (int l = (MASS ? 1 : 0); l < O; ++l) r.h[l] = in[l][c];
+  }
+  __device__ __forceinline__ void store(int64_t c, const Mat<K, TIER, MASS>& M,
+                                        const Raw<K, TIER, MASS>& x,
+                                        const Raw<K, TIER, MASS>& y) const {
+    if (MASS) out_mass[c] = M.mass_out(x, y);
+#pragma unroll
+    for (int j = (MASS ? 1 : 0); j < O; ++j) out[j][c] = M.hi_out(j, x, y);
+  }
 };
 
 // ---------------------------------------------------------------------------
-// Sweep along dimension 0 (contiguous).  One wave per (line, spectator tuple):
+// Sweep along dimension 0, generic form (any N_0).  One wave per (line,
+// spectator tuple):
 // the line's s, A and B are wave-uniform (scalar registers), lanes walk the
 // line's cells, so every plane access of a wave is one contiguous run with a
 // periodic wrap.  The second source cell of lane L is the first one of lane
@@ -229,11 +258,12 @@ template <int K, int TIER, bool MASS>
 __device__ __forceinline__ void contig_line(const SweepArgs& a, int64_t line, int32_t sp,
                                             int lane) {
   constexpr int O = K + 1;
-  Cell<K, TIER, MASS> cell;
+  Mat<K, TIER, MASS> M;
+  Planes<K, TIER, MASS> pl;
   const int32_t t = __builtin_amdgcn_readfirstlane(table_index(a.map, 0, (int32_t)line));
   const int32_t s = __builtin_amdgcn_readfirstlane(a.s_tab[t]);
-  cell.load_matrices(a.ab_tab + (int64_t)t * 2 * O * O);
-  cell.bind(a, (int64_t)sp * O, 1);
+  M.load(a.ab_tab + (int64_t)t * 2 * O * O);
+  pl.bind(a, (int64_t)sp * O, 1);
   const int32_t N = a.N;
   const int64_t base = line * (int64_t)N;
   for (int32_t i = lane; i < N; i += 64) {
@@ -241,10 +271,10 @@ __device__ __forceinline__ void contig_line(const SweepArgs& a, int64_t line, in
     if (ia < 0) ia += N;
     int32_t ib = ia - 1;
     if (ib < 0) ib += N;
-    double x[O], y[O];
-    cell.load(base + ia, x);
-    cell.load(base + ib, y);
-    cell.update_store(base + i, x, y);
+    Raw<K, TIER, MASS> x, y;
+    pl.load(base + ia, x);
+    pl.load(base + ib, y);
+    pl.store(base + i, M, x, y);
   }
 }
 
@@ -264,45 +294,71 @@ __global__ __launch_bounds__(256) void sweep_contig_kernel(SweepArgs a) {
 // ---------------------------------------------------------------------------
 // Sweep along a dimension d > 0 (strided).  Lanes take consecutive cells of
 // the flattened lower dimensions (contiguous in memory); each thread streams
-// along its line through a chunk of rows keeping the previous source row in
-// registers, so every input row of the chunk is read once.  The displacement
-// (and so s, A, B) may differ from lane to lane.
+// along its line through a chunk of rows, keeping the previous source row in
+// registers so every input row of the chunk is read once.  Rows are loaded U
+// at a time and the loads of the next U rows are issued before the current
+// ones are computed and stored, so a wave keeps 2U rows of o planes in flight
+// (the sweep is latency-bound otherwise: one row per wave is far too little
+// to cover HBM latency).  The displacement (and so s, A, B) may differ from
+// lane to lane.
 // ---------------------------------------------------------------------------
 
-template <int K, int TIER, bool MASS>
+template <int K, int TIER, bool MASS, int U>
 __device__ __forceinline__ void strided_run(const SweepArgs& a, int32_t ilow, int32_t chunk,
                                             int32_t ihigh, int32_t sp) {
   constexpr int O = K + 1;
-  Cell<K, TIER, MASS> cell;
+  using R = Raw<K, TIER, MASS>;
+  Mat<K, TIER, MASS> M;
+  Planes<K, TIER, MASS> pl;
   const int32_t t = table_index(a.map, ilow, ihigh);
   const int32_t s = a.s_tab[t];
-  cell.load_matrices(a.ab_tab + (int64_t)t * 2 * O * O);
+  M.load(a.ab_tab + (int64_t)t * 2 * O * O);
   const int32_t ms = a.mstride;
   const int64_t m0 = (int64_t)(sp % ms) + (int64_t)(sp / ms) * ms * O;
-  cell.bind(a, m0, ms);
+  pl.bind(a, m0, ms);
   const int32_t N = a.N, P = a.P;
   const int64_t base = (int64_t)ihigh * P * N + ilow;
   const int32_t r0 = chunk * a.chunk;
-  const int32_t r1 = min(N, r0 + a.chunk);
+  const int32_t n = min(N, r0 + a.chunk) - r0;
   int32_t iy = r0 - s - 1;
   if (iy < 0) iy += N;
-  if (iy < 0) iy += N;
-  double y[O];
-  cell.load(base + (int64_t)iy * P, y);
-  int32_t ix = iy + 1;
+  R y;
+  pl.load(base + (int64_t)iy * P, y);
+  int32_t ix = iy + 1;             // next source row to load (cell i - s)
   if (ix == N) ix = 0;
-  for (int32_t i = r0; i < r1; ++i) {
-    double x[O];
-    cell.load(base + (int64_t)ix * P, x);
-    cell.update_store(base + (int64_t)i * P, x, y);
+  R xa[U], xb[U];
 #pragma unroll
-    for (int l = 0; l < O; ++l) y[l] = x[l];
-    if (++ix == N) ix = 0;
+  for (int u = 0; u < U; ++u) {
+    if (u < n) {
+      pl.load(base + (int64_t)ix * P, xa[u]);
+      if (++ix == N) ix = 0;
+    }
+  }
+  for (int32_t g = 0; g < n; g += U) {
+    const int32_t cnt = min(U, n - g);
+    const int32_t nxt = n - g - U;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (u < nxt) {
+        pl.load(base + (int64_t)ix * P, xb[u]);
+        if (++ix == N) ix = 0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (u < cnt) {
+        pl.store(base + (int64_t)(r0 + g + u) * P, M, xa[u], y);
+        y = xa[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) xa[u] = xb[u];
   }
 }
 
 template <int K, int TIER>
 __global__ __launch_bounds__(256) void sweep_strided_kernel(SweepArgs a) {
+  constexpr int U = 4;
   const int32_t sp = blockIdx.y;
   const int64_t per = (int64_t)a.P * a.nchunk * a.Q;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -311,16 +367,162 @@ __global__ __launch_bounds__(256) void sweep_strided_kernel(SweepArgs a) {
   const int64_t r = tid / a.P;
   const int32_t chunk = (int32_t)(r % a.nchunk);
   const int32_t ihigh = (int32_t)(r / a.nchunk);
-  if (sp == 0) strided_run<K, TIER, true>(a, ilow, chunk, ihigh, sp);
-  else strided_run<K, TIER, false>(a, ilow, chunk, ihigh, sp);
+  if (sp == 0) strided_run<K, TIER, true, U>(a, ilow, chunk, ihigh, sp);
+  else strided_run<K, TIER, false, U>(a, ilow, chunk, ihigh, sp);
+}
+
+// ---------------------------------------------------------------------------
+// Sweep along dimension 0 with an LDS tile.  A block takes `tile_lines`
+// consecutive lines of one spectator tuple: a contiguous segment of each of
+// the o planes, copied to LDS with 16-byte loads (the whole line is resident,
+// so the periodic wrap and the upwind neighbour cost no extra HBM access),
+// together with the lines' s, A and B.  Each thread then produces V = 4
+// consecutive output cells of one line from a window of V+1 source cells
+// read from LDS, and writes them with one vector store per plane.
+// Requires N_0 % 8 == 0 (16-byte alignment of every line in every plane).
+// ---------------------------------------------------------------------------
+
+constexpr int kTileV = 4;
+
+template <class T> struct Vec4;
+template <> struct Vec4<double> { using type = double4; };
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<__bf16> { using type = uint2; };
+template <> struct Vec4<_Float16> { using type = uint2; };
+
+template <class T>
+__device__ __forceinline__ void store4(T* dst, const T (&v)[4]) {
+  if constexpr (sizeof(T) == 8) {
+    double2* d = reinterpret_cast<double2*>(dst);
+    d[0] = make_double2(v[0], v[1]);
+    d[1] = make_double2(v[2], v[3]);
+  } else if constexpr (sizeof(T) == 4) {
+    *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+  } else {
+    uint16_t b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) b[u] = __builtin_bit_cast(uint16_t, v[u]);
+    *reinterpret_cast<uint2*>(dst) = make_uint2((uint32_t)b[0] | ((uint32_t)b[1] << 16),
+                                                (uint32_t)b[2] | ((uint32_t)b[3] << 16));
+  }
+}
+
+// Copy `bytes` (a multiple of 16) from global to LDS with 16-byte accesses.
+__device__ __forceinline__ void copy_to_lds(void* lds, const void* src, int32_t bytes) {
+  const uint4* s4 = reinterpret_cast<const uint4*>(src);
+  uint4* d4 = reinterpret_cast<uint4*>(lds);
+  const int32_t n = bytes >> 4;
+  for (int32_t i = threadIdx.x; i < n; i += blockDim.x) d4[i] = s4[i];
+}
+
+template <int K, int TIER, bool MASS>
+__device__ __forceinline__ void contig_tile(const SweepArgs& a, int32_t tile_lines,
+                                            unsigned char* smem) {
+  constexpr int O = K + 1;
+  constexpr int V = kTileV;
+  using T = typename Tier<TIER>::T;
+  using Acc = typename Tier<TIER>::Acc;
+  using R = Raw<K, TIER, MASS>;
+  const int32_t sp = blockIdx.y;
+  const int32_t N = a.N;
+  const int64_t line0 = (int64_t)blockIdx.x * tile_lines;
+  const int32_t nl = (int32_t)min((int64_t)tile_lines, (int64_t)a.Q - line0);
+  const int32_t tc = nl * N;                      // cells in this tile
+  const int32_t cap = tile_lines * N;             // cells per plane slot
+  // LDS layout: A/B per line | s per line | plane 0 (8-byte slots) | planes 1..k
+  double* ab_l = reinterpret_cast<double*>(smem);
+  int32_t* s_l = reinterpret_cast<int32_t*>(ab_l + tile_lines * 2 * O * O);
+  unsigned char* pbase = smem + tile_lines * (2 * O * O * 8 + 4);
+  pbase += (16 - ((uintptr_t)pbase & 15)) & 15;
+  double* p0d = reinterpret_cast<double*>(pbase);
+  T* p0t = reinterpret_cast<T*>(pbase);
+  T* ph[O];
+#pragma unroll
+  for (int l = 1; l < O; ++l)
+    ph[l] = reinterpret_cast<T*>(pbase + (size_t)cap * 8 + (size_t)(l - 1) * cap * sizeof(T));
+  ph[0] = p0t;
+
+  Planes<K, TIER, MASS> pl;
+  pl.bind(a, (int64_t)sp * O, 1);
+  const int64_t cell0 = line0 * N;
+  // per-line tables
+  for (int32_t q = threadIdx.x; q < nl * 2 * O * O; q += blockDim.x) {
+    const int32_t li = q / (2 * O * O);
+    const int32_t e = q - li * (2 * O * O);
+    const int32_t t = table_index(a.map, 0, (int32_t)(line0 + li));
+    ab_l[q] = a.ab_tab[(int64_t)t * 2 * O * O + e];
+    if (e == 0) s_l[li] = a.s_tab[t];
+  }
+  // plane segments
+  if (MASS) copy_to_lds(p0d, pl.in_mass + cell0, tc * 8);
+#pragma unroll
+  for (int l = (MASS ? 1 : 0); l < O; ++l)
+    copy_to_lds(ph[l], pl.in[l] + cell0, tc * (int32_t)sizeof(T));
+  __syncthreads();
+
+  const int32_t ng = tc / V;
+  for (int32_t g = threadIdx.x; g < ng; g += blockDim.x) {
+    const int32_t c = g * V;
+    const int32_t li = c / N;
+    const int32_t i0 = c - li * N;
+    const int32_t s = s_l[li];
+    Mat<K, TIER, MASS> M;
+    M.load(ab_l + li * 2 * O * O);
+    // window of source cells i0-s-1 .. i0-s+V-1 (periodic in the line)
+    R w[V + 1];
+    int32_t idx = i0 - s - 1;
+    if (idx < 0) idx += N;
+    const int32_t lb = li * N;
+#pragma unroll
+    for (int u = 0; u <= V; ++u) {
+      if (MASS) w[u].m = p0d[lb + idx];
+#pragma unroll
+      for (int l = (MASS ? 1 : 0); l < O; ++l) w[u].h[l] = ph[l][lb + idx];
+      if (++idx == N) idx = 0;
+    }
+    const int64_t gc = cell0 + c;
+    if (MASS) {
+      double o4[V];
+#pragma unroll
+      for (int u = 0; u < V; ++u) o4[u] = M.mass_out(w[u + 1], w[u]);
+      store4<double>(pl.out_mass + gc, o4);
+    }
+#pragma unroll
+    for (int j = (MASS ? 1 : 0); j < O; ++j) {
+      T o4[V];
+#pragma unroll
+      for (int u = 0; u < V; ++u) o4[u] = M.hi_out(j, w[u + 1], w[u]);
+      store4<T>(pl.out[j] + gc, o4);
+    }
+  }
+}
+
+template <int K, int TIER>
+__global__ __launch_bounds__(256) void sweep_contig_tiled_kernel(SweepArgs a, int32_t tile_lines) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (blockIdx.y == 0) contig_tile<K, TIER, true>(a, tile_lines, smem);
+  else contig_tile<K, TIER, false>(a, tile_lines, smem);
 }
 
 template <int K, int TIER>
 static hipError_t launch_sweep_kt(int dim, const SweepArgs& a, hipStream_t st) {
+  using T = typename Tier<TIER>::T;
+  constexpr int O = K + 1;
   if (dim == 0) {
-    const int64_t items = (int64_t)a.Q * a.nspec;
-    dim3 grid((unsigned)((items + 3) / 4)), block(256);
-    sweep_contig_kernel<K, TIER><<<grid, block, 0, st>>>(a);
+    const int64_t lds_per_cell = 8 + (int64_t)(O - 1) * sizeof(T);
+    const int64_t tile_cells = sizeof(T) == 8 ? 1024 : 2048;
+    const uintptr_t align = (uintptr_t)a.in_mass | (uintptr_t)a.in_hi | (uintptr_t)a.out_mass |
+                            (uintptr_t)a.out_hi;
+    if (a.N % 8 == 0 && a.N <= tile_cells && (align & 15) == 0) {
+      const int32_t tl = (int32_t)(tile_cells / a.N);
+      const size_t lds = (size_t)tl * (2 * O * O * 8 + 4) + 16 + (size_t)tl * a.N * lds_per_cell;
+      dim3 grid((unsigned)((a.Q + tl - 1) / tl), (unsigned)a.nspec), block(256);
+      sweep_contig_tiled_kernel<K, TIER><<<grid, block, lds, st>>>(a, tl);
+    } else {
+      const int64_t items = (int64_t)a.Q * a.nspec;
+      dim3 grid((unsigned)((items + 3) / 4)), block(256);
+      sweep_contig_kernel<K, TIER><<<grid, block, 0, st>>>(a);
+    }
   } else {
     const int64_t per = (int64_t)a.P * a.nchunk * a.Q;
     dim3 grid((unsigned)((per + 255) / 256), (unsigned)a.nspec), block(256);
