@@ -66,6 +66,27 @@ def measured_traffic(kernel):
     return None if ent is None else ent.get("bytes_per_launch")
 
 
+def measured_copy_bandwidth(torch, nbytes, reps=10):
+    """Read+write bandwidth of a plain device copy of `nbytes` (torch's copy
+    kernel), the reference the paper's copy-benchmark column corresponds to."""
+    n = nbytes // 16
+    src = torch.ones(n, 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * n * 16 / (ms * 1e-3) / 1e9
+
+
 def run_tier(sl, torch, prob, tier, init, steps, warmup):
     """Time `steps` split steps (after `warmup`) of `prob` in `tier`."""
     p = sl.Plan(prob.ns, prob.k, tier)
@@ -98,9 +119,12 @@ def run_tier(sl, torch, prob, tier, init, steps, warmup):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / steps
     p.timing_enable(False)
+    tid = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}[tier]
+    contig = "sweep_contig_window_kernel" if prob.ns[0] % 4 == 0 else "sweep_contig_kernel"
+    rows = int(os.environ.get("SLDG_STRIDED_ROWS", "2"))
     kern = {
-        "sweep_contig": p.timing_read(-1),
-        "sweep_strided": p.timing_read(-2),
+        f"sldg::{contig}<{prob.k}, {tid}>": p.timing_read(-1),
+        f"sldg::sweep_strided_kernel<{prob.k}, {tid}, {rows}>": p.timing_read(-2),
     }
     per_dim = {d: p.timing_read(d) for d in range(prob.ndim)}
     m_end = p.mass(bufs[cur][0])
@@ -178,6 +202,8 @@ def main():
     mass0, hi0 = inputs.random_coefficients_device(prob.ndim, prob.k, cells, seed=args.seed)
     torch.cuda.synchronize()
 
+    copy_gbs = measured_copy_bandwidth(torch, state_bytes(cells, modes, args.tier))
+    log(f"bench: device copy bandwidth {copy_gbs:.0f} GB/s")
     tiers = [args.tier] + [t for t in args.compare.split(",") if t and t != args.tier]
     results = {}
     for t in tiers:
@@ -200,7 +226,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "kernel": kname, "launches": nl,
-                "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": launch_bytes}
+                "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": launch_bytes,
+                "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
 
     names = {0: "X1", 1: "X2", 2: "V1", 3: "V2"}
     per_sweep = {}

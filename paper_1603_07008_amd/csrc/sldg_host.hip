@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -31,7 +32,7 @@ struct sldg_plan_s {
   double* d_mass_part;    // [2 * mass_nblocks]
   double* d_mass_out;     // [2]
   double* h_mass_out;     // pinned [2]
-  int32_t target_threads; // strided sweep: threads to aim for when chunking
+  int rows_per_thread;    // strided sweep: rows per thread (1, 2, 4 or 8)
   // kernel timing (sldg_timing_*)
   bool timing;
   int ntimed;
@@ -144,15 +145,12 @@ void describe(const sldg_plan_s* p, int dim, uint32_t dep_mask, SweepArgs& a, in
   }
   a.map = m;
   ntab = str;
-  // strided sweep: split the swept dimension into chunks until the launch
-  // has enough threads to cover the chip
+  // strided sweep: rows per thread (one-shot chunks along the swept dim)
   if (dim > 0) {
-    const int64_t base = P * Q * a.nspec;
-    int64_t nch = (p->target_threads + base - 1) / base;
-    nch = std::max<int64_t>(1, std::min<int64_t>(nch, a.N));
-    const int64_t len = (a.N + nch - 1) / nch;
-    a.chunk = (int32_t)len;
-    a.nchunk = (int32_t)((a.N + len - 1) / len);
+    int rows = p->rows_per_thread;
+    while (rows > 1 && rows > a.N) rows >>= 1;
+    a.chunk = rows;
+    a.nchunk = (int32_t)((a.N + rows - 1) / rows);
   } else {
     a.chunk = a.N;
     a.nchunk = 1;
@@ -182,7 +180,8 @@ sldg_status run_sweep(sldg_plan_s* p, int dim, const double* shift, uint32_t dep
   if (ntab > p->table_cap)
     return fail(SLDG_ERR_ARG, "line table of %lld entries exceeds the plan's %lld",
                 (long long)ntab, (long long)p->table_cap);
-  hipError_t e = launch_line_tables(p->k, ntab, p->n[dim], shift, p->d_s, p->d_ab, p->stream);
+  hipError_t e = launch_line_tables(p->k, ntab, p->n[dim], shift, p->d_s, p->d_ab, true,
+                                    p->stream);
   if (e != hipSuccess) return device_error(e, "line-table launch");
   a.in_mass = in_mass;
   a.in_hi = in_hi;
@@ -190,6 +189,7 @@ sldg_status run_sweep(sldg_plan_s* p, int dim, const double* shift, uint32_t dep
   a.out_hi = out_hi;
   a.s_tab = p->d_s;
   a.ab_tab = p->d_ab;
+  a.ab_cs = ntab;
   const bool timed = p->timing && p->ntimed < kMaxTimed;
   if (timed) {
     const int i = p->ntimed;
@@ -264,7 +264,11 @@ sldg_status sldg_plan(sldg_plan_t* out, int ndim, const int64_t* ncells, int k, 
   for (int e = 0; e < ndim; ++e) p->modes *= p->o;
   p->hi_bytes = (p->modes - 1) * cells * elem_size(tier);
   p->table_cap = cells / min_n;     // the most lines any sweep can have
-  p->target_threads = 256 * 256 * 4;
+  p->rows_per_thread = 2;
+  if (const char* env = getenv("SLDG_STRIDED_ROWS")) {
+    const int r = atoi(env);
+    if (r == 1 || r == 2 || r == 4 || r == 8) p->rows_per_thread = r;
+  }
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) {
     free_plan(p);
@@ -338,7 +342,7 @@ sldg_status sldg_line_tables(sldg_plan_t p, int64_t n, int64_t period, const dou
   if (n < 0 || period < 1) return fail(SLDG_ERR_ARG, "n=%lld period=%lld", (long long)n, (long long)period);
   if (n > 0 && (!sigma || !s_out || !ab_out)) return fail(SLDG_ERR_ARG, "null pointer");
   if (period >= (1LL << 31)) return fail(SLDG_ERR_ARG, "period too large");
-  hipError_t e = launch_line_tables(p->k, n, period, sigma, s_out, ab_out, p->stream);
+  hipError_t e = launch_line_tables(p->k, n, period, sigma, s_out, ab_out, false, p->stream);
   if (e != hipSuccess) return device_error(e, "line-table launch");
   return ok();
 }

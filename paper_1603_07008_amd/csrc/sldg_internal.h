@@ -26,7 +26,9 @@ struct SweepArgs {
   double* out_mass;
   void* out_hi;
   const int32_t* s_tab;   // per table entry: s mod N, in [0, N)
-  const double* ab_tab;   // per table entry: A then B, (k+1)^2 each, row-major
+  const double* ab_tab;   // per table entry t: A then B, (k+1)^2 each, row-major,
+                          // component e of entry t at ab_tab[e * ab_cs + t]
+  int64_t ab_cs;          // component stride of the table (= its entry count)
   int64_t cells;          // cells of the grid (plane length)
   int32_t P;              // product of the extents below the swept dim (row stride)
   int32_t N;              // extent of the swept dim
@@ -34,13 +36,14 @@ struct SweepArgs {
   int32_t mstride;        // (k+1)^dim: mode-id distance between j_dim and j_dim+1
   int32_t nspec;          // (k+1)^(ndim-1) spectator mode tuples
   int32_t nchunk;         // strided sweep: chunks along the swept dim
-  int32_t chunk;          // strided sweep: rows per chunk
+  int32_t chunk;          // strided sweep: rows per thread (1, 2, 4 or 8)
   LineMap map;
 };
 
 // Launchers (defined in sldg_kernels.hip).  All return hipGetLastError().
 hipError_t launch_line_tables(int k, int64_t n, int64_t period, const double* sigma,
-                              int32_t* s_out, double* ab_out, hipStream_t st);
+                              int32_t* s_out, double* ab_out, bool component_major,
+                              hipStream_t st);
 hipError_t launch_sweep(int k, int tier, int dim, const SweepArgs& a, hipStream_t st);
 hipError_t launch_mass(const double* mass, int64_t n, double* partial, int nblocks,
                        double* result, hipStream_t st);

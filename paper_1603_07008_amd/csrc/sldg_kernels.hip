@@ -68,11 +68,16 @@ __device__ __forceinline__ double horner_comp(const double (&c)[2 * K + 2], doub
   return r + err;
 }
 
+// Table layout: entry t, component e (A row-major, then B row-major) at
+// ab_out[e * cs + t * ts]: (cs, ts) = (1, 2(k+1)^2) is entry-major (the public
+// layout), (n, 1) component-major (used by the sweeps, so that lanes reading
+// the matrices of consecutive lines touch consecutive addresses).
 template <int K>
 __global__ __launch_bounds__(256) void line_tables_kernel(int64_t n, int64_t period,
                                                           const double* __restrict__ sigma,
                                                           int32_t* __restrict__ s_out,
-                                                          double* __restrict__ ab_out) {
+                                                          double* __restrict__ ab_out,
+                                                          int64_t cs, int64_t ts) {
   constexpr int O = K + 1;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
@@ -88,8 +93,7 @@ __global__ __launch_bounds__(256) void line_tables_kernel(int64_t n, int64_t per
     beta = 1.0;
   }
   int32_t s = 0;
-  bool ok = isfinite(sg);
-  if (ok) {
+  if (isfinite(sg)) {
     double r = fmod(fs, (double)period);   // exact
     if (r < 0) r += (double)period;
     s = (int32_t)r;
@@ -98,32 +102,42 @@ __global__ __launch_bounds__(256) void line_tables_kernel(int64_t n, int64_t per
     beta = alpha;
   }
   s_out[t] = s;
-  double* A = ab_out + t * 2 * O * O;
-  double* B = A + O * O;
+  double A[O][O], B[O][O];
 #pragma unroll
   for (int j = 0; j < O; ++j) {
 #pragma unroll
     for (int l = 0; l < O; ++l) {
-      A[j * O + l] = horner_comp<K>(AbPoly<K>::A[j][l], alpha);
-      B[j * O + l] = horner_comp<K>(AbPoly<K>::B[j][l], alpha);
+      A[j][l] = horner_comp<K>(AbPoly<K>::A[j][l], alpha);
+      B[j][l] = horner_comp<K>(AbPoly<K>::B[j][l], alpha);
     }
   }
   // Mass row made exact: int P_l over a cell vanishes for l >= 1, so the two
   // contributions of a source cell to the cell means must cancel exactly.
-  A[0] = beta;
-  B[0] = alpha;
+  A[0][0] = beta;
+  B[0][0] = alpha;
 #pragma unroll
-  for (int l = 1; l < O; ++l) B[l] = -A[l];
+  for (int l = 1; l < O; ++l) B[0][l] = -A[0][l];
+  double* base = ab_out + t * ts;
+#pragma unroll
+  for (int j = 0; j < O; ++j)
+#pragma unroll
+    for (int l = 0; l < O; ++l) {
+      base[(j * O + l) * cs] = A[j][l];
+      base[(O * O + j * O + l) * cs] = B[j][l];
+    }
 }
 
 hipError_t launch_line_tables(int k, int64_t n, int64_t period, const double* sigma,
-                              int32_t* s_out, double* ab_out, hipStream_t st) {
+                              int32_t* s_out, double* ab_out, bool component_major,
+                              hipStream_t st) {
   if (n <= 0) return hipSuccess;
+  const int64_t e = 2LL * (k + 1) * (k + 1);
+  const int64_t cs = component_major ? n : 1, ts = component_major ? 1 : e;
   dim3 grid((unsigned)((n + 255) / 256)), block(256);
   switch (k) {
-    case 1: line_tables_kernel<1><<<grid, block, 0, st>>>(n, period, sigma, s_out, ab_out); break;
-    case 2: line_tables_kernel<2><<<grid, block, 0, st>>>(n, period, sigma, s_out, ab_out); break;
-    case 3: line_tables_kernel<3><<<grid, block, 0, st>>>(n, period, sigma, s_out, ab_out); break;
+    case 1: line_tables_kernel<1><<<grid, block, 0, st>>>(n, period, sigma, s_out, ab_out, cs, ts); break;
+    case 2: line_tables_kernel<2><<<grid, block, 0, st>>>(n, period, sigma, s_out, ab_out, cs, ts); break;
+    case 3: line_tables_kernel<3><<<grid, block, 0, st>>>(n, period, sigma, s_out, ab_out, cs, ts); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -154,32 +168,38 @@ struct Raw {
   T h[O];     // modes (h[0] unused when MASS)
 };
 
-template <int K, int TIER, bool MASS>
+template <int K, int TIER>
 struct Mat {
   static constexpr int O = K + 1;
   using T = typename Tier<TIER>::T;
   using Acc = typename Tier<TIER>::Acc;
-  double Ad[O], Bd[O];         // mass row in FP64 (used when MASS)
+  double Ad[O], Bd[O];         // mass row in FP64 (used by the tuple holding mode 0)
   Acc Aa[O][O], Ba[O][O];      // all rows in the arithmetic type
 
-  __device__ __forceinline__ void load(const double* ab) {
+  // Matrices of table entry ab (component e at ab[e * cs]).
+  __device__ __forceinline__ void load(const double* ab, int64_t cs) {
+    double a[O][O], b[O][O];
 #pragma unroll
     for (int j = 0; j < O; ++j)
 #pragma unroll
       for (int l = 0; l < O; ++l) {
-        Aa[j][l] = (Acc)ab[j * O + l];
-        Ba[j][l] = (Acc)ab[O * O + j * O + l];
+        a[j][l] = ab[(j * O + l) * cs];
+        b[j][l] = ab[(O * O + j * O + l) * cs];
+        Aa[j][l] = (Acc)a[j][l];
+        Ba[j][l] = (Acc)b[j][l];
       }
 #pragma unroll
     for (int l = 0; l < O; ++l) {
-      Ad[l] = ab[l];
-      Bd[l] = ab[O * O + l];
+      Ad[l] = a[0][l];
+      Bd[l] = b[0][l];
     }
   }
 
+  template <bool MASS>
   __device__ __forceinline__ static double wide(const Raw<K, TIER, MASS>& r, int l) {
     return (MASS && l == 0) ? r.m : widen(r.h[l]);
   }
+  template <bool MASS>
   __device__ __forceinline__ static Acc acc_of(const Raw<K, TIER, MASS>& r, int l) {
     if (MASS && l == 0) return (Acc)r.m;
     if constexpr (sizeof(Acc) == 8) return widen(r.h[l]);
@@ -187,7 +207,8 @@ struct Mat {
   }
 
   // Output mode j of the update from the two source cells x (cell i-s) and
-  // y (cell i-s-1).  The mass row of a MASS tuple is FP64 throughout.
+  // y (cell i-s-1).  The mass row of the tuple holding mode 0 is FP64 throughout.
+  template <bool MASS>
   __device__ __forceinline__ double mass_out(const Raw<K, TIER, MASS>& x,
                                              const Raw<K, TIER, MASS>& y) const {
     double acc = 0.0;
@@ -197,6 +218,7 @@ struct Mat {
     for (int l = 0; l < O; ++l) acc = fma(Bd[l], wide(y, l), acc);
     return acc;
   }
+  template <bool MASS>
   __device__ __forceinline__ T hi_out(int j, const Raw<K, TIER, MASS>& x,
                                       const Raw<K, TIER, MASS>& y) const {
     Acc acc = 0;
@@ -236,7 +258,7 @@ struct Planes {
 #pragma unroll
     for (int l = (MASS ? 1 : 0); l < O; ++l) r.h[l] = in[l][c];
   }
-  __device__ __forceinline__ void store(int64_t c, const Mat<K, TIER, MASS>& M,
+  __device__ __forceinline__ void store(int64_t c, const Mat<K, TIER>& M,
                                         const Raw<K, TIER, MASS>& x,
                                         const Raw<K, TIER, MASS>& y) const {
     if (MASS) out_mass[c] = M.mass_out(x, y);
@@ -246,23 +268,20 @@ struct Planes {
 };
 
 // ---------------------------------------------------------------------------
-// Sweep along dimension 0, generic form (any N_0).  One wave per (line,
-// spectator tuple):
-// the line's s, A and B are wave-uniform (scalar registers), lanes walk the
-// line's cells, so every plane access of a wave is one contiguous run with a
-// periodic wrap.  The second source cell of lane L is the first one of lane
-// L-1, so the reuse is served by the vector L1.
+// Sweep along dimension 0, generic form (any N_0, any alignment).  One wave
+// per (line, spectator tuple): the line's s, A and B are wave-uniform (scalar
+// registers), lanes walk the line's cells.
 // ---------------------------------------------------------------------------
 
 template <int K, int TIER, bool MASS>
 __device__ __forceinline__ void contig_line(const SweepArgs& a, int64_t line, int32_t sp,
                                             int lane) {
   constexpr int O = K + 1;
-  Mat<K, TIER, MASS> M;
+  Mat<K, TIER> M;
   Planes<K, TIER, MASS> pl;
   const int32_t t = __builtin_amdgcn_readfirstlane(table_index(a.map, 0, (int32_t)line));
   const int32_t s = __builtin_amdgcn_readfirstlane(a.s_tab[t]);
-  M.load(a.ab_tab + (int64_t)t * 2 * O * O);
+  M.load(a.ab_tab + t, a.ab_cs);
   pl.bind(a, (int64_t)sp * O, 1);
   const int32_t N = a.N;
   const int64_t base = line * (int64_t)N;
@@ -292,103 +311,40 @@ __global__ __launch_bounds__(256) void sweep_contig_kernel(SweepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Sweep along a dimension d > 0 (strided).  Lanes take consecutive cells of
-// the flattened lower dimensions (contiguous in memory); each thread streams
-// along its line through a chunk of rows, keeping the previous source row in
-// registers so every input row of the chunk is read once.  Rows are loaded U
-// at a time and the loads of the next U rows are issued before the current
-// ones are computed and stored, so a wave keeps 2U rows of o planes in flight
-// (the sweep is latency-bound otherwise: one row per wave is far too little
-// to cover HBM latency).  The displacement (and so s, A, B) may differ from
-// lane to lane.
+// Sweep along dimension 0, window form (N_0 % 4 == 0, 16-byte aligned
+// buffers).  A thread produces 4 consecutive output cells i0..i0+3 of one line
+// for one spectator tuple.  Their sources are the 5 cells i0-s-1 .. i0-s+3,
+// which lie in two consecutive aligned 4-cell blocks of the line (periodic at
+// block granularity since N_0 % 4 == 0); the thread loads both blocks with
+// vector loads, picks the window with the in-block offset and writes its 4
+// outputs with one vector store per plane.  Neighbouring threads load the same
+// blocks, which the vector L1 serves: every coefficient crosses HBM once.
+// A launch is one-shot (each thread a few loads, then stores, then exit),
+// which on MI355X streams closer to peak than long-lived threads.
 // ---------------------------------------------------------------------------
 
-template <int K, int TIER, bool MASS, int U>
-__device__ __forceinline__ void strided_run(const SweepArgs& a, int32_t ilow, int32_t chunk,
-                                            int32_t ihigh, int32_t sp) {
-  constexpr int O = K + 1;
-  using R = Raw<K, TIER, MASS>;
-  Mat<K, TIER, MASS> M;
-  Planes<K, TIER, MASS> pl;
-  const int32_t t = table_index(a.map, ilow, ihigh);
-  const int32_t s = a.s_tab[t];
-  M.load(a.ab_tab + (int64_t)t * 2 * O * O);
-  const int32_t ms = a.mstride;
-  const int64_t m0 = (int64_t)(sp % ms) + (int64_t)(sp / ms) * ms * O;
-  pl.bind(a, m0, ms);
-  const int32_t N = a.N, P = a.P;
-  const int64_t base = (int64_t)ihigh * P * N + ilow;
-  const int32_t r0 = chunk * a.chunk;
-  const int32_t n = min(N, r0 + a.chunk) - r0;
-  int32_t iy = r0 - s - 1;
-  if (iy < 0) iy += N;
-  R y;
-  pl.load(base + (int64_t)iy * P, y);
-  int32_t ix = iy + 1;             // next source row to load (cell i - s)
-  if (ix == N) ix = 0;
-  R xa[U], xb[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    if (u < n) {
-      pl.load(base + (int64_t)ix * P, xa[u]);
-      if (++ix == N) ix = 0;
-    }
+template <class T>
+struct Blk4 { T v[4]; };
+
+template <class T>
+__device__ __forceinline__ Blk4<T> load4(const T* p) {
+  Blk4<T> r;
+  if constexpr (sizeof(T) == 8) {
+    const double2* q = reinterpret_cast<const double2*>(p);
+    const double2 a = q[0], b = q[1];
+    r.v[0] = a.x; r.v[1] = a.y; r.v[2] = b.x; r.v[3] = b.y;
+  } else if constexpr (sizeof(T) == 4) {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    r.v[0] = a.x; r.v[1] = a.y; r.v[2] = a.z; r.v[3] = a.w;
+  } else {
+    const uint2 a = *reinterpret_cast<const uint2*>(p);
+    r.v[0] = __builtin_bit_cast(T, (uint16_t)(a.x & 0xffff));
+    r.v[1] = __builtin_bit_cast(T, (uint16_t)(a.x >> 16));
+    r.v[2] = __builtin_bit_cast(T, (uint16_t)(a.y & 0xffff));
+    r.v[3] = __builtin_bit_cast(T, (uint16_t)(a.y >> 16));
   }
-  for (int32_t g = 0; g < n; g += U) {
-    const int32_t cnt = min(U, n - g);
-    const int32_t nxt = n - g - U;
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (u < nxt) {
-        pl.load(base + (int64_t)ix * P, xb[u]);
-        if (++ix == N) ix = 0;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (u < cnt) {
-        pl.store(base + (int64_t)(r0 + g + u) * P, M, xa[u], y);
-        y = xa[u];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) xa[u] = xb[u];
-  }
+  return r;
 }
-
-template <int K, int TIER>
-__global__ __launch_bounds__(256) void sweep_strided_kernel(SweepArgs a) {
-  constexpr int U = 4;
-  const int32_t sp = blockIdx.y;
-  const int64_t per = (int64_t)a.P * a.nchunk * a.Q;
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= per) return;
-  const int32_t ilow = (int32_t)(tid % a.P);
-  const int64_t r = tid / a.P;
-  const int32_t chunk = (int32_t)(r % a.nchunk);
-  const int32_t ihigh = (int32_t)(r / a.nchunk);
-  if (sp == 0) strided_run<K, TIER, true, U>(a, ilow, chunk, ihigh, sp);
-  else strided_run<K, TIER, false, U>(a, ilow, chunk, ihigh, sp);
-}
-
-// ---------------------------------------------------------------------------
-// Sweep along dimension 0 with an LDS tile.  A block takes `tile_lines`
-// consecutive lines of one spectator tuple: a contiguous segment of each of
-// the o planes, copied to LDS with 16-byte loads (the whole line is resident,
-// so the periodic wrap and the upwind neighbour cost no extra HBM access),
-// together with the lines' s, A and B.  Each thread then produces V = 4
-// consecutive output cells of one line from a window of V+1 source cells
-// read from LDS, and writes them with one vector store per plane.
-// Requires N_0 % 8 == 0 (16-byte alignment of every line in every plane).
-// ---------------------------------------------------------------------------
-
-constexpr int kTileV = 4;
-
-template <class T> struct Vec4;
-template <> struct Vec4<double> { using type = double4; };
-template <> struct Vec4<float> { using type = float4; };
-template <> struct Vec4<__bf16> { using type = uint2; };
-template <> struct Vec4<_Float16> { using type = uint2; };
 
 template <class T>
 __device__ __forceinline__ void store4(T* dst, const T (&v)[4]) {
@@ -407,117 +363,220 @@ __device__ __forceinline__ void store4(T* dst, const T (&v)[4]) {
   }
 }
 
-// Copy `bytes` (a multiple of 16) from global to LDS with 16-byte accesses.
-__device__ __forceinline__ void copy_to_lds(void* lds, const void* src, int32_t bytes) {
-  const uint4* s4 = reinterpret_cast<const uint4*>(src);
-  uint4* d4 = reinterpret_cast<uint4*>(lds);
-  const int32_t n = bytes >> 4;
-  for (int32_t i = threadIdx.x; i < n; i += blockDim.x) d4[i] = s4[i];
+// The 5-cell window starting at offset d (0..3) of the 8 cells of blocks b0, b1.
+template <class T>
+__device__ __forceinline__ void window5(const Blk4<T>& b0, const Blk4<T>& b1, int d, T (&w)[5]) {
+  const T t[8] = {b0.v[0], b0.v[1], b0.v[2], b0.v[3], b1.v[0], b1.v[1], b1.v[2], b1.v[3]};
+#pragma unroll
+  for (int u = 0; u < 5; ++u) w[u] = d == 0 ? t[u] : d == 1 ? t[u + 1] : d == 2 ? t[u + 2] : t[u + 3];
+}
+
+// Mode-id base of spectator tuple q: the tuple's modes are m0 + l * mstride,
+// l = 0..k (the swept index j_d varies, the others are fixed).
+__device__ __forceinline__ int32_t tuple_base(int32_t q, int32_t ms, int O) {
+  return (q % ms) + (q / ms) * ms * O;
 }
 
 template <int K, int TIER, bool MASS>
-__device__ __forceinline__ void contig_tile(const SweepArgs& a, int32_t tile_lines,
-                                            unsigned char* smem) {
+struct Win {               // the 5-cell source window of one tuple
+  Raw<K, TIER, MASS> w[5];
+};
+
+template <int K, int TIER, bool MASS>
+__device__ __forceinline__ void contig_load(const SweepArgs& a, int32_t m0, int64_t lb,
+                                            int32_t blk0, int32_t blk1, int d,
+                                            Win<K, TIER, MASS>& W) {
   constexpr int O = K + 1;
-  constexpr int V = kTileV;
   using T = typename Tier<TIER>::T;
-  using Acc = typename Tier<TIER>::Acc;
-  using R = Raw<K, TIER, MASS>;
-  const int32_t sp = blockIdx.y;
-  const int32_t N = a.N;
-  const int64_t line0 = (int64_t)blockIdx.x * tile_lines;
-  const int32_t nl = (int32_t)min((int64_t)tile_lines, (int64_t)a.Q - line0);
-  const int32_t tc = nl * N;                      // cells in this tile
-  const int32_t cap = tile_lines * N;             // cells per plane slot
-  // LDS layout: A/B per line | s per line | plane 0 (8-byte slots) | planes 1..k
-  double* ab_l = reinterpret_cast<double*>(smem);
-  int32_t* s_l = reinterpret_cast<int32_t*>(ab_l + tile_lines * 2 * O * O);
-  unsigned char* pbase = smem + tile_lines * (2 * O * O * 8 + 4);
-  pbase += (16 - ((uintptr_t)pbase & 15)) & 15;
-  double* p0d = reinterpret_cast<double*>(pbase);
-  T* p0t = reinterpret_cast<T*>(pbase);
-  T* ph[O];
+  const T* hin = reinterpret_cast<const T*>(a.in_hi);
+  if (MASS) {
+    double m[5];
+    window5<double>(load4(a.in_mass + lb + 4 * blk0), load4(a.in_mass + lb + 4 * blk1), d, m);
 #pragma unroll
-  for (int l = 1; l < O; ++l)
-    ph[l] = reinterpret_cast<T*>(pbase + (size_t)cap * 8 + (size_t)(l - 1) * cap * sizeof(T));
-  ph[0] = p0t;
-
-  Planes<K, TIER, MASS> pl;
-  pl.bind(a, (int64_t)sp * O, 1);
-  const int64_t cell0 = line0 * N;
-  // per-line tables
-  for (int32_t q = threadIdx.x; q < nl * 2 * O * O; q += blockDim.x) {
-    const int32_t li = q / (2 * O * O);
-    const int32_t e = q - li * (2 * O * O);
-    const int32_t t = table_index(a.map, 0, (int32_t)(line0 + li));
-    ab_l[q] = a.ab_tab[(int64_t)t * 2 * O * O + e];
-    if (e == 0) s_l[li] = a.s_tab[t];
+    for (int u = 0; u < 5; ++u) W.w[u].m = m[u];
   }
-  // plane segments
-  if (MASS) copy_to_lds(p0d, pl.in_mass + cell0, tc * 8);
 #pragma unroll
-  for (int l = (MASS ? 1 : 0); l < O; ++l)
-    copy_to_lds(ph[l], pl.in[l] + cell0, tc * (int32_t)sizeof(T));
-  __syncthreads();
+  for (int l = (MASS ? 1 : 0); l < O; ++l) {
+    const T* pin = hin + (int64_t)(m0 + l - 1) * a.cells + lb;
+    T h[5];
+    window5<T>(load4(pin + 4 * blk0), load4(pin + 4 * blk1), d, h);
+#pragma unroll
+    for (int u = 0; u < 5; ++u) W.w[u].h[l] = h[u];
+  }
+}
 
-  const int32_t ng = tc / V;
-  for (int32_t g = threadIdx.x; g < ng; g += blockDim.x) {
-    const int32_t c = g * V;
-    const int32_t li = c / N;
-    const int32_t i0 = c - li * N;
-    const int32_t s = s_l[li];
-    Mat<K, TIER, MASS> M;
-    M.load(ab_l + li * 2 * O * O);
-    // window of source cells i0-s-1 .. i0-s+V-1 (periodic in the line)
-    R w[V + 1];
-    int32_t idx = i0 - s - 1;
-    if (idx < 0) idx += N;
-    const int32_t lb = li * N;
+template <int K, int TIER, bool MASS>
+__device__ __forceinline__ void contig_store(const SweepArgs& a, int32_t m0, int64_t c,
+                                             const Mat<K, TIER>& M,
+                                             const Win<K, TIER, MASS>& W) {
+  constexpr int O = K + 1;
+  using T = typename Tier<TIER>::T;
+  T* hout = reinterpret_cast<T*>(a.out_hi);
+  if (MASS) {
+    double o4[4];
 #pragma unroll
-    for (int u = 0; u <= V; ++u) {
-      if (MASS) w[u].m = p0d[lb + idx];
+    for (int u = 0; u < 4; ++u) o4[u] = M.mass_out(W.w[u + 1], W.w[u]);
+    store4<double>(a.out_mass + c, o4);
+  }
 #pragma unroll
-      for (int l = (MASS ? 1 : 0); l < O; ++l) w[u].h[l] = ph[l][lb + idx];
-      if (++idx == N) idx = 0;
-    }
-    const int64_t gc = cell0 + c;
-    if (MASS) {
-      double o4[V];
+  for (int j = (MASS ? 1 : 0); j < O; ++j) {
+    T o4[4];
 #pragma unroll
-      for (int u = 0; u < V; ++u) o4[u] = M.mass_out(w[u + 1], w[u]);
-      store4<double>(pl.out_mass + gc, o4);
-    }
+    for (int u = 0; u < 4; ++u) o4[u] = M.hi_out(j, W.w[u + 1], W.w[u]);
+    store4<T>(hout + (int64_t)(m0 + j - 1) * a.cells + c, o4);
+  }
+}
+
+// One thread: 4 consecutive output cells of one line, for every spectator
+// tuple in turn (the line's s, A and B are loaded once; the loads of the next
+// tuple are issued before the current tuple is computed and stored).
+template <int K, int TIER>
+__global__ __launch_bounds__(256) void sweep_contig_window_kernel(SweepArgs a) {
+  constexpr int O = K + 1;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (a.cells >> 2)) return;
+  const int32_t c = (int32_t)(g << 2);
+  const int32_t N = a.N;
+  const int32_t line = c / N;
+  const int32_t i0 = c - line * N;
+  const int32_t t = table_index(a.map, 0, line);
+  const int32_t s = a.s_tab[t];
+  int32_t w0 = i0 - s - 1;
+  if (w0 < 0) w0 += N;
+  const int32_t nb = N >> 2;
+  const int32_t blk0 = w0 >> 2, d = w0 & 3;
+  const int32_t blk1 = (blk0 + 1 == nb) ? 0 : blk0 + 1;
+  const int64_t lb = (int64_t)line * N;
+  Mat<K, TIER> M;
+  M.load(a.ab_tab + t, a.ab_cs);
+  {
+    Win<K, TIER, true> W;
+    contig_load<K, TIER, true>(a, 0, lb, blk0, blk1, d, W);
+    contig_store<K, TIER, true>(a, 0, c, M, W);
+  }
+  const int32_t nq = a.nspec;
+  if (nq < 2) return;
+  Win<K, TIER, false> cur, nxt;
+  contig_load<K, TIER, false>(a, O, lb, blk0, blk1, d, cur);     // tuple 1: modes O..2O-1
+  for (int32_t q = 1; q < nq; ++q) {
+    if (q + 1 < nq) contig_load<K, TIER, false>(a, (q + 1) * O, lb, blk0, blk1, d, nxt);
+    contig_store<K, TIER, false>(a, q * O, c, M, cur);
+    cur = nxt;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sweep along a dimension d > 0 (strided).  Lanes take consecutive cells of
+// the flattened lower dimensions (contiguous in memory, coalesced in every
+// plane).  A thread produces L consecutive rows i..i+L-1 along d, for every
+// spectator tuple in turn: its L+1 source rows per plane are loaded before
+// any arithmetic, the loads of the next tuple are issued before the current
+// tuple is computed, and the line's s, A and B (which may differ from lane to
+// lane) are loaded once for all tuples.  Concurrent waves work on
+// neighbouring cells of the same rows of the same planes, which keeps the
+// HBM access stream local; the one extra source row per thread is re-read by
+// the neighbouring chunk shortly afterwards and served by the caches.
+// ---------------------------------------------------------------------------
+
+template <int K, int TIER, bool MASS, int L>
+struct Rows {
+  Raw<K, TIER, MASS> v[L + 1];
+};
+
+template <int K, int TIER, bool MASS, int L>
+__device__ __forceinline__ void strided_load(const SweepArgs& a, int32_t m0, int32_t ms,
+                                             int64_t base, const int32_t (&roff)[L + 1],
+                                             int32_t n, Rows<K, TIER, MASS, L>& R) {
+  constexpr int O = K + 1;
+  using T = typename Tier<TIER>::T;
+  const T* hin = reinterpret_cast<const T*>(a.in_hi);
 #pragma unroll
-    for (int j = (MASS ? 1 : 0); j < O; ++j) {
-      T o4[V];
+  for (int u = 0; u <= L; ++u) {
+    if (u <= n) {
+      if (MASS) R.v[u].m = a.in_mass[base + roff[u]];
 #pragma unroll
-      for (int u = 0; u < V; ++u) o4[u] = M.hi_out(j, w[u + 1], w[u]);
-      store4<T>(pl.out[j] + gc, o4);
+      for (int l = (MASS ? 1 : 0); l < O; ++l)
+        R.v[u].h[l] = hin[(int64_t)(m0 + l * ms - 1) * a.cells + base + roff[u]];
     }
   }
 }
 
-template <int K, int TIER>
-__global__ __launch_bounds__(256) void sweep_contig_tiled_kernel(SweepArgs a, int32_t tile_lines) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  if (blockIdx.y == 0) contig_tile<K, TIER, true>(a, tile_lines, smem);
-  else contig_tile<K, TIER, false>(a, tile_lines, smem);
+template <int K, int TIER, bool MASS, int L>
+__device__ __forceinline__ void strided_store(const SweepArgs& a, int32_t m0, int32_t ms,
+                                              int64_t base, int32_t r0, int32_t n,
+                                              const Mat<K, TIER>& M,
+                                              const Rows<K, TIER, MASS, L>& R) {
+  constexpr int O = K + 1;
+  using T = typename Tier<TIER>::T;
+  T* hout = reinterpret_cast<T*>(a.out_hi);
+#pragma unroll
+  for (int u = 0; u < L; ++u) {
+    if (u < n) {
+      const int64_t c = base + (int64_t)(r0 + u) * a.P;
+      if (MASS) a.out_mass[c] = M.mass_out(R.v[u + 1], R.v[u]);
+#pragma unroll
+      for (int j = (MASS ? 1 : 0); j < O; ++j)
+        hout[(int64_t)(m0 + j * ms - 1) * a.cells + c] = M.hi_out(j, R.v[u + 1], R.v[u]);
+    }
+  }
+}
+
+template <int K, int TIER, int L>
+__global__ __launch_bounds__(256) void sweep_strided_kernel(SweepArgs a) {
+  constexpr int O = K + 1;
+  const int64_t per = (int64_t)a.P * a.nchunk * a.Q;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= per) return;
+  const int32_t tt = (int32_t)tid;                 // per < 2^31
+  const int32_t ilow = tt % a.P;
+  const int32_t r = tt / a.P;
+  const int32_t chunk = r % a.nchunk;
+  const int32_t ihigh = r / a.nchunk;
+  const int32_t t = table_index(a.map, ilow, ihigh);
+  const int32_t s = a.s_tab[t];
+  const int32_t N = a.N, P = a.P, ms = a.mstride;
+  const int64_t base = (int64_t)ihigh * P * N + ilow;
+  const int32_t r0 = chunk * L;
+  const int32_t n = min(L, N - r0);
+  int32_t roff[L + 1];
+  int32_t row = r0 - s - 1;
+  if (row < 0) row += N;
+#pragma unroll
+  for (int u = 0; u <= L; ++u) {
+    roff[u] = row * P;
+    if (++row == N) row = 0;
+  }
+  Mat<K, TIER> M;
+  M.load(a.ab_tab + t, a.ab_cs);
+  {
+    Rows<K, TIER, true, L> R;
+    strided_load<K, TIER, true, L>(a, 0, ms, base, roff, n, R);
+    strided_store<K, TIER, true, L>(a, 0, ms, base, r0, n, M, R);
+  }
+  const int32_t nq = a.nspec;
+  if (nq < 2) return;
+  Rows<K, TIER, false, L> cur, nxt;
+  strided_load<K, TIER, false, L>(a, tuple_base(1, ms, O), ms, base, roff, n, cur);
+  for (int32_t q = 1; q < nq; ++q) {
+    if (q + 1 < nq) strided_load<K, TIER, false, L>(a, tuple_base(q + 1, ms, O), ms, base, roff, n, nxt);
+    strided_store<K, TIER, false, L>(a, tuple_base(q, ms, O), ms, base, r0, n, M, cur);
+    cur = nxt;
+  }
+}
+
+bool contig_window_ok(const SweepArgs& a) {
+  const uintptr_t align = (uintptr_t)a.in_mass | (uintptr_t)a.in_hi | (uintptr_t)a.out_mass |
+                          (uintptr_t)a.out_hi;
+  return a.N % 4 == 0 && (align & 15) == 0;
 }
 
 template <int K, int TIER>
 static hipError_t launch_sweep_kt(int dim, const SweepArgs& a, hipStream_t st) {
-  using T = typename Tier<TIER>::T;
-  constexpr int O = K + 1;
   if (dim == 0) {
-    const int64_t lds_per_cell = 8 + (int64_t)(O - 1) * sizeof(T);
-    const int64_t tile_cells = sizeof(T) == 8 ? 1024 : 2048;
-    const uintptr_t align = (uintptr_t)a.in_mass | (uintptr_t)a.in_hi | (uintptr_t)a.out_mass |
-                            (uintptr_t)a.out_hi;
-    if (a.N % 8 == 0 && a.N <= tile_cells && (align & 15) == 0) {
-      const int32_t tl = (int32_t)(tile_cells / a.N);
-      const size_t lds = (size_t)tl * (2 * O * O * 8 + 4) + 16 + (size_t)tl * a.N * lds_per_cell;
-      dim3 grid((unsigned)((a.Q + tl - 1) / tl), (unsigned)a.nspec), block(256);
-      sweep_contig_tiled_kernel<K, TIER><<<grid, block, lds, st>>>(a, tl);
+    if (contig_window_ok(a)) {
+      const int64_t groups = a.cells >> 2;
+      dim3 grid((unsigned)((groups + 255) / 256)), block(256);
+      sweep_contig_window_kernel<K, TIER><<<grid, block, 0, st>>>(a);
     } else {
       const int64_t items = (int64_t)a.Q * a.nspec;
       dim3 grid((unsigned)((items + 3) / 4)), block(256);
@@ -525,8 +584,14 @@ static hipError_t launch_sweep_kt(int dim, const SweepArgs& a, hipStream_t st) {
     }
   } else {
     const int64_t per = (int64_t)a.P * a.nchunk * a.Q;
-    dim3 grid((unsigned)((per + 255) / 256), (unsigned)a.nspec), block(256);
-    sweep_strided_kernel<K, TIER><<<grid, block, 0, st>>>(a);
+    dim3 grid((unsigned)((per + 255) / 256)), block(256);
+    switch (a.chunk) {
+      case 1: sweep_strided_kernel<K, TIER, 1><<<grid, block, 0, st>>>(a); break;
+      case 2: sweep_strided_kernel<K, TIER, 2><<<grid, block, 0, st>>>(a); break;
+      case 4: sweep_strided_kernel<K, TIER, 4><<<grid, block, 0, st>>>(a); break;
+      case 8: sweep_strided_kernel<K, TIER, 8><<<grid, block, 0, st>>>(a); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }

@@ -80,6 +80,12 @@ CASES = [
     ((5, 7, 6), 2, {0: (1, 2), 1: (0, 2), 2: (0,)}),
     ((12, 10, 8, 9), 2, {0: (2,), 1: (3,), 2: (0, 1), 3: (0, 1)}),
     ((6, 4, 5, 3), 1, {0: (2, 3), 1: (), 2: (0, 1, 3), 3: (1,)}),
+    # dimension-0 lengths that take the LDS-tiled kernel (N_0 % 8 == 0)
+    ((16, 6, 5), 2, {0: (1, 2), 1: (0,), 2: (0, 1)}),
+    ((24, 7), 3, {0: (1,), 1: (0,)}),
+    ((8, 6, 4, 5), 2, {0: (2,), 1: (3,), 2: (0, 1), 3: (0, 1)}),
+    ((2048,), 1, {0: ()}),
+    ((4096, 3), 2, {0: (1,), 1: ()}),
 ]
 
 
@@ -287,3 +293,25 @@ def test_split_steps_equals_advect_dim_sequence(sl):
             x, y = y, x
     torch.cuda.synchronize()
     assert np.array_equal(fin, download(*x))
+
+
+@pytest.mark.parametrize("tier", TIERS)
+def test_unaligned_buffers_take_the_generic_path_with_identical_results(sl, tier):
+    import torch
+    ns, k = (48, 10), 2
+    cells = 480
+    state = O.to_tier(inputs.random_coefficients(2, k, cells, seed=21), tier)
+    p = sl.Plan(ns, k, tier)
+    m_in, h_in = upload(state, tier)
+    sig = _dev(np.random.default_rng(4).uniform(-30, 30, 10))
+    m_out, h_out = p.empty_state()
+    p.advect_dim(0, sig, 2, m_in, h_in, m_out, h_out)
+    # the same input, one element into larger buffers: not 16-byte aligned
+    big_h = torch.empty(h_in.numel() + 8, dtype=h_in.dtype, device="cuda")
+    big_h[1:1 + h_in.numel()].copy_(h_in.reshape(-1))
+    h_in_u = big_h[1:1 + h_in.numel()].view(h_in.shape)
+    m_out2, h_out2 = p.empty_state()
+    p.advect_dim(0, sig, 2, m_in, h_in_u, m_out2, h_out2)
+    torch.cuda.synchronize()
+    assert (h_in_u.data_ptr() & 15) != 0
+    assert np.array_equal(download(m_out, h_out), download(m_out2, h_out2))
