@@ -66,20 +66,20 @@ def measured_traffic(kernel):
     return None if ent is None else ent.get("bytes_per_launch")
 
 
-def measured_copy_bandwidth(torch, nbytes, reps=10):
-    """Read+write bandwidth of a plain device copy of `nbytes` (torch's copy
-    kernel), the reference the paper's copy-benchmark column corresponds to."""
+def measured_copy_bandwidth(sl, torch, nbytes, reps=10):
+    """Read+write bandwidth of the library's plain 16-byte-per-thread device
+    copy of `nbytes` (the copy-benchmark reference, cf. the paper's Table I)."""
     n = nbytes // 16
     src = torch.ones(n, 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
-        dst.copy_(src)
+        sl.device_copy(src, dst)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
     for _ in range(reps):
-        dst.copy_(src)
+        sl.device_copy(src, dst)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
@@ -202,7 +202,7 @@ def main():
     mass0, hi0 = inputs.random_coefficients_device(prob.ndim, prob.k, cells, seed=args.seed)
     torch.cuda.synchronize()
 
-    copy_gbs = measured_copy_bandwidth(torch, state_bytes(cells, modes, args.tier))
+    copy_gbs = measured_copy_bandwidth(sl, torch, state_bytes(cells, modes, args.tier))
     log(f"bench: device copy bandwidth {copy_gbs:.0f} GB/s")
     tiers = [args.tier] + [t for t in args.compare.split(",") if t and t != args.tier]
     results = {}

@@ -163,6 +163,16 @@ sldg_status sldg_mass_device(sldg_plan_t plan, const double* mass, double* out_d
 sldg_status sldg_timing_enable(sldg_plan_t plan, int enable);
 sldg_status sldg_timing_read(sldg_plan_t plan, int dim, int64_t* launches, double* total_ms);
 
+/*
+ * Plain device-to-device copy of `bytes` bytes (a multiple of 16, both
+ * pointers 16-byte aligned) with one 16-byte load and store per thread, on
+ * `stream`.  It measures the copy bandwidth the sweeps are compared with (the
+ * paper lists copy-benchmark bandwidths beside the vendor figures, Table I)
+ * and is the known-size kernel that hardware byte counters are scaled by.
+ * Errors: SLDG_ERR_ARG (size or alignment), SLDG_ERR_ALIAS, SLDG_ERR_DEVICE.
+ */
+sldg_status sldg_device_copy(const void* src, void* dst, int64_t bytes, void* stream);
+
 /* Bytes of one state's `hi` array for this plan, (o^ndim - 1) * cells * sizeof(T). */
 int64_t sldg_hi_bytes(sldg_plan_t plan);
 

@@ -19,7 +19,7 @@ TIER_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}
 EXPORTS = ("sldg_plan", "sldg_plan_destroy", "sldg_plan_set_stream", "sldg_line_tables",
            "sldg_advect_dim", "sldg_split_steps", "sldg_mass", "sldg_hi_bytes",
            "sldg_status_string", "sldg_last_error", "sldg_timing_enable", "sldg_timing_read",
-           "sldg_mass_device")
+           "sldg_mass_device", "sldg_device_copy")
 
 
 class SldgError(RuntimeError):
@@ -61,6 +61,8 @@ def lib():
     L.sldg_mass.restype = i32
     L.sldg_hi_bytes.argtypes = [vp]
     L.sldg_hi_bytes.restype = i64
+    L.sldg_device_copy.argtypes = [vp, vp, i64, vp]
+    L.sldg_device_copy.restype = i32
     L.sldg_mass_device.argtypes = [vp, vp, vp]
     L.sldg_mass_device.restype = i32
     L.sldg_timing_enable.argtypes = [vp, i32]
@@ -262,6 +264,18 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def device_copy(src, dst, nbytes=None, stream=None):
+    """Plain device copy of nbytes (sldg_device_copy): the reference bandwidth."""
+    nbytes = src.numel() * src.element_size() if nbytes is None else int(nbytes)
+    if nbytes > src.numel() * src.element_size() or nbytes > dst.numel() * dst.element_size():
+        raise ValueError("copy larger than the buffers")
+    if not (src.is_cuda and dst.is_cuda):
+        raise ValueError("device_copy needs device tensors")
+    stream = _current_stream() if stream is None else stream
+    _check(lib().sldg_device_copy(_ptr(src), _ptr(dst), nbytes, ctypes.c_void_p(stream)),
+           "sldg_device_copy")
 
 
 # Function names of the C ABI, for callers that prefer them.

@@ -33,6 +33,7 @@ struct sldg_plan_s {
   double* d_mass_out;     // [2]
   double* h_mass_out;     // pinned [2]
   int rows_per_thread;    // strided sweep: rows per thread (1, 2, 4 or 8)
+  int tuples_per_thread;  // spectator tuples per thread (0: all)
   // kernel timing (sldg_timing_*)
   bool timing;
   int ntimed;
@@ -128,13 +129,13 @@ void describe(const sldg_plan_s* p, int dim, uint32_t dep_mask, SweepArgs& a, in
     const bool below = e < dim;
     if (dep_mask & (1u << e)) {
       if (below) {
-        m.lo_div[m.nlo] = (int32_t)div_lo;
-        m.lo_mod[m.nlo] = (int32_t)p->n[e];
+        m.lo_div[m.nlo] = FastDiv::make((uint32_t)div_lo);
+        m.lo_mod[m.nlo] = FastDiv::make((uint32_t)p->n[e]);
         m.lo_str[m.nlo] = (int32_t)str;
         ++m.nlo;
       } else {
-        m.hi_div[m.nhi] = (int32_t)div_hi;
-        m.hi_mod[m.nhi] = (int32_t)p->n[e];
+        m.hi_div[m.nhi] = FastDiv::make((uint32_t)div_hi);
+        m.hi_mod[m.nhi] = FastDiv::make((uint32_t)p->n[e]);
         m.hi_str[m.nhi] = (int32_t)str;
         ++m.nhi;
       }
@@ -145,6 +146,8 @@ void describe(const sldg_plan_s* p, int dim, uint32_t dep_mask, SweepArgs& a, in
   }
   a.map = m;
   ntab = str;
+  a.tuples = (p->tuples_per_thread > 0 && p->tuples_per_thread < a.nspec) ? p->tuples_per_thread
+                                                                          : a.nspec;
   // strided sweep: rows per thread (one-shot chunks along the swept dim)
   if (dim > 0) {
     int rows = p->rows_per_thread;
@@ -155,6 +158,9 @@ void describe(const sldg_plan_s* p, int dim, uint32_t dep_mask, SweepArgs& a, in
     a.chunk = a.N;
     a.nchunk = 1;
   }
+  a.fP = FastDiv::make((uint32_t)a.P);
+  a.fN = FastDiv::make((uint32_t)a.N);
+  a.fchunk = FastDiv::make((uint32_t)a.nchunk);
 }
 
 sldg_status device_error(hipError_t e, const char* what) {
@@ -265,6 +271,11 @@ sldg_status sldg_plan(sldg_plan_t* out, int ndim, const int64_t* ncells, int k, 
   p->hi_bytes = (p->modes - 1) * cells * elem_size(tier);
   p->table_cap = cells / min_n;     // the most lines any sweep can have
   p->rows_per_thread = 2;
+  p->tuples_per_thread = 0;
+  if (const char* env = getenv("SLDG_TUPLES")) {
+    const int g = atoi(env);
+    if (g >= 0) p->tuples_per_thread = g;
+  }
   if (const char* env = getenv("SLDG_STRIDED_ROWS")) {
     const int r = atoi(env);
     if (r == 1 || r == 2 || r == 4 || r == 8) p->rows_per_thread = r;
@@ -382,6 +393,16 @@ sldg_status sldg_split_steps(sldg_plan_t p, const sldg_sweep_desc* seq, int nseq
     }
   }
   if (result_buffer) *result_buffer = cur;
+  return ok();
+}
+
+sldg_status sldg_device_copy(const void* src, void* dst, int64_t bytes, void* stream) {
+  if (!src || !dst) return fail(SLDG_ERR_ARG, "null pointer");
+  if (bytes < 0 || (bytes & 15) || (((uintptr_t)src | (uintptr_t)dst) & 15))
+    return fail(SLDG_ERR_ARG, "copy needs a multiple of 16 bytes and 16-byte aligned pointers");
+  if (overlap(src, bytes, dst, bytes)) return fail(SLDG_ERR_ALIAS, "copy buffers overlap");
+  hipError_t e = launch_copy16(src, dst, bytes / 16, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_error(e, "copy launch");
   return ok();
 }
 

@@ -8,6 +8,28 @@ namespace sldg {
 
 constexpr int kMaxDim = 6;
 
+// Division by a runtime-invariant divisor d >= 1 by multiply and shift
+// (T. Granlund, P. Montgomery, "Division by invariant integers using
+// multiplication", 1994): with l = ceil(log2 d) and
+// m = floor(2^32 (2^l - d) / d) + 1, floor(n / d) = (mulhi(n, m) + n) >> l for
+// every 0 <= n < 2^31.
+struct FastDiv {
+  uint32_t d, m, l;
+  static FastDiv make(uint32_t d) {
+    FastDiv f;
+    f.d = d;
+    uint32_t l = 0;
+    while (l < 32 && (1ull << l) < d) ++l;
+    f.l = l;
+    f.m = (uint32_t)((((1ull << 32) * ((1ull << l) - d)) / d) + 1);
+    return f;
+  }
+  __host__ __device__ __forceinline__ uint32_t div(uint32_t n) const {
+    return ((uint32_t)(((uint64_t)n * m) >> 32) + n) >> l;   // mulhi: v_mul_hi_u32
+  }
+  __host__ __device__ __forceinline__ uint32_t mod(uint32_t n) const { return n - div(n) * d; }
+};
+
 // Maps a line (a fixed transverse cell) to its entry in the per-line table.
 // The table is indexed over the dimensions the displacement depends on,
 // lowest dimension fastest.  A line is identified by two flattened indices:
@@ -16,8 +38,10 @@ constexpr int kMaxDim = 6;
 // idx is lo or hi depending on the side of e.
 struct LineMap {
   int nlo, nhi;
-  int32_t lo_div[kMaxDim], lo_mod[kMaxDim], lo_str[kMaxDim];
-  int32_t hi_div[kMaxDim], hi_mod[kMaxDim], hi_str[kMaxDim];
+  FastDiv lo_div[kMaxDim], lo_mod[kMaxDim];
+  int32_t lo_str[kMaxDim];
+  FastDiv hi_div[kMaxDim], hi_mod[kMaxDim];
+  int32_t hi_str[kMaxDim];
 };
 
 struct SweepArgs {
@@ -37,6 +61,10 @@ struct SweepArgs {
   int32_t nspec;          // (k+1)^(ndim-1) spectator mode tuples
   int32_t nchunk;         // strided sweep: chunks along the swept dim
   int32_t chunk;          // strided sweep: rows per thread (1, 2, 4 or 8)
+  int32_t tuples;         // spectator tuples per thread (a run; blockIdx.y picks it)
+  FastDiv fP;             // division by P
+  FastDiv fN;             // division by N
+  FastDiv fchunk;         // division by nchunk
   LineMap map;
 };
 
@@ -47,6 +75,8 @@ hipError_t launch_line_tables(int k, int64_t n, int64_t period, const double* si
 hipError_t launch_sweep(int k, int tier, int dim, const SweepArgs& a, hipStream_t st);
 hipError_t launch_mass(const double* mass, int64_t n, double* partial, int nblocks,
                        double* result, hipStream_t st);
+
+hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t st);
 
 int mass_blocks(int64_t n);
 

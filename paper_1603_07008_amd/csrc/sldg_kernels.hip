@@ -149,8 +149,10 @@ hipError_t launch_line_tables(int k, int64_t n, int64_t period, const double* si
 
 __device__ __forceinline__ int32_t table_index(const LineMap& m, int32_t lo, int32_t hi) {
   int32_t t = 0;
-  for (int e = 0; e < m.nlo; ++e) t += ((lo / m.lo_div[e]) % m.lo_mod[e]) * m.lo_str[e];
-  for (int e = 0; e < m.nhi; ++e) t += ((hi / m.hi_div[e]) % m.hi_mod[e]) * m.hi_str[e];
+  for (int e = 0; e < m.nlo; ++e)
+    t += (int32_t)m.lo_mod[e].mod(m.lo_div[e].div((uint32_t)lo)) * m.lo_str[e];
+  for (int e = 0; e < m.nhi; ++e)
+    t += (int32_t)m.hi_mod[e].mod(m.hi_div[e].div((uint32_t)hi)) * m.hi_str[e];
   return t;
 }
 
@@ -176,22 +178,22 @@ struct Mat {
   double Ad[O], Bd[O];         // mass row in FP64 (used by the tuple holding mode 0)
   Acc Aa[O][O], Ba[O][O];      // all rows in the arithmetic type
 
-  // Matrices of table entry ab (component e at ab[e * cs]).
-  __device__ __forceinline__ void load(const double* ab, int64_t cs) {
-    double a[O][O], b[O][O];
+  // Matrices of table entry ab (component e at ab[e * cs]); the FP64 mass row
+  // only when the thread handles the tuple that holds mode 0.
+  __device__ __forceinline__ void load(const double* ab, int64_t cs, bool mass_row) {
 #pragma unroll
     for (int j = 0; j < O; ++j)
 #pragma unroll
       for (int l = 0; l < O; ++l) {
-        a[j][l] = ab[(j * O + l) * cs];
-        b[j][l] = ab[(O * O + j * O + l) * cs];
-        Aa[j][l] = (Acc)a[j][l];
-        Ba[j][l] = (Acc)b[j][l];
+        Aa[j][l] = (Acc)ab[(j * O + l) * cs];
+        Ba[j][l] = (Acc)ab[(O * O + j * O + l) * cs];
       }
+    if (mass_row) {
 #pragma unroll
-    for (int l = 0; l < O; ++l) {
-      Ad[l] = a[0][l];
-      Bd[l] = b[0][l];
+      for (int l = 0; l < O; ++l) {
+        Ad[l] = ab[l * cs];
+        Bd[l] = ab[(O * O + l) * cs];
+      }
     }
   }
 
@@ -281,7 +283,7 @@ __device__ __forceinline__ void contig_line(const SweepArgs& a, int64_t line, in
   Planes<K, TIER, MASS> pl;
   const int32_t t = __builtin_amdgcn_readfirstlane(table_index(a.map, 0, (int32_t)line));
   const int32_t s = __builtin_amdgcn_readfirstlane(a.s_tab[t]);
-  M.load(a.ab_tab + t, a.ab_cs);
+  M.load(a.ab_tab + t, a.ab_cs, sp == 0);
   pl.bind(a, (int64_t)sp * O, 1);
   const int32_t N = a.N;
   const int64_t base = line * (int64_t)N;
@@ -363,18 +365,18 @@ __device__ __forceinline__ void store4(T* dst, const T (&v)[4]) {
   }
 }
 
-// The 5-cell window starting at offset d (0..3) of the 8 cells of blocks b0, b1.
+// The 5-cell window starting at offset d (0..3) of the 8 cells of blocks b0,
+// b1, as two branch-free shifts (by d & 1, then by d & 2): 12 selects, no
+// divergent control flow.
 template <class T>
 __device__ __forceinline__ void window5(const Blk4<T>& b0, const Blk4<T>& b1, int d, T (&w)[5]) {
   const T t[8] = {b0.v[0], b0.v[1], b0.v[2], b0.v[3], b1.v[0], b1.v[1], b1.v[2], b1.v[3]};
+  const bool s1 = (d & 1) != 0, s2 = (d & 2) != 0;
+  T u1[7];
 #pragma unroll
-  for (int u = 0; u < 5; ++u) w[u] = d == 0 ? t[u] : d == 1 ? t[u + 1] : d == 2 ? t[u + 2] : t[u + 3];
-}
-
-// Mode-id base of spectator tuple q: the tuple's modes are m0 + l * mstride,
-// l = 0..k (the swept index j_d varies, the others are fixed).
-__device__ __forceinline__ int32_t tuple_base(int32_t q, int32_t ms, int O) {
-  return (q % ms) + (q / ms) * ms * O;
+  for (int i = 0; i < 7; ++i) u1[i] = s1 ? t[i + 1] : t[i];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) w[i] = s2 ? u1[i + 2] : u1[i];
 }
 
 template <int K, int TIER, bool MASS>
@@ -427,19 +429,18 @@ __device__ __forceinline__ void contig_store(const SweepArgs& a, int32_t m0, int
   }
 }
 
-// One thread: 4 consecutive output cells of one line, for every spectator
-// tuple in turn (the line's s, A and B are loaded once; the loads of the next
-// tuple are issued before the current tuple is computed and stored).
+// One thread: 4 consecutive output cells of one line, for a run of
+// `tuples` spectator tuples in turn (the line's s, A and B are loaded once;
+// the loads of the next tuple are issued before the current tuple is computed
+// and stored).  blockIdx.y selects the run of tuples.  When every lane of the
+// wave works on lines that share one table entry (the common case: the
+// displacement of a dimension-0 sweep rarely depends on dimension 1), the
+// entry is read with scalar loads and the matrices live in scalar registers.
 template <int K, int TIER>
-__global__ __launch_bounds__(256) void sweep_contig_window_kernel(SweepArgs a) {
+__device__ __forceinline__ void contig_body(const SweepArgs& a, int32_t c, int32_t line,
+                                            int32_t i0, int32_t t) {
   constexpr int O = K + 1;
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= (a.cells >> 2)) return;
-  const int32_t c = (int32_t)(g << 2);
   const int32_t N = a.N;
-  const int32_t line = c / N;
-  const int32_t i0 = c - line * N;
-  const int32_t t = table_index(a.map, 0, line);
   const int32_t s = a.s_tab[t];
   int32_t w0 = i0 - s - 1;
   if (w0 < 0) w0 += N;
@@ -447,29 +448,44 @@ __global__ __launch_bounds__(256) void sweep_contig_window_kernel(SweepArgs a) {
   const int32_t blk0 = w0 >> 2, d = w0 & 3;
   const int32_t blk1 = (blk0 + 1 == nb) ? 0 : blk0 + 1;
   const int64_t lb = (int64_t)line * N;
+  int32_t q = blockIdx.y * a.tuples;
+  const int32_t qe = min(a.nspec, q + a.tuples);
   Mat<K, TIER> M;
-  M.load(a.ab_tab + t, a.ab_cs);
-  {
+  M.load(a.ab_tab + t, a.ab_cs, q == 0);
+  if (q == 0) {
     Win<K, TIER, true> W;
     contig_load<K, TIER, true>(a, 0, lb, blk0, blk1, d, W);
     contig_store<K, TIER, true>(a, 0, c, M, W);
+    ++q;
   }
-  const int32_t nq = a.nspec;
-  if (nq < 2) return;
+  if (q >= qe) return;
   Win<K, TIER, false> cur, nxt;
-  contig_load<K, TIER, false>(a, O, lb, blk0, blk1, d, cur);     // tuple 1: modes O..2O-1
-  for (int32_t q = 1; q < nq; ++q) {
-    if (q + 1 < nq) contig_load<K, TIER, false>(a, (q + 1) * O, lb, blk0, blk1, d, nxt);
+  contig_load<K, TIER, false>(a, q * O, lb, blk0, blk1, d, cur);
+  for (; q < qe; ++q) {
+    if (q + 1 < qe) contig_load<K, TIER, false>(a, (q + 1) * O, lb, blk0, blk1, d, nxt);
     contig_store<K, TIER, false>(a, q * O, c, M, cur);
     cur = nxt;
   }
 }
 
+template <int K, int TIER>
+__global__ __launch_bounds__(256) void sweep_contig_window_kernel(SweepArgs a) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (a.cells >> 2)) return;
+  const int32_t c = (int32_t)(g << 2);
+  const int32_t line = (int32_t)a.fN.div((uint32_t)c);
+  const int32_t i0 = c - line * a.N;
+  const int32_t t = table_index(a.map, 0, line);
+  const int32_t t0 = __builtin_amdgcn_readfirstlane(t);
+  if (__all(t == t0)) contig_body<K, TIER>(a, c, line, i0, t0);
+  else contig_body<K, TIER>(a, c, line, i0, t);
+}
+
 // ---------------------------------------------------------------------------
 // Sweep along a dimension d > 0 (strided).  Lanes take consecutive cells of
 // the flattened lower dimensions (contiguous in memory, coalesced in every
-// plane).  A thread produces L consecutive rows i..i+L-1 along d, for every
-// spectator tuple in turn: its L+1 source rows per plane are loaded before
+// plane).  A thread produces L consecutive rows i..i+L-1 along d, for a run of
+// spectator tuples (blockIdx.y selects the run) in turn: its L+1 source rows per plane are loaded before
 // any arithmetic, the loads of the next tuple are issued before the current
 // tuple is computed, and the line's s, A and B (which may differ from lane to
 // lane) are loaded once for all tuples.  Concurrent waves work on
@@ -490,14 +506,13 @@ __device__ __forceinline__ void strided_load(const SweepArgs& a, int32_t m0, int
   constexpr int O = K + 1;
   using T = typename Tier<TIER>::T;
   const T* hin = reinterpret_cast<const T*>(a.in_hi);
+  (void)n;   // all L+1 rows are loaded (row offsets wrap), only the stores are cut
 #pragma unroll
   for (int u = 0; u <= L; ++u) {
-    if (u <= n) {
-      if (MASS) R.v[u].m = a.in_mass[base + roff[u]];
+    if (MASS) R.v[u].m = a.in_mass[base + roff[u]];
 #pragma unroll
-      for (int l = (MASS ? 1 : 0); l < O; ++l)
-        R.v[u].h[l] = hin[(int64_t)(m0 + l * ms - 1) * a.cells + base + roff[u]];
-    }
+    for (int l = (MASS ? 1 : 0); l < O; ++l)
+      R.v[u].h[l] = hin[(int64_t)(m0 + l * ms - 1) * a.cells + base + roff[u]];
   }
 }
 
@@ -509,9 +524,17 @@ __device__ __forceinline__ void strided_store(const SweepArgs& a, int32_t m0, in
   constexpr int O = K + 1;
   using T = typename Tier<TIER>::T;
   T* hout = reinterpret_cast<T*>(a.out_hi);
+  if (n == L) {            // full chunk: no per-row predicate
 #pragma unroll
-  for (int u = 0; u < L; ++u) {
-    if (u < n) {
+    for (int u = 0; u < L; ++u) {
+      const int64_t c = base + (int64_t)(r0 + u) * a.P;
+      if (MASS) a.out_mass[c] = M.mass_out(R.v[u + 1], R.v[u]);
+#pragma unroll
+      for (int j = (MASS ? 1 : 0); j < O; ++j)
+        hout[(int64_t)(m0 + j * ms - 1) * a.cells + c] = M.hi_out(j, R.v[u + 1], R.v[u]);
+    }
+  } else {                 // the last chunk of a line whose length L does not divide
+    for (int u = 0; u < n; ++u) {
       const int64_t c = base + (int64_t)(r0 + u) * a.P;
       if (MASS) a.out_mass[c] = M.mass_out(R.v[u + 1], R.v[u]);
 #pragma unroll
@@ -522,17 +545,9 @@ __device__ __forceinline__ void strided_store(const SweepArgs& a, int32_t m0, in
 }
 
 template <int K, int TIER, int L>
-__global__ __launch_bounds__(256) void sweep_strided_kernel(SweepArgs a) {
+__device__ __forceinline__ void strided_body(const SweepArgs& a, int32_t ilow, int32_t chunk,
+                                             int32_t ihigh, int32_t t) {
   constexpr int O = K + 1;
-  const int64_t per = (int64_t)a.P * a.nchunk * a.Q;
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= per) return;
-  const int32_t tt = (int32_t)tid;                 // per < 2^31
-  const int32_t ilow = tt % a.P;
-  const int32_t r = tt / a.P;
-  const int32_t chunk = r % a.nchunk;
-  const int32_t ihigh = r / a.nchunk;
-  const int32_t t = table_index(a.map, ilow, ihigh);
   const int32_t s = a.s_tab[t];
   const int32_t N = a.N, P = a.P, ms = a.mstride;
   const int64_t base = (int64_t)ihigh * P * N + ilow;
@@ -546,22 +561,58 @@ __global__ __launch_bounds__(256) void sweep_strided_kernel(SweepArgs a) {
     roff[u] = row * P;
     if (++row == N) row = 0;
   }
+  int32_t q = blockIdx.y * a.tuples;
+  const int32_t qe = min(a.nspec, q + a.tuples);
   Mat<K, TIER> M;
-  M.load(a.ab_tab + t, a.ab_cs);
-  {
+  M.load(a.ab_tab + t, a.ab_cs, q == 0);
+  if (q == 0) {
     Rows<K, TIER, true, L> R;
     strided_load<K, TIER, true, L>(a, 0, ms, base, roff, n, R);
     strided_store<K, TIER, true, L>(a, 0, ms, base, r0, n, M, R);
+    ++q;
   }
-  const int32_t nq = a.nspec;
-  if (nq < 2) return;
+  if (q >= qe) return;
+  // mode base of tuple q, stepped without division: the low part (dims below
+  // d) counts to ms, then the base jumps over the swept index's o-1 planes
+  int32_t low = q % ms;
+  int32_t m0 = low + (q / ms) * ms * O;
+  int32_t low1 = low + 1, m1 = m0 + 1;
+  if (low1 == ms) {
+    low1 = 0;
+    m1 = m0 + 1 + ms * (O - 1);
+  }
   Rows<K, TIER, false, L> cur, nxt;
-  strided_load<K, TIER, false, L>(a, tuple_base(1, ms, O), ms, base, roff, n, cur);
-  for (int32_t q = 1; q < nq; ++q) {
-    if (q + 1 < nq) strided_load<K, TIER, false, L>(a, tuple_base(q + 1, ms, O), ms, base, roff, n, nxt);
-    strided_store<K, TIER, false, L>(a, tuple_base(q, ms, O), ms, base, r0, n, M, cur);
+  strided_load<K, TIER, false, L>(a, m0, ms, base, roff, n, cur);
+  for (; q < qe; ++q) {
+    if (q + 1 < qe) strided_load<K, TIER, false, L>(a, m1, ms, base, roff, n, nxt);
+    strided_store<K, TIER, false, L>(a, m0, ms, base, r0, n, M, cur);
     cur = nxt;
+    m0 = m1;
+    low = low1;
+    ++low1;
+    ++m1;
+    if (low1 == ms) {
+      low1 = 0;
+      m1 += ms * (O - 1);
+    }
   }
+}
+
+template <int K, int TIER, int L>
+__global__ __launch_bounds__(256) void sweep_strided_kernel(SweepArgs a) {
+  const int64_t per = (int64_t)a.P * a.nchunk * a.Q;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= per) return;
+  const uint32_t tt = (uint32_t)tid;                 // per < 2^31
+  const uint32_t r = a.fP.div(tt);
+  const int32_t ilow = (int32_t)(tt - r * (uint32_t)a.P);
+  const uint32_t ih = a.fchunk.div(r);
+  const int32_t chunk = (int32_t)(r - ih * (uint32_t)a.nchunk);
+  const int32_t ihigh = (int32_t)ih;
+  const int32_t t = table_index(a.map, ilow, ihigh);
+  const int32_t t0 = __builtin_amdgcn_readfirstlane(t);
+  if (__all(t == t0)) strided_body<K, TIER, L>(a, ilow, chunk, ihigh, t0);
+  else strided_body<K, TIER, L>(a, ilow, chunk, ihigh, t);
 }
 
 bool contig_window_ok(const SweepArgs& a) {
@@ -575,7 +626,8 @@ static hipError_t launch_sweep_kt(int dim, const SweepArgs& a, hipStream_t st) {
   if (dim == 0) {
     if (contig_window_ok(a)) {
       const int64_t groups = a.cells >> 2;
-      dim3 grid((unsigned)((groups + 255) / 256)), block(256);
+      dim3 grid((unsigned)((groups + 255) / 256), (unsigned)((a.nspec + a.tuples - 1) / a.tuples)),
+          block(256);
       sweep_contig_window_kernel<K, TIER><<<grid, block, 0, st>>>(a);
     } else {
       const int64_t items = (int64_t)a.Q * a.nspec;
@@ -584,7 +636,8 @@ static hipError_t launch_sweep_kt(int dim, const SweepArgs& a, hipStream_t st) {
     }
   } else {
     const int64_t per = (int64_t)a.P * a.nchunk * a.Q;
-    dim3 grid((unsigned)((per + 255) / 256)), block(256);
+    dim3 grid((unsigned)((per + 255) / 256), (unsigned)((a.nspec + a.tuples - 1) / a.tuples)),
+        block(256);
     switch (a.chunk) {
       case 1: sweep_strided_kernel<K, TIER, 1><<<grid, block, 0, st>>>(a); break;
       case 2: sweep_strided_kernel<K, TIER, 2><<<grid, block, 0, st>>>(a); break;
@@ -614,6 +667,25 @@ hipError_t launch_sweep(int k, int tier, int dim, const SweepArgs& a, hipStream_
     case 3: return launch_sweep_k<3>(tier, dim, a, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Plain copy (reference bandwidth): one 16-byte load and store per thread.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void copy16_kernel(const uint4* __restrict__ src,
+                                                     uint4* __restrict__ dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t st) {
+  if (n16 <= 0) return hipSuccess;
+  const int64_t blocks = (n16 + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  copy16_kernel<<<(unsigned)blocks, 256, 0, st>>>(static_cast<const uint4*>(src),
+                                                  static_cast<uint4*>(dst), n16);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -65,6 +65,16 @@ def test_calls_on_a_null_plan(L):
     assert L.sldg_split_steps(None, None, 0, 0, None, None, None, None, None) == sl.SLDG_ERR_ARG
     assert L.sldg_line_tables(None, 0, 1, None, None, None) == sl.SLDG_ERR_ARG
     assert L.sldg_plan_set_stream(None, None) == sl.SLDG_ERR_ARG
+    assert L.sldg_timing_enable(None, 1) == sl.SLDG_ERR_ARG
+    assert L.sldg_mass_device(None, None, None) == sl.SLDG_ERR_ARG
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    assert L.sldg_timing_read(None, 0, ctypes.byref(n), ctypes.byref(ms)) == sl.SLDG_ERR_ARG
+    # copy: argument checks happen before any device call
+    assert L.sldg_device_copy(None, None, 16, None) == sl.SLDG_ERR_ARG
+    assert L.sldg_device_copy(16, 64, 15, None) == sl.SLDG_ERR_ARG
+    assert L.sldg_device_copy(16, 40, 16, None) == sl.SLDG_ERR_ARG
+    assert L.sldg_device_copy(16, 32, 32, None) == sl.SLDG_ERR_ALIAS
     assert L.sldg_hi_bytes(None) == -1
     L.sldg_plan_destroy(None)
 

@@ -315,3 +315,27 @@ def test_unaligned_buffers_take_the_generic_path_with_identical_results(sl, tier
     torch.cuda.synchronize()
     assert (h_in_u.data_ptr() & 15) != 0
     assert np.array_equal(download(m_out, h_out), download(m_out2, h_out2))
+
+
+def test_device_copy_and_kernel_timing(sl):
+    import torch
+    src = torch.arange(4096 * 4, dtype=torch.float32, device="cuda")
+    dst = torch.zeros_like(src)
+    sl.device_copy(src, dst)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+    with pytest.raises(sl.SldgError):
+        sl.device_copy(src[1:], dst[1:], 16 * 100)      # misaligned
+    # timing records one pair of events per sweep kernel launch
+    prob = inputs.vlasov_2d(nx=32, nv=24, steps=2)
+    p = sl.Plan(prob.ns, prob.k, "fp32")
+    a = upload(O.to_tier(inputs.random_coefficients(2, 2, 32 * 24, seed=2), "fp32"), "fp32")
+    b = p.empty_state()
+    seq = [(sw.dim, sw.dep_mask, _dev(sw.sigma)) for sw in prob.seq]
+    p.timing_enable(True)
+    p.split_steps(seq, prob.steps, a, b)
+    n0, ms0 = p.timing_read(-1)
+    n1, ms1 = p.timing_read(-2)
+    nd1, _ = p.timing_read(1)
+    assert (n0, n1, nd1) == (4, 2, 2) and ms0 > 0 and ms1 > 0
+    p.timing_enable(False)
