@@ -210,6 +210,8 @@ sldg_status run_sweep(sldg_plan_s* p, int dim, const double* shift, uint32_t dep
     if (e != hipSuccess) return device_error(e, "hipEventRecord");
   }
   e = launch_sweep(p->k, (int)p->tier, dim, a, p->stream);
+  if (e == hipErrorInvalidConfiguration)
+    return fail(SLDG_ERR_UNSUPPORTED, "sweep along dim %d: grid too large for one launch", dim);
   if (e != hipSuccess) return device_error(e, "sweep launch");
   if (timed) {
     const int i = p->ntimed;

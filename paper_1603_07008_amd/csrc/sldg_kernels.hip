@@ -598,16 +598,20 @@ __device__ __forceinline__ void strided_body(const SweepArgs& a, int32_t ilow, i
   }
 }
 
+// Work decomposition: a wave takes 64 consecutive columns (column =
+// ihigh * P + ilow, i.e. a cell of the transverse dimensions, consecutive
+// columns contiguous in memory), the waves of a workgroup take consecutive
+// row chunks of the same columns.  The halo row a wave loads is the last row
+// its neighbour wave loads, so it is served by the CU's caches, and the
+// waves share the columns' s, A, B in L1.
 template <int K, int TIER, int L>
 __global__ __launch_bounds__(256) void sweep_strided_kernel(SweepArgs a) {
-  const int64_t per = (int64_t)a.P * a.nchunk * a.Q;
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= per) return;
-  const uint32_t tt = (uint32_t)tid;                 // per < 2^31
-  const uint32_t r = a.fP.div(tt);
-  const int32_t ilow = (int32_t)(tt - r * (uint32_t)a.P);
-  const uint32_t ih = a.fchunk.div(r);
-  const int32_t chunk = (int32_t)(r - ih * (uint32_t)a.nchunk);
+  const int32_t ncol = a.P * a.Q;
+  const int32_t col = (int32_t)blockIdx.x * 64 + (int32_t)(threadIdx.x & 63);
+  const int32_t chunk = (int32_t)blockIdx.z * (int32_t)(blockDim.x >> 6) + (int32_t)(threadIdx.x >> 6);
+  if (col >= ncol || chunk >= a.nchunk) return;
+  const uint32_t ih = a.fP.div((uint32_t)col);
+  const int32_t ilow = col - (int32_t)ih * a.P;
   const int32_t ihigh = (int32_t)ih;
   const int32_t t = table_index(a.map, ilow, ihigh);
   const int32_t t0 = __builtin_amdgcn_readfirstlane(t);
@@ -635,9 +639,13 @@ static hipError_t launch_sweep_kt(int dim, const SweepArgs& a, hipStream_t st) {
       sweep_contig_kernel<K, TIER><<<grid, block, 0, st>>>(a);
     }
   } else {
-    const int64_t per = (int64_t)a.P * a.nchunk * a.Q;
-    dim3 grid((unsigned)((per + 255) / 256), (unsigned)((a.nspec + a.tuples - 1) / a.tuples)),
-        block(256);
+    const int64_t ncol = (int64_t)a.P * a.Q;
+    const int waves = a.nchunk < 4 ? a.nchunk : 4;     // row chunks per workgroup
+    if ((a.nchunk + waves - 1) / waves > 65535 || (ncol + 63) / 64 > 0x7fffffff)
+      return hipErrorInvalidConfiguration;
+    dim3 grid((unsigned)((ncol + 63) / 64), (unsigned)((a.nspec + a.tuples - 1) / a.tuples),
+              (unsigned)((a.nchunk + waves - 1) / waves)),
+        block(64 * waves);
     switch (a.chunk) {
       case 1: sweep_strided_kernel<K, TIER, 1><<<grid, block, 0, st>>>(a); break;
       case 2: sweep_strided_kernel<K, TIER, 2><<<grid, block, 0, st>>>(a); break;
