@@ -115,6 +115,19 @@ sldg_status sldg_advect_dim(sldg_plan_t plan, int dim, const double* shift,
                             uint32_t dep_mask, const double* in_mass,
                             const void* in_hi, double* out_mass, void* out_hi);
 
+/*
+ * The transpose of sldg_advect_dim with the same displacements: for every
+ * line, g_in[m] = A(alpha)^T g[m + s] + B(alpha)^T g[m + s + 1], i.e. the
+ * adjoint of the projection sweep with respect to the Euclidean inner product
+ * of the coefficient arrays (the gradient of a loss of the output with respect
+ * to the input, for reverse-mode differentiation through split steps,
+ * section II).  Same arguments, layout, storage tier and error behaviour as
+ * sldg_advect_dim; in/out are the output-side and input-side gradients.
+ */
+sldg_status sldg_advect_dim_adjoint(sldg_plan_t plan, int dim, const double* shift,
+                                    uint32_t dep_mask, const double* in_mass,
+                                    const void* in_hi, double* out_mass, void* out_hi);
+
 /* One sweep of a split step: dimension, dependence mask, device displacements. */
 typedef struct {
     int dim;

@@ -59,6 +59,11 @@ def _load():
             ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+        lib.oracle_sweep_adjoint.restype = None
+        lib.oracle_sweep_adjoint.argtypes = [
+            ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+            ctypes.c_void_p, ctypes.c_void_p]
         lib.oracle_round_tier.restype = ctypes.c_double
         lib.oracle_round_tier.argtypes = [ctypes.c_double, ctypes.c_int]
         lib.oracle_round_array.restype = None
@@ -253,6 +258,39 @@ def sweep(state, ns, k, dim, sigma, dep=(), tier="fp64", sel=None, absolute=Fals
                          s_tab.ctypes.data, ab_tab.ctypes.data, TIERS[tier],
                          state.ctypes.data, out.ctypes.data, nsel, selp)
     return out
+
+
+def sweep_adjoint(grad, ns, k, dim, sigma, dep=()):
+    """Transpose of `sweep` (FP64, no rounding) with the same displacements:
+    the gradient with respect to the sweep's input of a function of its
+    output, given the gradient with respect to the output."""
+    ns = [int(v) for v in ns]
+    ndim = len(ns)
+    if dim in dep:
+        raise ValueError("the displacement of a sweep cannot depend on the swept dimension")
+    grad = np.ascontiguousarray(grad, dtype=np.float64)
+    M, C = n_modes(ndim, k), n_cells(ns)
+    if grad.shape != (M, C):
+        raise ValueError(f"gradient shape {grad.shape} != {(M, C)}")
+    stride, ntab = line_strides(ns, dep)
+    sigma = np.atleast_1d(np.asarray(sigma, dtype=np.float64)).ravel()
+    if sigma.size != ntab:
+        raise ValueError(f"need {ntab} displacements, got {sigma.size}")
+    s_tab, ab_tab = line_tables(sigma, k)
+    out = np.empty((M, C))
+    nsarr = np.asarray(ns, dtype=np.int64)
+    _load().oracle_sweep_adjoint(ndim, nsarr.ctypes.data, k, dim, stride.ctypes.data,
+                                 s_tab.ctypes.data, ab_tab.ctypes.data, grad.ctypes.data,
+                                 out.ctypes.data)
+    return out
+
+
+def run_sequence_adjoint(grad, ns, k, seq, steps=1):
+    """Transpose of run_sequence (FP64): the sweeps' adjoints in reverse order."""
+    for _ in range(steps):
+        for dim, sigma, dep in reversed(seq):
+            grad = sweep_adjoint(grad, ns, k, dim, sigma, dep)
+    return grad
 
 
 def round_tier(x, tier):

@@ -153,3 +153,56 @@ int oracle_num_threads(void)
     }
     return nt;
 }
+
+/*
+ * Transpose of oracle_sweep (no rounding): g_in = M^T g_out, M the sweep with
+ * the same tables.  Output cell i reads input cells i-s (through A) and
+ * i-s-1 (through B), so input cell m is read by output cells m+s (A) and
+ * m+s+1 (B):
+ *     g_in[l](m) = sum_j A[j][l] g_out[j](m+s) + sum_j B[j][l] g_out[j](m+s+1)
+ * for every spectator tuple, periodic along dim.  Arguments as oracle_sweep.
+ */
+void oracle_sweep_adjoint(int ndim, const int64_t* n, int k, int dim,
+                          const int64_t* line_stride, const int32_t* s_tab,
+                          const double* ab_tab, const double* g_out, double* g_in)
+{
+    const int o = k + 1;
+    int64_t cells = 1, modes = 1, mstride = 1;
+    for (int e = 0; e < ndim; ++e) {
+        cells *= n[e];
+        modes *= o;
+        if (e < dim)
+            mstride *= o;
+    }
+    int64_t cstride = 1;
+    for (int e = 0; e < dim; ++e)
+        cstride *= n[e];
+
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < cells; ++c) {
+        int64_t rest = c, t = 0, idim = 0;
+        for (int e = 0; e < ndim; ++e) {
+            int64_t ie = rest % n[e];
+            rest /= n[e];
+            t += ie * line_stride[e];
+            if (e == dim)
+                idim = ie;
+        }
+        const int64_t s = s_tab[t];
+        const double* A = ab_tab + t * 2 * o * o;
+        const double* B = A + o * o;
+        const int64_t base = c - idim * cstride;
+        const int64_t ca = base + wrap(idim + s, n[dim]) * cstride;      /* output m+s   */
+        const int64_t cb = base + wrap(idim + s + 1, n[dim]) * cstride;  /* output m+s+1 */
+        for (int64_t m = 0; m < modes; ++m) {
+            const int l = (int)((m / mstride) % o);
+            const int64_t m0 = m - l * mstride;
+            double acc = 0.0;
+            for (int j = 0; j < o; ++j)
+                acc += A[j * o + l] * g_out[(m0 + j * mstride) * cells + ca];
+            for (int j = 0; j < o; ++j)
+                acc += B[j * o + l] * g_out[(m0 + j * mstride) * cells + cb];
+            g_in[m * cells + c] = acc;
+        }
+    }
+}

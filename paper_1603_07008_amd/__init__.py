@@ -19,7 +19,7 @@ TIER_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}
 EXPORTS = ("sldg_plan", "sldg_plan_destroy", "sldg_plan_set_stream", "sldg_line_tables",
            "sldg_advect_dim", "sldg_split_steps", "sldg_mass", "sldg_hi_bytes",
            "sldg_status_string", "sldg_last_error", "sldg_timing_enable", "sldg_timing_read",
-           "sldg_mass_device", "sldg_device_copy")
+           "sldg_mass_device", "sldg_device_copy", "sldg_advect_dim_adjoint")
 
 
 class SldgError(RuntimeError):
@@ -54,6 +54,8 @@ def lib():
     L.sldg_line_tables.restype = i32
     L.sldg_advect_dim.argtypes = [vp, i32, vp, u32, vp, vp, vp, vp]
     L.sldg_advect_dim.restype = i32
+    L.sldg_advect_dim_adjoint.argtypes = [vp, i32, vp, u32, vp, vp, vp, vp]
+    L.sldg_advect_dim_adjoint.restype = i32
     L.sldg_split_steps.argtypes = [vp, ctypes.POINTER(SweepDesc), i32, i32, vp, vp, vp, vp,
                                    ctypes.POINTER(i32)]
     L.sldg_split_steps.restype = i32
@@ -203,6 +205,15 @@ class Plan:
                                      _ptr(in_mass), _ptr(in_hi), _ptr(out_mass), _ptr(out_hi)),
                "sldg_advect_dim")
 
+    def advect_dim_adjoint(self, dim, shift, dep_mask, in_mass, in_hi, out_mass, out_hi):
+        """The transposed sweep (sldg_advect_dim_adjoint)."""
+        self._check_shift(shift, dep_mask, "advect_dim_adjoint")
+        self._check_state(in_mass, in_hi, "advect_dim_adjoint input")
+        self._check_state(out_mass, out_hi, "advect_dim_adjoint output")
+        _check(lib().sldg_advect_dim_adjoint(self.handle, int(dim), _ptr(shift), int(dep_mask),
+                                             _ptr(in_mass), _ptr(in_hi), _ptr(out_mass),
+                                             _ptr(out_hi)), "sldg_advect_dim_adjoint")
+
     def split_steps(self, seq, nsteps, state0, state1):
         """Apply the sweeps `seq` [(dim, dep_mask, shift tensor), ...] nsteps
         times, ping-ponging between state0 and state1 (sldg_split_steps).
@@ -289,6 +300,10 @@ def plan_destroy(p):
 
 def advect_dim(p, dim, shift, dep_mask, in_mass, in_hi, out_mass, out_hi):
     p.advect_dim(dim, shift, dep_mask, in_mass, in_hi, out_mass, out_hi)
+
+
+def advect_dim_adjoint(p, dim, shift, dep_mask, in_mass, in_hi, out_mass, out_hi):
+    p.advect_dim_adjoint(dim, shift, dep_mask, in_mass, in_hi, out_mass, out_hi)
 
 
 def split_steps(p, seq, nsteps, state0, state1):

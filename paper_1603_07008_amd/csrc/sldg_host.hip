@@ -179,7 +179,8 @@ void free_plan(sldg_plan_s* p) {
 }
 
 sldg_status run_sweep(sldg_plan_s* p, int dim, const double* shift, uint32_t dep_mask,
-                      const double* in_mass, const void* in_hi, double* out_mass, void* out_hi) {
+                      const double* in_mass, const void* in_hi, double* out_mass, void* out_hi,
+                      bool adjoint = false) {
   SweepArgs a{};
   int64_t ntab = 0;
   describe(p, dim, dep_mask, a, ntab);
@@ -187,7 +188,7 @@ sldg_status run_sweep(sldg_plan_s* p, int dim, const double* shift, uint32_t dep
     return fail(SLDG_ERR_ARG, "line table of %lld entries exceeds the plan's %lld",
                 (long long)ntab, (long long)p->table_cap);
   hipError_t e = launch_line_tables(p->k, ntab, p->n[dim], shift, p->d_s, p->d_ab, true,
-                                    p->stream);
+                                    adjoint, p->stream);
   if (e != hipSuccess) return device_error(e, "line-table launch");
   a.in_mass = in_mass;
   a.in_hi = in_hi;
@@ -355,7 +356,8 @@ sldg_status sldg_line_tables(sldg_plan_t p, int64_t n, int64_t period, const dou
   if (n < 0 || period < 1) return fail(SLDG_ERR_ARG, "n=%lld period=%lld", (long long)n, (long long)period);
   if (n > 0 && (!sigma || !s_out || !ab_out)) return fail(SLDG_ERR_ARG, "null pointer");
   if (period >= (1LL << 31)) return fail(SLDG_ERR_ARG, "period too large");
-  hipError_t e = launch_line_tables(p->k, n, period, sigma, s_out, ab_out, false, p->stream);
+  hipError_t e = launch_line_tables(p->k, n, period, sigma, s_out, ab_out, false, false,
+                                    p->stream);
   if (e != hipSuccess) return device_error(e, "line-table launch");
   return ok();
 }
@@ -366,6 +368,15 @@ sldg_status sldg_advect_dim(sldg_plan_t p, int dim, const double* shift, uint32_
   sldg_status st = check_sweep(p, dim, shift, dep_mask, in_mass, in_hi, out_mass, out_hi);
   if (st != SLDG_OK) return st;
   st = run_sweep(p, dim, shift, dep_mask, in_mass, in_hi, out_mass, out_hi);
+  return st == SLDG_OK ? ok() : st;
+}
+
+sldg_status sldg_advect_dim_adjoint(sldg_plan_t p, int dim, const double* shift,
+                                    uint32_t dep_mask, const double* in_mass, const void* in_hi,
+                                    double* out_mass, void* out_hi) {
+  sldg_status st = check_sweep(p, dim, shift, dep_mask, in_mass, in_hi, out_mass, out_hi);
+  if (st != SLDG_OK) return st;
+  st = run_sweep(p, dim, shift, dep_mask, in_mass, in_hi, out_mass, out_hi, true);
   return st == SLDG_OK ? ok() : st;
 }
 

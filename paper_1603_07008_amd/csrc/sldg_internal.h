@@ -71,7 +71,7 @@ struct SweepArgs {
 // Launchers (defined in sldg_kernels.hip).  All return hipGetLastError().
 hipError_t launch_line_tables(int k, int64_t n, int64_t period, const double* sigma,
                               int32_t* s_out, double* ab_out, bool component_major,
-                              hipStream_t st);
+                              bool adjoint, hipStream_t st);
 hipError_t launch_sweep(int k, int tier, int dim, const SweepArgs& a, hipStream_t st);
 hipError_t launch_mass(const double* mass, int64_t n, double* partial, int nblocks,
                        double* result, hipStream_t st);

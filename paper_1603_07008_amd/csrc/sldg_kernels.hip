@@ -72,7 +72,14 @@ __device__ __forceinline__ double horner_comp(const double (&c)[2 * K + 2], doub
 // ab_out[e * cs + t * ts]: (cs, ts) = (1, 2(k+1)^2) is entry-major (the public
 // layout), (n, 1) component-major (used by the sweeps, so that lanes reading
 // the matrices of consecutive lines touch consecutive addresses).
-template <int K>
+//
+// ADJ: the table of the transposed sweep.  The forward sweep of one line,
+// out[i] = A in[i-s] + B in[i-s-1], has the transpose
+// g_in[m] = A^T g[m+s] + B^T g[m+s+1], which is again a forward-form sweep
+// with shift s' = -s-1 and matrices (A', B') = (B^T, A^T).  It is built from
+// the same (snapped, exact-mass-row) A and B, so it is the exact transpose of
+// the forward map.
+template <int K, bool ADJ>
 __global__ __launch_bounds__(256) void line_tables_kernel(int64_t n, int64_t period,
                                                           const double* __restrict__ sigma,
                                                           int32_t* __restrict__ s_out,
@@ -94,7 +101,7 @@ __global__ __launch_bounds__(256) void line_tables_kernel(int64_t n, int64_t per
   }
   int32_t s = 0;
   if (isfinite(sg)) {
-    double r = fmod(fs, (double)period);   // exact
+    double r = fmod(ADJ ? -fs - 1.0 : fs, (double)period);   // exact
     if (r < 0) r += (double)period;
     s = (int32_t)r;
   } else {
@@ -122,24 +129,29 @@ __global__ __launch_bounds__(256) void line_tables_kernel(int64_t n, int64_t per
   for (int j = 0; j < O; ++j)
 #pragma unroll
     for (int l = 0; l < O; ++l) {
-      base[(j * O + l) * cs] = A[j][l];
-      base[(O * O + j * O + l) * cs] = B[j][l];
+      base[(j * O + l) * cs] = ADJ ? B[l][j] : A[j][l];
+      base[(O * O + j * O + l) * cs] = ADJ ? A[l][j] : B[j][l];
     }
 }
 
 hipError_t launch_line_tables(int k, int64_t n, int64_t period, const double* sigma,
                               int32_t* s_out, double* ab_out, bool component_major,
-                              hipStream_t st) {
+                              bool adjoint, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const int64_t e = 2LL * (k + 1) * (k + 1);
   const int64_t cs = component_major ? n : 1, ts = component_major ? 1 : e;
   dim3 grid((unsigned)((n + 255) / 256)), block(256);
-  switch (k) {
-    case 1: line_tables_kernel<1><<<grid, block, 0, st>>>(n, period, sigma, s_out, ab_out, cs, ts); break;
-    case 2: line_tables_kernel<2><<<grid, block, 0, st>>>(n, period, sigma, s_out, ab_out, cs, ts); break;
-    case 3: line_tables_kernel<3><<<grid, block, 0, st>>>(n, period, sigma, s_out, ab_out, cs, ts); break;
+#define SLDG_TABLES(KK, AA) line_tables_kernel<KK, AA><<<grid, block, 0, st>>>(n, period, sigma, s_out, ab_out, cs, ts)
+  switch (k * 2 + (adjoint ? 1 : 0)) {
+    case 2: SLDG_TABLES(1, false); break;
+    case 3: SLDG_TABLES(1, true); break;
+    case 4: SLDG_TABLES(2, false); break;
+    case 5: SLDG_TABLES(2, true); break;
+    case 6: SLDG_TABLES(3, false); break;
+    case 7: SLDG_TABLES(3, true); break;
     default: return hipErrorInvalidValue;
   }
+#undef SLDG_TABLES
   return hipGetLastError();
 }
 

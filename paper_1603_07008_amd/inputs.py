@@ -181,3 +181,24 @@ def random_coefficients_device(ndim, k, cells, seed=0, scale0=0.15, decay=0.05, 
         js = sum((m // o ** e) % o for e in range(ndim))
         hi[m - 1].normal_(0.0, scale0 * decay ** js, generator=g)
     return mass, hi
+
+
+def vlasov_2d_differentiation(n=512, steps=50, k=2, seed=5, dt=0.1, eps=0.01):
+    """The 2D (x, v) problem of vlasov_2d on n x n cells for differentiation:
+    fixed E, `steps` Strang steps, and a seeded target
+    f_t = (1 + eps cos(x/2 + phi)) M(v) (phi from `seed`), whose projection plus
+    N(0, 1e-4) noise on every coefficient (also from `seed`) is the target
+    state of the misfit."""
+    p = vlasov_2d(nx=n, nv=n, k=k, dt=dt, steps=steps, eps=eps)
+    p.name = "vlasov-2d-adjoint"
+    rng = np.random.default_rng(seed)
+    phi = float(rng.uniform(0.0, 2 * math.pi))
+    p.target_terms = [(lambda x: 1.0 + eps * np.cos(0.5 * x + phi), maxwellian)]
+    p.target_noise = rng.standard_normal((p.modes, p.cells)) * 1e-4
+    return p
+
+
+def fd_directions(count, modes, cells, seed=6):
+    """Seeded N(0, 1) directions over all coefficients, [count, modes, cells]."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((count, modes, cells))

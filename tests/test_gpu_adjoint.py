@@ -1,0 +1,131 @@
+"""GPU adjoint sweep and differentiation through split steps, against the
+oracle's transpose and central finite differences."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import sldg_oracle as O
+from paper_1603_07008_amd import inputs
+from gpu_helpers import download, have_gpu, upload, weighted_rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sl():
+    if not have_gpu():
+        pytest.skip("no HIP device")
+    import paper_1603_07008_amd as sl
+    sl.lib()
+    return sl
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+CASES = [((64,), 2, {0: ()}), ((37, 19), 3, {0: (1,), 1: (0,)}),
+         ((48, 10), 2, {0: (1,), 1: (0,)}), ((12, 10, 8, 9), 2, {0: (2,), 1: (3,), 2: (0, 1), 3: (0, 1)}),
+         ((6, 4, 5, 3), 1, {0: (2, 3), 1: (), 2: (0, 1, 3), 3: (1,)})]
+
+
+@pytest.mark.parametrize("case", CASES, ids=["x".join(map(str, c[0])) + f"-k{c[1]}" for c in CASES])
+def test_adjoint_sweep_matches_oracle_transpose(sl, case):
+    import torch
+    ns, k, deps = case
+    cells = int(np.prod(ns))
+    rng = np.random.default_rng(cells + k)
+    g = rng.standard_normal(((k + 1) ** len(ns), cells))
+    p = sl.Plan(ns, k, "fp64")
+    gi = upload(g, "fp64")
+    go = p.empty_state()
+    for dim, dep in deps.items():
+        nsig = int(np.prod([ns[e] for e in dep])) if dep else 1
+        sig = rng.uniform(-2.5 * ns[dim], 2.5 * ns[dim], nsig)
+        p.advect_dim_adjoint(dim, _dev(sig), sum(1 << e for e in dep), gi[0], gi[1], go[0], go[1])
+        torch.cuda.synchronize()
+        got = download(*go)
+        want = O.sweep_adjoint(g, ns, k, dim, sig, dep)
+        scale = np.max(np.abs(want)) + 1e-300
+        assert np.max(np.abs(got - want)) <= 64 * np.finfo(float).eps * scale * (k + 1), (dim, np.max(np.abs(got - want)))
+        # dot-product identity on the device results: <M x, y> = <x, M^T y>
+        x = rng.standard_normal(g.shape)
+        xi = upload(x, "fp64")
+        mx = p.empty_state()
+        p.advect_dim(dim, _dev(sig), sum(1 << e for e in dep), xi[0], xi[1], mx[0], mx[1])
+        torch.cuda.synchronize()
+        lhs = math.fsum((download(*mx) * g).ravel().tolist())
+        rhs = math.fsum((x * got).ravel().tolist())
+        assert abs(lhs - rhs) <= 1e-12 * math.sqrt(g.size) * (1 + abs(lhs))
+
+
+def _setup_diff(sl, n, steps):
+    import torch
+    prob = inputs.vlasov_2d_differentiation(n=n, steps=steps)
+    c0 = O.project_separable(prob.f0_terms, prob.ns, prob.los, prob.his, prob.k)
+    tgt = O.project_separable(prob.target_terms, prob.ns, prob.los, prob.his, prob.k) + prob.target_noise
+    p = sl.Plan(prob.ns, prob.k, "fp64")
+    seq = [(sw.dim, sw.dep_mask, _dev(sw.sigma)) for sw in prob.seq]
+    vol = O.cell_volume(prob.ns, prob.los, prob.his)
+    return prob, c0, tgt, p, seq, vol
+
+
+def _loss_and_grad(sl, p, seq, steps, c0, tgt, vol, ckpt=None):
+    import torch
+    from paper_1603_07008_amd import autograd as AG
+    m0, h0 = upload(c0, "fp64")
+    m0.requires_grad_(True)
+    h0.requires_grad_(True)
+    tm, th = upload(tgt, "fp64")
+    m1, h1 = AG.split_steps(p, seq, steps, m0, h0, checkpoint_every=ckpt)
+    L = AG.weighted_l2_misfit(m1, h1, tm, th, 2, p.k, vol)
+    L.backward()
+    return float(L), np.concatenate([m0.grad.cpu().numpy()[None], h0.grad.cpu().numpy()])
+
+
+def _loss_only(sl, p, seq, steps, c, tgt, vol):
+    import torch
+    from paper_1603_07008_amd import autograd as AG
+    m0, h0 = upload(c, "fp64")
+    tm, th = upload(tgt, "fp64")
+    with torch.no_grad():
+        m1, h1 = AG.split_steps(p, seq, steps, m0, h0)
+        return float(AG.weighted_l2_misfit(m1, h1, tm, th, 2, p.k, vol))
+
+
+def test_gradient_matches_oracle_adjoint_and_checkpointing_is_bitwise(sl):
+    prob, c0, tgt, p, seq, vol = _setup_diff(sl, 64, 12)
+    L, g = _loss_and_grad(sl, p, seq, prob.steps, c0, tgt, vol)
+    _, g_ck = _loss_and_grad(sl, p, seq, prob.steps, c0, tgt, vol, ckpt=5)
+    assert np.array_equal(g, g_ck)
+    oseq = [(s.dim, s.sigma, s.dep) for s in prob.seq]
+    cT = O.run_sequence(c0, prob.ns, prob.k, oseq, "fp64", prob.steps)
+    w = O.mode_weights(2, prob.k)[:, None]
+    gT = vol * w * (cT - tgt)
+    g_or = O.run_sequence_adjoint(gT, prob.ns, prob.k, oseq, prob.steps)
+    assert weighted_rel_l2(g, g_or, 2, prob.k) <= 1e-12
+    L_or = 0.5 * vol * math.fsum((w * (cT - tgt) ** 2).ravel().tolist())
+    assert abs(L - L_or) <= 1e-12 * L_or
+
+
+@pytest.mark.parametrize("n,steps,ndir", [(64, 12, 8), (512, 50, 64)])
+def test_gradient_matches_central_finite_differences(sl, n, steps, ndir):
+    prob, c0, tgt, p, seq, vol = _setup_diff(sl, n, steps)
+    L, g = _loss_and_grad(sl, p, seq, steps, c0, tgt, vol, ckpt=10)
+    dirs = inputs.fd_directions(ndir, prob.modes, prob.cells)
+    h = 1e-6
+    eps = np.finfo(float).eps
+    worst = 0.0
+    for d in dirs:
+        Lp = _loss_only(sl, p, seq, steps, c0 + h * d, tgt, vol)
+        Lm = _loss_only(sl, p, seq, steps, c0 - h * d, tgt, vol)
+        fd = (Lp - Lm) / (2 * h)
+        gd = math.fsum((g * d).ravel().tolist())
+        # the loss is quadratic in c0: central differences are exact up to the
+        # rounding of the two loss values (and of the directional derivative)
+        tol = 8 * eps * max(abs(Lp), abs(Lm)) / h + 1e-10 * abs(gd)
+        worst = max(worst, abs(fd - gd) / tol)
+        assert abs(fd - gd) <= tol, (fd, gd, tol)
+    print(f"finite differences n={n}: worst error / bound = {worst:.3f}")

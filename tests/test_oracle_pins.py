@@ -419,3 +419,44 @@ def test_separable_projection_equals_direct_tensor_rule():
                         wg[:, None] * wg[None, :] * P[j0][:, None] * P[j1][None, :] * F)
                     got = c[j0 + o * j1, i0 + 6 * i1]
                     assert abs(got - want) < 1e-15
+
+
+# --------------------------------------------------------------------------
+# adjoint (transpose) sweep
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_adjoint_dot_product_identity(k):
+    # <M x, y> = <x, M^T y> for the sweep M and its oracle transpose
+    rng = np.random.default_rng(50 + k)
+    for ns, dim, dep in [((9,), 0, ()), ((7, 6), 1, (0,)), ((5, 4, 6), 0, (1, 2)),
+                         ((4, 5, 3), 2, (0,))]:
+        o = k + 1
+        M, C = o ** len(ns), int(np.prod(ns))
+        x = rng.standard_normal((M, C))
+        y = rng.standard_normal((M, C))
+        nsig = int(np.prod([ns[e] for e in dep])) if dep else 1
+        sig = rng.uniform(-7, 7, nsig)
+        lhs = math.fsum((O.sweep(x, ns, k, dim, sig, dep) * y).ravel().tolist())
+        rhs = math.fsum((x * O.sweep_adjoint(y, ns, k, dim, sig, dep)).ravel().tolist())
+        assert abs(lhs - rhs) <= 1e-13 * math.sqrt(M * C), (ns, dim, lhs, rhs)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_adjoint_equals_weighted_reflected_forward(k):
+    # A(a)^T = W B(1-a) W^-1 and B(a)^T = W A(1-a) W^-1 with W = diag(2/(2j+1)):
+    # so the transpose sweep is W F(-sigma) W^-1: the weight-conjugated forward
+    # sweep with the opposite displacement (the projection is self-adjoint in
+    # the L2 inner product, whose Gram matrix per cell is W)
+    W = np.diag([2.0 / (2 * j + 1) for j in range(k + 1)])
+    Wi = np.linalg.inv(W)
+    for alpha in [0.125, 0.375, 0.5, 0.6875]:
+        A, B = O.ab_exact(alpha, k)
+        A1, B1 = O.ab_exact(1 - alpha, k)
+        assert np.allclose(A.T, W @ B1 @ Wi, atol=1e-15, rtol=0)
+        assert np.allclose(B.T, W @ A1 @ Wi, atol=1e-15, rtol=0)
+    n = 11
+    g = np.random.default_rng(5).standard_normal((k + 1, n))
+    sigma = 2.6
+    via_forward = W @ O.sweep(Wi @ g, (n,), k, 0, -sigma)
+    assert np.allclose(O.sweep_adjoint(g, (n,), k, 0, sigma), via_forward, atol=1e-13, rtol=0)
