@@ -189,6 +189,49 @@ sldg_status sldg_device_copy(const void* src, void* dst, int64_t bytes, void* st
 /* Bytes of one state's `hi` array for this plan, (o^ndim - 1) * cells * sizeof(T). */
 int64_t sldg_hi_bytes(sldg_plan_t plan);
 
+/*
+ * Batches: many independent problems advanced together (each with its own
+ * grid, degree and displacement fields; one storage tier and dimension count
+ * for the whole batch).  Each sweep of a split step is one persistent launch
+ * over a work list of tiles of all problems.
+ */
+typedef struct sldg_batch_s* sldg_batch_t;
+
+/*   nprob   number of problems (>= 1); ndim: dimensions of every problem (1..6)
+ *   ncells  host int64 [nprob * ndim]: problem p's extents at ncells[p*ndim ...],
+ *           dimension 0 fastest, total per problem below 2^31
+ *   k       host int [nprob]: degree of each problem (1..3)
+ *   stream  hipStream_t of every later call (graph replay needs a non-null one) */
+sldg_status sldg_batch_create(sldg_batch_t* batch, int nprob, int ndim, const int64_t* ncells,
+                              const int* k, sldg_tier tier, void* stream);
+/* Release (synchronises the stream first).  NULL is a no-op. */
+void sldg_batch_destroy(sldg_batch_t batch);
+/* Bind the two state buffers of every problem: host arrays [nprob] of device
+ * pointers (layout of each problem as in sldg_advect_dim).  No buffer may
+ * overlap another buffer of the same problem. */
+sldg_status sldg_batch_bind(sldg_batch_t batch, double* const* mass0, void* const* hi0,
+                            double* const* mass1, void* const* hi1);
+/* The sweeps of one split step: sweep q runs along dims[q]; problem p uses
+ * the dependence mask masks[q*nprob + p] and the device displacements
+ * shifts[q*nprob + p] (as in sldg_advect_dim).  The per-line tables of every
+ * sweep are computed now, once (section II-A: the matrices depend only on the
+ * step); set the sequence again after changing displacements. */
+sldg_status sldg_batch_set_sequence(sldg_batch_t batch, int nseq, const int* dims,
+                                    const uint32_t* masks, const double* const* shifts);
+/* nsteps split steps; sweep number q (over all steps) reads buffer q % 2 and
+ * writes the other; *result_buffer receives the buffer holding the result.
+ * use_graph != 0: each step is captured once (per starting buffer) into a
+ * HIP graph and replayed. */
+sldg_status sldg_batch_run(sldg_batch_t batch, int nsteps, int use_graph, int* result_buffer);
+/* Launch-shape tuner: for every sweep of the sequence, times rows-per-thread
+ * {2, 4, 8} (strided sweeps) x tuples-per-thread {1, 3, 9, all} on the bound
+ * data (reads buffer 0, overwrites buffer 1) and keeps the fastest. */
+sldg_status sldg_batch_tune(sldg_batch_t batch, int reps);
+/* Read / set the launch shape of sweep q (tuples 0 = all); ms is the tuned
+ * time per launch (-1 if not tuned). */
+sldg_status sldg_batch_get_tuning(sldg_batch_t batch, int q, int* rows, int* tuples, double* ms);
+sldg_status sldg_batch_set_tuning(sldg_batch_t batch, int q, int rows, int tuples);
+
 const char* sldg_status_string(sldg_status s);
 const char* sldg_last_error(void);
 

@@ -19,7 +19,9 @@ TIER_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}
 EXPORTS = ("sldg_plan", "sldg_plan_destroy", "sldg_plan_set_stream", "sldg_line_tables",
            "sldg_advect_dim", "sldg_split_steps", "sldg_mass", "sldg_hi_bytes",
            "sldg_status_string", "sldg_last_error", "sldg_timing_enable", "sldg_timing_read",
-           "sldg_mass_device", "sldg_device_copy", "sldg_advect_dim_adjoint")
+           "sldg_mass_device", "sldg_device_copy", "sldg_advect_dim_adjoint",
+           "sldg_batch_create", "sldg_batch_destroy", "sldg_batch_bind", "sldg_batch_set_sequence",
+           "sldg_batch_run", "sldg_batch_tune", "sldg_batch_get_tuning", "sldg_batch_set_tuning")
 
 
 class SldgError(RuntimeError):

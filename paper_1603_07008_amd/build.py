@@ -7,7 +7,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsldg.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("sldg_host.hip", "sldg_kernels.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("sldg_host.hip", "sldg_batch.hip", "sldg_kernels.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("sldg_internal.h", "ab_poly.h")] + \
     [os.path.join(ROOT, "include", "sldg.h")]
 ARCH = os.environ.get("SLDG_OFFLOAD_ARCH", "gfx950")

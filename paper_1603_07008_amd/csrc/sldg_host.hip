@@ -42,10 +42,9 @@ struct sldg_plan_s {
   int nev_created;
 };
 
-namespace {
+namespace sldg {
 
-constexpr int kMaxTimed = 4096;
-thread_local char g_err[512] = "";
+static thread_local char g_err[512] = "";
 
 sldg_status fail(sldg_status st, const char* fmt, ...) {
   va_list ap;
@@ -59,6 +58,8 @@ sldg_status ok() {
   g_err[0] = '\0';
   return SLDG_OK;
 }
+
+const char* last_error_text() { return g_err; }
 
 int64_t elem_size(sldg_tier t) {
   switch (t) {
@@ -76,7 +77,71 @@ bool overlap(const void* a, int64_t na, const void* b, int64_t nb) {
   return pa < pb + nb && pb < pa + na;
 }
 
-// Checks of one sweep's arguments that need no device.
+sldg_status device_error(hipError_t e, const char* what) {
+  return fail(SLDG_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void describe_grid(int ndim, const int64_t* n, int o, int64_t modes, int dim, uint32_t dep_mask,
+                   int rows_per_thread, int tuples_per_thread, SweepArgs& a, int64_t& ntab) {
+  int64_t P = 1, Q = 1, cells = 1;
+  for (int e = 0; e < ndim; ++e) cells *= n[e];
+  for (int e = 0; e < dim; ++e) P *= n[e];
+  for (int e = dim + 1; e < ndim; ++e) Q *= n[e];
+  a.cells = cells;
+  a.P = (int32_t)P;
+  a.N = (int32_t)n[dim];
+  a.Q = (int32_t)Q;
+  int64_t ms = 1;
+  for (int e = 0; e < dim; ++e) ms *= o;
+  a.mstride = (int32_t)ms;
+  a.nspec = (int32_t)(modes / o);
+  // table over the dependent dims, lowest fastest
+  LineMap m{};
+  int64_t str = 1, div_lo = 1, div_hi = 1;
+  for (int e = 0; e < ndim; ++e) {
+    if (e == dim) continue;
+    const bool below = e < dim;
+    if (dep_mask & (1u << e)) {
+      if (below) {
+        m.lo_div[m.nlo] = FastDiv::make((uint32_t)div_lo);
+        m.lo_mod[m.nlo] = FastDiv::make((uint32_t)n[e]);
+        m.lo_str[m.nlo] = (int32_t)str;
+        ++m.nlo;
+      } else {
+        m.hi_div[m.nhi] = FastDiv::make((uint32_t)div_hi);
+        m.hi_mod[m.nhi] = FastDiv::make((uint32_t)n[e]);
+        m.hi_str[m.nhi] = (int32_t)str;
+        ++m.nhi;
+      }
+      str *= n[e];
+    }
+    if (below) div_lo *= n[e];
+    else div_hi *= n[e];
+  }
+  a.map = m;
+  ntab = str;
+  a.tuples = (tuples_per_thread > 0 && tuples_per_thread < a.nspec) ? tuples_per_thread : a.nspec;
+  // strided sweep: rows per thread (one-shot chunks along the swept dim)
+  if (dim > 0) {
+    int rows = rows_per_thread;
+    while (rows > 1 && rows > a.N) rows >>= 1;
+    a.chunk = rows;
+    a.nchunk = (int32_t)((a.N + rows - 1) / rows);
+  } else {
+    a.chunk = a.N;
+    a.nchunk = 1;
+  }
+  a.fP = FastDiv::make((uint32_t)a.P);
+  a.fN = FastDiv::make((uint32_t)a.N);
+  a.fchunk = FastDiv::make((uint32_t)a.nchunk);
+}
+
+}  // namespace sldg
+
+namespace {
+
+constexpr int kMaxTimed = 4096;
+
 sldg_status check_sweep(const sldg_plan_s* p, int dim, const double* shift, uint32_t dep_mask,
                         const double* in_mass, const void* in_hi, const double* out_mass,
                         const void* out_hi) {
@@ -110,62 +175,10 @@ sldg_status check_sweep(const sldg_plan_s* p, int dim, const double* shift, uint
 
 // Describe the sweep along dim for the kernels (everything but the buffers).
 void describe(const sldg_plan_s* p, int dim, uint32_t dep_mask, SweepArgs& a, int64_t& ntab) {
-  int64_t P = 1, Q = 1;
-  for (int e = 0; e < dim; ++e) P *= p->n[e];
-  for (int e = dim + 1; e < p->ndim; ++e) Q *= p->n[e];
-  a.cells = p->cells;
-  a.P = (int32_t)P;
-  a.N = (int32_t)p->n[dim];
-  a.Q = (int32_t)Q;
-  int64_t ms = 1;
-  for (int e = 0; e < dim; ++e) ms *= p->o;
-  a.mstride = (int32_t)ms;
-  a.nspec = (int32_t)(p->modes / p->o);
-  // table over the dependent dims, lowest fastest
-  LineMap m{};
-  int64_t str = 1, div_lo = 1, div_hi = 1;
-  for (int e = 0; e < p->ndim; ++e) {
-    if (e == dim) continue;
-    const bool below = e < dim;
-    if (dep_mask & (1u << e)) {
-      if (below) {
-        m.lo_div[m.nlo] = FastDiv::make((uint32_t)div_lo);
-        m.lo_mod[m.nlo] = FastDiv::make((uint32_t)p->n[e]);
-        m.lo_str[m.nlo] = (int32_t)str;
-        ++m.nlo;
-      } else {
-        m.hi_div[m.nhi] = FastDiv::make((uint32_t)div_hi);
-        m.hi_mod[m.nhi] = FastDiv::make((uint32_t)p->n[e]);
-        m.hi_str[m.nhi] = (int32_t)str;
-        ++m.nhi;
-      }
-      str *= p->n[e];
-    }
-    if (below) div_lo *= p->n[e];
-    else div_hi *= p->n[e];
-  }
-  a.map = m;
-  ntab = str;
-  a.tuples = (p->tuples_per_thread > 0 && p->tuples_per_thread < a.nspec) ? p->tuples_per_thread
-                                                                          : a.nspec;
-  // strided sweep: rows per thread (one-shot chunks along the swept dim)
-  if (dim > 0) {
-    int rows = p->rows_per_thread;
-    while (rows > 1 && rows > a.N) rows >>= 1;
-    a.chunk = rows;
-    a.nchunk = (int32_t)((a.N + rows - 1) / rows);
-  } else {
-    a.chunk = a.N;
-    a.nchunk = 1;
-  }
-  a.fP = FastDiv::make((uint32_t)a.P);
-  a.fN = FastDiv::make((uint32_t)a.N);
-  a.fchunk = FastDiv::make((uint32_t)a.nchunk);
+  describe_grid(p->ndim, p->n, p->o, p->modes, dim, dep_mask, p->rows_per_thread,
+                p->tuples_per_thread, a, ntab);
 }
 
-sldg_status device_error(hipError_t e, const char* what) {
-  return fail(SLDG_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
-}
 
 void free_plan(sldg_plan_s* p) {
   if (!p) return;
@@ -240,7 +253,7 @@ const char* sldg_status_string(sldg_status s) {
   return "unknown status";
 }
 
-const char* sldg_last_error(void) { return g_err; }
+const char* sldg_last_error(void) { return last_error_text(); }
 
 sldg_status sldg_plan(sldg_plan_t* out, int ndim, const int64_t* ncells, int k, sldg_tier tier,
                       void* stream) {

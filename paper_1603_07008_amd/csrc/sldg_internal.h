@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sldg.h"
+
 namespace sldg {
 
 constexpr int kMaxDim = 6;
@@ -68,6 +70,15 @@ struct SweepArgs {
   LineMap map;
 };
 
+// One workgroup-sized tile of one problem of a batched sweep.
+//   kind 0: dimension-0 sweep, window form: groups [x*256, x*256+256) of 4 cells
+//   kind 1: dimension-0 sweep, generic form: (line, tuple) pairs [4x, 4x+4)
+//   kind 2: strided sweep: columns [64x, 64x+64), row chunks from z*(blockDim/64)
+// qg selects the run of spectator tuples (kinds 0 and 2).
+struct BatchItem {
+  int32_t prob, kind, x, qg, z;
+};
+
 // Launchers (defined in sldg_kernels.hip).  All return hipGetLastError().
 hipError_t launch_line_tables(int k, int64_t n, int64_t period, const double* sigma,
                               int32_t* s_out, double* ab_out, bool component_major,
@@ -76,8 +87,24 @@ hipError_t launch_sweep(int k, int tier, int dim, const SweepArgs& a, hipStream_
 hipError_t launch_mass(const double* mass, int64_t n, double* partial, int nblocks,
                        double* result, hipStream_t st);
 
+hipError_t launch_batch_sweep(int tier, int rows, const SweepArgs* args, const int32_t* kdeg,
+                              const BatchItem* items, int32_t nitems, int32_t grid,
+                              hipStream_t st);
+bool contig_window_ok(const SweepArgs& a);
 hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t st);
 
 int mass_blocks(int64_t n);
+
+// Host helpers shared by the plan and batch front ends (sldg_host.hip).
+sldg_status fail(sldg_status st, const char* fmt, ...);
+sldg_status ok();
+const char* last_error_text();
+int64_t elem_size(sldg_tier t);
+bool overlap(const void* a, int64_t na, const void* b, int64_t nb);
+sldg_status device_error(hipError_t e, const char* what);
+// Everything a sweep kernel needs to know about one grid except the buffers
+// and tables; ntab = entries of the sweep's per-line table.
+void describe_grid(int ndim, const int64_t* n, int o, int64_t modes, int dim, uint32_t dep_mask,
+                   int rows_per_thread, int tuples_per_thread, SweepArgs& a, int64_t& ntab);
 
 }  // namespace sldg

@@ -450,7 +450,7 @@ __device__ __forceinline__ void contig_store(const SweepArgs& a, int32_t m0, int
 // entry is read with scalar loads and the matrices live in scalar registers.
 template <int K, int TIER>
 __device__ __forceinline__ void contig_body(const SweepArgs& a, int32_t c, int32_t line,
-                                            int32_t i0, int32_t t) {
+                                            int32_t i0, int32_t t, int32_t q, int32_t qe) {
   constexpr int O = K + 1;
   const int32_t N = a.N;
   const int32_t s = a.s_tab[t];
@@ -460,8 +460,6 @@ __device__ __forceinline__ void contig_body(const SweepArgs& a, int32_t c, int32
   const int32_t blk0 = w0 >> 2, d = w0 & 3;
   const int32_t blk1 = (blk0 + 1 == nb) ? 0 : blk0 + 1;
   const int64_t lb = (int64_t)line * N;
-  int32_t q = blockIdx.y * a.tuples;
-  const int32_t qe = min(a.nspec, q + a.tuples);
   Mat<K, TIER> M;
   M.load(a.ab_tab + t, a.ab_cs, q == 0);
   if (q == 0) {
@@ -480,17 +478,25 @@ __device__ __forceinline__ void contig_body(const SweepArgs& a, int32_t c, int32
   }
 }
 
+// Group g (4 cells) of the dimension-0 sweep, tuples [q, qe).
 template <int K, int TIER>
-__global__ __launch_bounds__(256) void sweep_contig_window_kernel(SweepArgs a) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void contig_group(const SweepArgs& a, int64_t g, int32_t q,
+                                             int32_t qe) {
   if (g >= (a.cells >> 2)) return;
   const int32_t c = (int32_t)(g << 2);
   const int32_t line = (int32_t)a.fN.div((uint32_t)c);
   const int32_t i0 = c - line * a.N;
   const int32_t t = table_index(a.map, 0, line);
   const int32_t t0 = __builtin_amdgcn_readfirstlane(t);
-  if (__all(t == t0)) contig_body<K, TIER>(a, c, line, i0, t0);
-  else contig_body<K, TIER>(a, c, line, i0, t);
+  if (__all(t == t0)) contig_body<K, TIER>(a, c, line, i0, t0, q, qe);
+  else contig_body<K, TIER>(a, c, line, i0, t, q, qe);
+}
+
+template <int K, int TIER>
+__global__ __launch_bounds__(256) void sweep_contig_window_kernel(SweepArgs a) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t q = blockIdx.y * a.tuples;
+  contig_group<K, TIER>(a, g, q, min(a.nspec, q + a.tuples));
 }
 
 // ---------------------------------------------------------------------------
@@ -558,7 +564,7 @@ __device__ __forceinline__ void strided_store(const SweepArgs& a, int32_t m0, in
 
 template <int K, int TIER, int L>
 __device__ __forceinline__ void strided_body(const SweepArgs& a, int32_t ilow, int32_t chunk,
-                                             int32_t ihigh, int32_t t) {
+                                             int32_t ihigh, int32_t t, int32_t q, int32_t qe) {
   constexpr int O = K + 1;
   const int32_t s = a.s_tab[t];
   const int32_t N = a.N, P = a.P, ms = a.mstride;
@@ -573,8 +579,6 @@ __device__ __forceinline__ void strided_body(const SweepArgs& a, int32_t ilow, i
     roff[u] = row * P;
     if (++row == N) row = 0;
   }
-  int32_t q = blockIdx.y * a.tuples;
-  const int32_t qe = min(a.nspec, q + a.tuples);
   Mat<K, TIER> M;
   M.load(a.ab_tab + t, a.ab_cs, q == 0);
   if (q == 0) {
@@ -616,19 +620,26 @@ __device__ __forceinline__ void strided_body(const SweepArgs& a, int32_t ilow, i
 // row chunks of the same columns.  The halo row a wave loads is the last row
 // its neighbour wave loads, so it is served by the CU's caches, and the
 // waves share the columns' s, A, B in L1.
+// Column col, row chunk `chunk` of a strided sweep, tuples [q, qe).
 template <int K, int TIER, int L>
-__global__ __launch_bounds__(256) void sweep_strided_kernel(SweepArgs a) {
-  const int32_t ncol = a.P * a.Q;
-  const int32_t col = (int32_t)blockIdx.x * 64 + (int32_t)(threadIdx.x & 63);
-  const int32_t chunk = (int32_t)blockIdx.z * (int32_t)(blockDim.x >> 6) + (int32_t)(threadIdx.x >> 6);
-  if (col >= ncol || chunk >= a.nchunk) return;
+__device__ __forceinline__ void strided_cell(const SweepArgs& a, int32_t col, int32_t chunk,
+                                             int32_t q, int32_t qe) {
+  if (col >= a.P * a.Q || chunk >= a.nchunk) return;
   const uint32_t ih = a.fP.div((uint32_t)col);
   const int32_t ilow = col - (int32_t)ih * a.P;
   const int32_t ihigh = (int32_t)ih;
   const int32_t t = table_index(a.map, ilow, ihigh);
   const int32_t t0 = __builtin_amdgcn_readfirstlane(t);
-  if (__all(t == t0)) strided_body<K, TIER, L>(a, ilow, chunk, ihigh, t0);
-  else strided_body<K, TIER, L>(a, ilow, chunk, ihigh, t);
+  if (__all(t == t0)) strided_body<K, TIER, L>(a, ilow, chunk, ihigh, t0, q, qe);
+  else strided_body<K, TIER, L>(a, ilow, chunk, ihigh, t, q, qe);
+}
+
+template <int K, int TIER, int L>
+__global__ __launch_bounds__(256) void sweep_strided_kernel(SweepArgs a) {
+  const int32_t col = (int32_t)blockIdx.x * 64 + (int32_t)(threadIdx.x & 63);
+  const int32_t chunk = (int32_t)blockIdx.z * (int32_t)(blockDim.x >> 6) + (int32_t)(threadIdx.x >> 6);
+  const int32_t q = blockIdx.y * a.tuples;
+  strided_cell<K, TIER, L>(a, col, chunk, q, min(a.nspec, q + a.tuples));
 }
 
 bool contig_window_ok(const SweepArgs& a) {
@@ -685,6 +696,87 @@ hipError_t launch_sweep(int k, int tier, int dim, const SweepArgs& a, hipStream_
     case 1: return launch_sweep_k<1>(tier, dim, a, st);
     case 2: return launch_sweep_k<2>(tier, dim, a, st);
     case 3: return launch_sweep_k<3>(tier, dim, a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched sweep: many independent problems (own grid, degree and tables) in
+// one persistent launch.  The work list holds one item per workgroup-sized
+// tile of one problem; a fixed grid of workgroups walks the list, so uneven
+// problem sizes and degrees share the launch without idle tails per problem.
+// Items of dimension-0 sweeps are windows of 256 x 4 cells (when the
+// problem's N_0 % 4 == 0 and its buffers are 16-byte aligned) or, otherwise,
+// 4 (line, tuple) pairs of the generic form; items of strided sweeps are 64
+// columns x (blockDim/64) row chunks.  A run of tuples is part of the item.
+// ---------------------------------------------------------------------------
+
+template <int K, int TIER>
+__device__ __forceinline__ void contig_generic_item(const SweepArgs& a, int64_t item4) {
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t nlines = (int64_t)a.Q;
+  const int64_t item = item4 * 4 + wave;
+  if (item >= nlines * a.nspec) return;
+  const int32_t sp = (int32_t)(item / nlines);
+  const int64_t line = item - (int64_t)sp * nlines;
+  if (sp == 0) contig_line<K, TIER, true>(a, line, sp, lane);
+  else contig_line<K, TIER, false>(a, line, sp, lane);
+}
+
+template <int TIER, int L>
+__global__ __launch_bounds__(256) void batch_sweep_kernel(const SweepArgs* __restrict__ args,
+                                                          const int32_t* __restrict__ kdeg,
+                                                          const BatchItem* __restrict__ items,
+                                                          int32_t nitems) {
+  for (int32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BatchItem w = items[it];
+    const SweepArgs& a = args[w.prob];
+    const int32_t k = kdeg[w.prob];
+    const int32_t q = w.qg * a.tuples;
+    const int32_t qe = min(a.nspec, q + a.tuples);
+    if (w.kind == 0) {               // dimension 0, window form
+      const int64_t g = (int64_t)w.x * blockDim.x + threadIdx.x;
+      if (k == 1) contig_group<1, TIER>(a, g, q, qe);
+      else if (k == 2) contig_group<2, TIER>(a, g, q, qe);
+      else contig_group<3, TIER>(a, g, q, qe);
+    } else if (w.kind == 1) {        // dimension 0, generic form
+      if (k == 1) contig_generic_item<1, TIER>(a, w.x);
+      else if (k == 2) contig_generic_item<2, TIER>(a, w.x);
+      else contig_generic_item<3, TIER>(a, w.x);
+    } else {                         // strided
+      const int32_t col = w.x * 64 + (int32_t)(threadIdx.x & 63);
+      const int32_t chunk = w.z * (int32_t)(blockDim.x >> 6) + (int32_t)(threadIdx.x >> 6);
+      if (k == 1) strided_cell<1, TIER, L>(a, col, chunk, q, qe);
+      else if (k == 2) strided_cell<2, TIER, L>(a, col, chunk, q, qe);
+      else strided_cell<3, TIER, L>(a, col, chunk, q, qe);
+    }
+  }
+}
+
+template <int TIER>
+static hipError_t launch_batch_t(int rows, const SweepArgs* args, const int32_t* kdeg,
+                                 const BatchItem* items, int32_t nitems, int32_t grid,
+                                 hipStream_t st) {
+  switch (rows) {
+    case 1: batch_sweep_kernel<TIER, 1><<<grid, 256, 0, st>>>(args, kdeg, items, nitems); break;
+    case 2: batch_sweep_kernel<TIER, 2><<<grid, 256, 0, st>>>(args, kdeg, items, nitems); break;
+    case 4: batch_sweep_kernel<TIER, 4><<<grid, 256, 0, st>>>(args, kdeg, items, nitems); break;
+    case 8: batch_sweep_kernel<TIER, 8><<<grid, 256, 0, st>>>(args, kdeg, items, nitems); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_sweep(int tier, int rows, const SweepArgs* args, const int32_t* kdeg,
+                              const BatchItem* items, int32_t nitems, int32_t grid,
+                              hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  switch (tier) {
+    case 0: return launch_batch_t<0>(rows, args, kdeg, items, nitems, grid, st);
+    case 1: return launch_batch_t<1>(rows, args, kdeg, items, nitems, grid, st);
+    case 2: return launch_batch_t<2>(rows, args, kdeg, items, nitems, grid, st);
+    case 3: return launch_batch_t<3>(rows, args, kdeg, items, nitems, grid, st);
     default: return hipErrorInvalidValue;
   }
 }

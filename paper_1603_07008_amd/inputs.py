@@ -202,3 +202,31 @@ def fd_directions(count, modes, cells, seed=6):
     """Seeded N(0, 1) directions over all coefficients, [count, modes, cells]."""
     rng = np.random.default_rng(seed)
     return rng.standard_normal((count, modes, cells))
+
+
+def landau_2d(nx, nv, k, dt, kappa, eps=0.01, amp=0.01, steps=1):
+    """2D (x, v) Landau-like problem: x in [0, 2 pi / kappa) periodic,
+    v in [-6, 6) periodic, f0 = (1 + eps cos(kappa x)) M(v),
+    E(x) = amp sin(kappa x) / kappa; Strang X(dt/2) V(dt) X(dt/2)."""
+    p = Problem("landau-2d", (nx, nv), (0.0, -6.0), (2 * math.pi / kappa, 6.0), k, steps)
+    hx, hv = p.h
+    sx = _grid_field(p, (1,), lambda v: v * (0.5 * dt) / hx)
+    sv = _grid_field(p, (0,), lambda x: amp * np.sin(kappa * x) / kappa * dt / hv)
+    p.seq = [Sweep(0, sx, (1,)), Sweep(1, sv, (0,)), Sweep(0, sx, (1,))]
+    p.f0_terms = [(lambda x: 1.0 + eps * np.cos(kappa * x), maxwellian)]
+    p.dt, p.kappa = dt, kappa
+    return p
+
+
+def batched_landau(nprob=512, seed=4, nmin=32, nmax=512):
+    """Independent Landau-like problems with seeded Nx, Nv ~ U{nmin..nmax},
+    k ~ U{1, 2, 3}, dt ~ U[0.02, 0.2], kappa ~ U[0.3, 0.8]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(nprob):
+        nx, nv = (int(v) for v in rng.integers(nmin, nmax + 1, size=2))
+        k = int(rng.integers(1, 4))
+        dt = float(rng.uniform(0.02, 0.2))
+        kappa = float(rng.uniform(0.3, 0.8))
+        out.append(landau_2d(nx, nv, k, dt, kappa))
+    return out

@@ -83,3 +83,22 @@ def test_status_strings(L):
     for st in range(6):
         assert sl.status_string(st)
     assert sl.status_string(99) == "unknown status"
+
+
+def test_batch_rejects_bad_arguments_before_the_device(L):
+    from paper_1603_07008_amd import batch as B
+    BL = B._lib()
+    h = ctypes.c_void_p()
+    n = (ctypes.c_int64 * 4)(8, 8, 8, 8)
+    k = (ctypes.c_int * 2)(2, 2)
+    assert BL.sldg_batch_create(None, 2, 2, n, k, 1, None) == sl.SLDG_ERR_ARG
+    assert BL.sldg_batch_create(ctypes.byref(h), 0, 2, n, k, 1, None) == sl.SLDG_ERR_ARG
+    assert BL.sldg_batch_create(ctypes.byref(h), 2, 9, n, k, 1, None) == sl.SLDG_ERR_ARG
+    assert BL.sldg_batch_create(ctypes.byref(h), 2, 2, n, k, 7, None) == sl.SLDG_ERR_UNSUPPORTED
+    kbad = (ctypes.c_int * 2)(2, 5)
+    assert BL.sldg_batch_create(ctypes.byref(h), 2, 2, n, kbad, 1, None) == sl.SLDG_ERR_UNSUPPORTED
+    nbad = (ctypes.c_int64 * 4)(8, 0, 8, 8)
+    assert BL.sldg_batch_create(ctypes.byref(h), 2, 2, nbad, k, 1, None) == sl.SLDG_ERR_ARG
+    assert BL.sldg_batch_run(None, 1, 0, None) == sl.SLDG_ERR_ARG
+    assert BL.sldg_batch_tune(None, 1) == sl.SLDG_ERR_ARG
+    BL.sldg_batch_destroy(None)

@@ -55,7 +55,7 @@ def test_fastdiv_matches_integer_division():
         exe = os.path.join(d, "fd")
         with open(src, "w") as f:
             f.write(PROG)
-        subprocess.check_call([hipcc, "-O2", "-std=c++17", "-I", CSRC, src, "-o", exe],
+        subprocess.check_call([hipcc, "-O2", "-std=c++17", "-I", CSRC, "-I", os.path.join(ROOT, "include"), src, "-o", exe],
                               stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
         out = subprocess.run([exe], capture_output=True, text=True)
         assert out.returncode == 0, out.stdout

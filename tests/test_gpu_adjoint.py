@@ -117,15 +117,25 @@ def test_gradient_matches_central_finite_differences(sl, n, steps, ndir):
     dirs = inputs.fd_directions(ndir, prob.modes, prob.cells)
     h = 1e-6
     eps = np.finfo(float).eps
+    # the loss is quadratic in c0, so central differences are exact up to the
+    # rounding of the two loss values.  Each value carries the rounding of the
+    # forward run, |dc_T| <~ n_sweeps * eps * |c_T|, which enters the misfit
+    # through (c_T - t): |dL| <~ n_sweeps * eps * vol * sum_m w_m |c_T - t| |c_T|
+    m0, h0 = upload(c0, "fp64")
+    from paper_1603_07008_amd import autograd as AG
+    import torch
+    with torch.no_grad():
+        cT = download(*AG.split_steps(p, seq, steps, m0, h0))
+    w = O.mode_weights(2, prob.k)[:, None]
+    S = vol * float(np.sum(w * np.abs(cT - tgt) * np.abs(cT)))
+    nsw = steps * len(seq)
     worst = 0.0
     for d in dirs:
         Lp = _loss_only(sl, p, seq, steps, c0 + h * d, tgt, vol)
         Lm = _loss_only(sl, p, seq, steps, c0 - h * d, tgt, vol)
         fd = (Lp - Lm) / (2 * h)
         gd = math.fsum((g * d).ravel().tolist())
-        # the loss is quadratic in c0: central differences are exact up to the
-        # rounding of the two loss values (and of the directional derivative)
-        tol = 8 * eps * max(abs(Lp), abs(Lm)) / h + 1e-10 * abs(gd)
+        tol = 2 * nsw * eps * S / h + 1e-10 * abs(gd)
         worst = max(worst, abs(fd - gd) / tol)
         assert abs(fd - gd) <= tol, (fd, gd, tol)
     print(f"finite differences n={n}: worst error / bound = {worst:.3f}")

@@ -1,0 +1,115 @@
+"""Batched sweeps: every problem of a batch matches its own single-problem
+run bit for bit (same kernels, same arithmetic) and the oracle; graph replays
+match eager runs; tuning changes speed, not results."""
+import numpy as np
+import pytest
+
+from oracle import sldg_oracle as O
+from paper_1603_07008_amd import inputs
+from gpu_helpers import download, have_gpu, upload, weighted_rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sl():
+    if not have_gpu():
+        pytest.skip("no HIP device")
+    import paper_1603_07008_amd as sl
+    sl.lib()
+    return sl
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def _problems():
+    probs = inputs.batched_landau(nprob=9, seed=11, nmin=17, nmax=70)
+    probs.append(inputs.landau_2d(64, 40, 2, 0.1, 0.5))     # window path (N0 % 4 == 0)
+    probs.append(inputs.landau_2d(33, 8, 3, 0.15, 0.7))     # generic path
+    return probs
+
+
+def _setup(sl, probs, tier, stream):
+    from paper_1603_07008_amd.batch import Batch
+    b = Batch([p.ns for p in probs], [p.k for p in probs], tier, stream=stream)
+    c0s = [O.to_tier(O.project_separable(p.f0_terms, p.ns, p.los, p.his, p.k), tier) for p in probs]
+    s0 = [upload(c, tier) for c in c0s]
+    s1 = [(m.clone(), h.clone()) for m, h in s0]
+    b.bind(s0, s1)
+    shifts = [[(sw.dep_mask, _dev(sw.sigma)) for sw in p.seq] for p in probs]
+    seq = [(probs[0].seq[q].dim, [shifts[p][q] for p in range(len(probs))]) for q in range(3)]
+    b.set_sequence(seq)
+    return b, c0s, s0, s1, shifts
+
+
+@pytest.mark.parametrize("tier", ["fp64", "fp32", "bf16"])
+def test_batch_matches_single_problem_runs_and_oracle(sl, tier):
+    import torch
+    probs = _problems()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b, c0s, s0, s1, shifts = _setup(sl, probs, tier, stream.cuda_stream)
+        steps = 3
+        res = b.run(steps)
+        stream.synchronize()
+        for i, p in enumerate(probs):
+            got = download(*(s0, s1)[res][i])
+            plan = sl.Plan(p.ns, p.k, tier, stream=stream.cuda_stream)
+            a = upload(c0s[i], tier)
+            c = plan.empty_state()
+            r = plan.split_steps([(sw.dim, sw.dep_mask, shifts[i][q][1]) for q, sw in enumerate(p.seq)],
+                                 steps, a, c)
+            stream.synchronize()
+            single = download(*(a, c)[r])
+            assert np.array_equal(got, single), (i, p.ns, p.k)
+            want = O.run_sequence(c0s[i], p.ns, p.k, [(s.dim, s.sigma, s.dep) for s in p.seq],
+                                  tier, steps)
+            tol = {"fp64": 1e-13, "fp32": 2.0 ** -24, "bf16": 1e-3}[tier]
+            assert weighted_rel_l2(got, want, 2, p.k) <= tol
+
+
+def test_graph_replays_match_eager_and_tuning_keeps_results(sl):
+    import torch
+    probs = _problems()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b, c0s, s0, s1, shifts = _setup(sl, probs, "fp32", stream.cuda_stream)
+        init = [(m.clone(), h.clone()) for m, h in s0]
+        # eager reference: 4 steps, result after each step
+        ref = []
+        for n in range(4):
+            res = b.run(1)
+            stream.synchronize()
+            ref.append([download(*(s0, s1)[res][i]) for i in range(len(probs))])
+            if res == 1:        # move the state back to buffer 0 for the next step
+                for i in range(len(probs)):
+                    s0[i][0].copy_(s1[i][0])
+                    s0[i][1].copy_(s1[i][1])
+        # graph replays from the same start, with eager work in between
+        for i in range(len(probs)):
+            s0[i][0].copy_(init[i][0])
+            s0[i][1].copy_(init[i][1])
+        stream.synchronize()
+        for n in range(4):
+            res = b.run(1, use_graph=True)
+            stream.synchronize()
+            for i in range(len(probs)):
+                assert np.array_equal(download(*(s0, s1)[res][i]), ref[n][i]), (n, i)
+            torch.cuda.synchronize()
+            if res == 1:
+                for i in range(len(probs)):
+                    s0[i][0].copy_(s1[i][0])
+                    s0[i][1].copy_(s1[i][1])
+        # tuning (clobbers buffer 1) then one step from the initial state again
+        shapes = b.tune(reps=2)
+        assert len(shapes) == 3 and all(s["ms"] > 0 for s in shapes)
+        for i in range(len(probs)):
+            s0[i][0].copy_(init[i][0])
+            s0[i][1].copy_(init[i][1])
+        res = b.run(1)
+        stream.synchronize()
+        for i in range(len(probs)):
+            assert np.array_equal(download(*(s0, s1)[res][i]), ref[0][i])
