@@ -11,13 +11,18 @@
  * stored as tensor-product Legendre coefficients, o = k + 1 per dimension:
  *     mode id m = j_0 + o * (j_1 + o * (j_2 + ...)),  0 <= j_e <= k.
  * Mode 0 is the cell mean (the mass mode).  The state is split in two arrays:
- *     mass : double [cells]                 mode 0, always FP64
- *     hi   : T      [o^ndim - 1][cells]     modes 1 .. o^ndim-1, mode-major
+ *     mass : double [n_lo][cells]   the modes of total degree j_0+...+j_{d-1}
+ *                                   below `ndouble`, in increasing mode id
+ *     hi   : T      [n_hi][cells]   all other modes, in increasing mode id
  * where T is the storage type of the plan's tier: double (FP64 tier), float
  * (FP32 tier), bfloat16 or IEEE half (BF16 / FP16 tiers; raw 16-bit words).
- * Keeping the mass mode in FP64 while the others are narrower is the paper's
- * mixed-precision scheme (section II-A, the paragraph on the storage of c_0;
- * section III-A); it conserves the total mass to FP64 rounding.
+ * With the default ndouble = 1 (sldg_plan), `mass` holds mode 0 only and
+ * `hi` holds modes 1 .. o^ndim-1 at planes 0 .. o^ndim-2.  Keeping the mass
+ * mode in FP64 while the others are narrower is the paper's mixed-precision
+ * scheme (section II-A, the paragraph on the storage of c_0; section III-A); it
+ * conserves the total mass to FP64 rounding.  Larger ndouble keeps more
+ * leading coefficients in FP64 (the "number of doubles" of the paper's
+ * section III-A and its tables); ndouble = 0 stores every mode narrow.
  *
  * All state pointers are device pointers (HIP device memory) owned by the
  * caller.  A plan owns only small device tables.  Functions never abort: they
@@ -66,6 +71,22 @@ typedef enum {
  */
 sldg_status sldg_plan(sldg_plan_t* plan, int ndim, const int64_t* ncells, int k,
                       sldg_tier tier, void* stream);
+
+/*
+ * As sldg_plan, with the modes of total degree below `ndouble` stored in FP64
+ * (0 <= ndouble <= ndim*k + 1; see the data model above).  The FP64 modes'
+ * updates are computed in FP64 from exactly widened inputs.  sldg_mass needs
+ * ndouble >= 1.
+ */
+sldg_status sldg_plan_ex(sldg_plan_t* plan, int ndim, const int64_t* ncells, int k,
+                         sldg_tier tier, int ndouble, void* stream);
+
+/* Planes of the `mass` (FP64) and `hi` arrays of a state of this plan. */
+int64_t sldg_lo_planes(sldg_plan_t plan);
+int64_t sldg_hi_planes(sldg_plan_t plan);
+/* Where each mode is stored: out[m] >= 0 is plane out[m] of `hi`, out[m] < 0 is
+ * plane -1-out[m] of `mass`; out is host int32 [o^ndim]. */
+sldg_status sldg_plane_map(sldg_plan_t plan, int32_t* out);
 
 /* Release a plan (synchronises its stream first).  NULL is a no-op. */
 void sldg_plan_destroy(sldg_plan_t plan);
@@ -186,7 +207,7 @@ sldg_status sldg_timing_read(sldg_plan_t plan, int dim, int64_t* launches, doubl
  */
 sldg_status sldg_device_copy(const void* src, void* dst, int64_t bytes, void* stream);
 
-/* Bytes of one state's `hi` array for this plan, (o^ndim - 1) * cells * sizeof(T). */
+/* Bytes of one state's `hi` array for this plan, n_hi * cells * sizeof(T). */
 int64_t sldg_hi_bytes(sldg_plan_t plan);
 
 /*

@@ -57,7 +57,7 @@ def _load():
         lib.oracle_sweep.restype = None
         lib.oracle_sweep.argtypes = [
             ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
-            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
         lib.oracle_sweep_adjoint.restype = None
         lib.oracle_sweep_adjoint.argtypes = [
@@ -216,7 +216,18 @@ def line_strides(ns, dep):
 # Sweep (section II-A update rule), via the plain C loops in sweep.c
 # ---------------------------------------------------------------------------
 
-def sweep(state, ns, k, dim, sigma, dep=(), tier="fp64", sel=None, absolute=False):
+def fp64_modes(ndim, k, ndouble=1):
+    """Modes kept in FP64: total degree j_0 + ... + j_{d-1} below ndouble (the
+    leading coefficients, c_j ~ h^|j| for smooth data, section II-A)."""
+    o = k + 1
+    keep = np.zeros(o ** ndim, dtype=np.uint8)
+    for m in range(o ** ndim):
+        deg = sum((m // o ** e) % o for e in range(ndim))
+        keep[m] = 1 if deg < ndouble else 0
+    return keep
+
+
+def sweep(state, ns, k, dim, sigma, dep=(), tier="fp64", sel=None, absolute=False, ndouble=1):
     """One sLdG projection sweep along `dim`.
 
     state  float64 [o^ndim, cells] (mode-major, cells dimension-0 fastest)
@@ -225,6 +236,7 @@ def sweep(state, ns, k, dim, sigma, dep=(), tier="fp64", sel=None, absolute=Fals
     tier   storage emulation for modes m != 0 ('fp64', 'fp32', 'bf16', 'fp16')
     sel    optional int64 array of output cells; then the result is
            [o^ndim, len(sel)]
+    ndouble number of leading modes kept in FP64 (fp64_modes)
     absolute  use |A|, |B| and |state| (no rounding): gives the magnitude
            sum_l |A_jl x_l| + |B_jl y_l| of every output, which bounds the
            rounding error of any evaluation order of the update
@@ -254,8 +266,9 @@ def sweep(state, ns, k, dim, sigma, dep=(), tier="fp64", sel=None, absolute=Fals
         out = np.empty((M, sel.size))
         nsel, selp = sel.size, sel.ctypes.data
     nsarr = np.asarray(ns, dtype=np.int64)
+    keep = fp64_modes(ndim, k, ndouble)
     _load().oracle_sweep(ndim, nsarr.ctypes.data, k, dim, stride.ctypes.data,
-                         s_tab.ctypes.data, ab_tab.ctypes.data, TIERS[tier],
+                         s_tab.ctypes.data, ab_tab.ctypes.data, TIERS[tier], keep.ctypes.data,
                          state.ctypes.data, out.ctypes.data, nsel, selp)
     return out
 
@@ -300,20 +313,28 @@ def round_tier(x, tier):
     return x
 
 
-def to_tier(state, tier):
-    """Emulated storage of a state: mode 0 stays FP64, the others are rounded."""
+def to_tier(state, tier, ndouble=1, k=None, ndim=None):
+    """Emulated storage of a state: the FP64 modes (by default mode 0 alone)
+    stay, the others are rounded.  k and ndim are needed when ndouble != 1."""
     out = np.array(state, dtype=np.float64, copy=True)
     if tier != "fp64":
-        out[1:] = round_tier(out[1:], tier)
+        if ndouble == 1:
+            keep = np.zeros(out.shape[0], dtype=bool)
+            keep[0] = True
+        else:
+            if k is None or ndim is None:
+                raise ValueError("to_tier needs k and ndim when ndouble != 1")
+            keep = fp64_modes(ndim, k, ndouble).astype(bool)
+        out[~keep] = round_tier(out[~keep], tier)
     return out
 
 
-def run_sequence(state, ns, k, seq, tier="fp64", steps=1):
+def run_sequence(state, ns, k, seq, tier="fp64", steps=1, ndouble=1):
     """Apply a list of sweeps (dim, sigma, dep) `steps` times (section II,
     eq. (1): the split step is a composition of 1D advections)."""
     for _ in range(steps):
         for dim, sigma, dep in seq:
-            state = sweep(state, ns, k, dim, sigma, dep, tier)
+            state = sweep(state, ns, k, dim, sigma, dep, tier, ndouble=ndouble)
     return state
 
 

@@ -21,9 +21,10 @@
  * Storage of the oracle state: one FP64 array [mode][cell], mode id
  * m = j_0 + o*(j_1 + o*(j_2 + ...)), cell id = i_0 + N_0*(i_1 + N_1*(...)),
  * dimension 0 fastest.  Mixed precision (section II-A, the paragraph on storing
- * c_0 in double precision; section III-A) is emulated: every mode except the
- * cell mean m = 0 is rounded to nearest-even onto the storage format after each
- * sweep, while the m = 0 output is computed and kept in FP64.
+ * c_0 in double precision; section III-A, where the number of leading
+ * coefficients kept in double precision varies) is emulated: every mode not
+ * marked `keep` is rounded to nearest-even onto the storage format after each
+ * sweep, the kept modes (by default the cell mean m = 0 alone) stay FP64.
  *
  * Plain loops, no blocking, no reordering; OpenMP only splits the independent
  * output cells between threads and does not change any result.
@@ -84,15 +85,16 @@ static int64_t wrap(int64_t i, int64_t n)
  *                   the displacement does not depend on e (must be 0 for dim)
  *   s_tab, ab_tab   per table entry t: integer shift s_tab[t] and the matrices
  *                   A = ab_tab[t*2*o*o ...], B = A + o*o, row-major [j][l]
- *   tier            storage emulation of the modes m != 0
+ *   tier            storage emulation of the modes with keep[m] == 0
+ *   keep            [o^ndim] 1 for the modes stored (and updated) in FP64
  *   in              [o^ndim][cells]
  *   out             [o^ndim][n_sel]  (n_sel = cells when sel == NULL)
  *   sel             optional list of output cells to compute
  */
 void oracle_sweep(int ndim, const int64_t* n, int k, int dim,
                   const int64_t* line_stride, const int32_t* s_tab,
-                  const double* ab_tab, int tier, const double* in,
-                  double* out, int64_t n_sel, const int64_t* sel)
+                  const double* ab_tab, int tier, const unsigned char* keep,
+                  const double* in, double* out, int64_t n_sel, const int64_t* sel)
 {
     const int o = k + 1;
     int64_t cells = 1, modes = 1, mstride = 1;
@@ -133,7 +135,7 @@ void oracle_sweep(int ndim, const int64_t* n, int k, int dim,
                 acc += A[j * o + l] * in[(m0 + l * mstride) * cells + ca];
             for (int l = 0; l < o; ++l)
                 acc += B[j * o + l] * in[(m0 + l * mstride) * cells + cb];
-            out[m * nout + q] = (m == 0) ? acc : oracle_round_tier(acc, tier);
+            out[m * nout + q] = keep[m] ? acc : oracle_round_tier(acc, tier);
         }
     }
 }

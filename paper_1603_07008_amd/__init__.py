@@ -21,7 +21,8 @@ EXPORTS = ("sldg_plan", "sldg_plan_destroy", "sldg_plan_set_stream", "sldg_line_
            "sldg_status_string", "sldg_last_error", "sldg_timing_enable", "sldg_timing_read",
            "sldg_mass_device", "sldg_device_copy", "sldg_advect_dim_adjoint",
            "sldg_batch_create", "sldg_batch_destroy", "sldg_batch_bind", "sldg_batch_set_sequence",
-           "sldg_batch_run", "sldg_batch_tune", "sldg_batch_get_tuning", "sldg_batch_set_tuning")
+           "sldg_batch_run", "sldg_batch_tune", "sldg_batch_get_tuning", "sldg_batch_set_tuning",
+           "sldg_plan_ex", "sldg_lo_planes", "sldg_hi_planes", "sldg_plane_map")
 
 
 class SldgError(RuntimeError):
@@ -48,6 +49,14 @@ def lib():
     vp, i64, i32, u32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_uint32
     L.sldg_plan.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(i64), i32, i32, vp]
     L.sldg_plan.restype = i32
+    L.sldg_plan_ex.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(i64), i32, i32, i32, vp]
+    L.sldg_plan_ex.restype = i32
+    L.sldg_lo_planes.argtypes = [vp]
+    L.sldg_lo_planes.restype = i64
+    L.sldg_hi_planes.argtypes = [vp]
+    L.sldg_hi_planes.restype = i64
+    L.sldg_plane_map.argtypes = [vp, vp]
+    L.sldg_plane_map.restype = i32
     L.sldg_plan_destroy.argtypes = [vp]
     L.sldg_plan_destroy.restype = None
     L.sldg_plan_set_stream.argtypes = [vp, vp]
@@ -117,7 +126,7 @@ class Plan:
     """A grid + degree + storage tier (sldg_plan).  Calls are enqueued on the
     HIP stream given at creation (default: torch's current stream)."""
 
-    def __init__(self, ncells, k, tier="fp32", stream=None):
+    def __init__(self, ncells, k, tier="fp32", stream=None, ndouble=1):
         self.ncells = tuple(int(n) for n in ncells)
         self.ndim = len(self.ncells)
         self.k = int(k)
@@ -129,11 +138,14 @@ class Plan:
         if tier not in TIERS:
             raise ValueError(f"unknown tier {tier!r}")
         self.stream = _current_stream() if stream is None else stream
+        self.ndouble = int(ndouble)
         h = ctypes.c_void_p()
         arr = (ctypes.c_int64 * self.ndim)(*self.ncells)
-        _check(lib().sldg_plan(ctypes.byref(h), self.ndim, arr, self.k, TIERS[tier],
-                               ctypes.c_void_p(self.stream)), "sldg_plan")
+        _check(lib().sldg_plan_ex(ctypes.byref(h), self.ndim, arr, self.k, TIERS[tier],
+                                  self.ndouble, ctypes.c_void_p(self.stream)), "sldg_plan_ex")
         self._h = h
+        self.n_lo = int(lib().sldg_lo_planes(h))
+        self.n_hi = int(lib().sldg_hi_planes(h))
 
     # -- helpers -----------------------------------------------------------
     @property
@@ -145,11 +157,19 @@ class Plan:
     def hi_bytes(self):
         return int(lib().sldg_hi_bytes(self.handle))
 
+    def plane_map(self):
+        """Per mode id: >= 0 plane of `hi`, < 0 plane -1-v of `mass` (sldg_plane_map)."""
+        out = (ctypes.c_int32 * self.modes)()
+        _check(lib().sldg_plane_map(self.handle, out), "sldg_plane_map")
+        return list(out)
+
     def empty_state(self, device="cuda"):
-        """Uninitialised (mass, hi) device tensors of this plan's layout."""
+        """Uninitialised (mass, hi) device tensors of this plan's layout: mass is
+        [cells] when it holds mode 0 alone, else [n_lo, cells]."""
         import torch
-        mass = torch.empty(self.cells, dtype=torch.float64, device=device)
-        hi = torch.empty((self.modes - 1, self.cells), dtype=hi_dtype(self.tier), device=device)
+        shape = (self.cells,) if self.n_lo == 1 else (self.n_lo, self.cells)
+        mass = torch.empty(shape, dtype=torch.float64, device=device)
+        hi = torch.empty((self.n_hi, self.cells), dtype=hi_dtype(self.tier), device=device)
         return mass, hi
 
     def _check_state(self, mass, hi, what):
@@ -158,8 +178,10 @@ class Plan:
             raise TypeError(f"{what}: state buffers must be torch tensors")
         if not (mass.is_cuda and hi.is_cuda):
             raise ValueError(f"{what}: state buffers must be device tensors")
-        if mass.dtype != torch.float64 or not mass.is_contiguous() or mass.numel() < self.cells:
-            raise ValueError(f"{what}: mass must be contiguous float64 with >= {self.cells} elements")
+        if mass.dtype != torch.float64 or not mass.is_contiguous() or \
+                mass.numel() < self.n_lo * self.cells:
+            raise ValueError(f"{what}: mass must be contiguous float64 with >= "
+                             f"{self.n_lo * self.cells} elements")
         if hi.dtype != hi_dtype(self.tier) or not hi.is_contiguous() or \
                 hi.numel() * hi.element_size() < self.hi_bytes():
             raise ValueError(f"{what}: hi must be contiguous {hi_dtype(self.tier)} of "

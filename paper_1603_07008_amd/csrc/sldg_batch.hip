@@ -36,6 +36,8 @@ struct sldg_batch_s {
   int32_t* d_s = nullptr;
   double* d_ab = nullptr;
   int32_t* d_k = nullptr;
+  int32_t* d_pmap = nullptr;              // mode -> plane maps (FP64 cell mean only), per problem
+  std::vector<int64_t> pmap_off;
   // launch shape per sweep of the sequence
   std::vector<int> rows, tuples;
   std::vector<double> tuned_ms;
@@ -73,6 +75,7 @@ void free_batch(sldg_batch_s* b) {
   if (b->d_s) (void)hipFree(b->d_s);
   if (b->d_ab) (void)hipFree(b->d_ab);
   if (b->d_k) (void)hipFree(b->d_k);
+  if (b->d_pmap) (void)hipFree(b->d_pmap);
   delete b;
 }
 
@@ -95,10 +98,11 @@ sldg_status build_sweep(sldg_batch_s* b, int q) {
       int64_t ntab = 0;
       describe_grid(b->ndim, ext(b, p), o, b->modes[p], dim, mask, b->rows[q], b->tuples[q], a,
                     ntab);
-      a.in_mass = b->mass[src][p];
+      a.in_lo = b->mass[src][p];
       a.in_hi = b->hi[src][p];
-      a.out_mass = b->mass[1 - src][p];
+      a.out_lo = b->mass[1 - src][p];
       a.out_hi = b->hi[1 - src][p];
+      a.pmap = b->d_pmap + b->pmap_off[p];
       a.s_tab = b->d_s + b->tab_off[(size_t)q * b->nprob + p];
       a.ab_tab = b->d_ab + b->ab_off[(size_t)q * b->nprob + p];
       a.ab_cs = ntab;
@@ -220,6 +224,16 @@ sldg_status sldg_batch_create(sldg_batch_t* out, int nprob, int ndim, const int6
   int ncu = 0;
   if (e == hipSuccess)
     e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device);
+  // mode -> plane maps: mode 0 in the FP64 array, mode m >= 1 at hi plane m-1
+  std::vector<int32_t> pm;
+  for (int p = 0; p < nprob; ++p) {
+    b->pmap_off.push_back((int64_t)pm.size());
+    pm.push_back(-1);
+    for (int64_t m = 1; m < b->modes[p]; ++m) pm.push_back((int32_t)(m - 1));
+  }
+  if (e == hipSuccess) e = hipMalloc(&b->d_pmap, sizeof(int32_t) * pm.size());
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_pmap, pm.data(), sizeof(int32_t) * pm.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc(&b->d_k, sizeof(int32_t) * nprob);
   if (e == hipSuccess) {
     std::vector<int32_t> kk(b->k.begin(), b->k.end());

@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "sldg.h"
 #include "sldg_internal.h"
@@ -24,7 +25,12 @@ struct sldg_plan_s {
   int device;
   int64_t cells;
   int64_t modes;          // o^ndim
+  int ndouble;            // modes of total degree < ndouble are stored in FP64
+  int64_t n_lo, n_hi;     // planes in the FP64 array and in the storage-type array
+  int64_t lo_bytes;
   int64_t hi_bytes;
+  int32_t* d_pmap;        // per mode: >= 0 hi plane, < 0 lo plane -1-v
+  std::vector<int32_t> h_pmap;
   int64_t table_cap;      // entries of the per-line table
   int32_t* d_s;
   double* d_ab;
@@ -143,7 +149,7 @@ namespace {
 constexpr int kMaxTimed = 4096;
 
 sldg_status check_sweep(const sldg_plan_s* p, int dim, const double* shift, uint32_t dep_mask,
-                        const double* in_mass, const void* in_hi, const double* out_mass,
+                        const double* in_lo, const void* in_hi, const double* out_lo,
                         const void* out_hi) {
   if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
   if (dim < 0 || dim >= p->ndim)
@@ -152,23 +158,24 @@ sldg_status check_sweep(const sldg_plan_s* p, int dim, const double* shift, uint
     return fail(SLDG_ERR_ARG, "dep_mask 0x%x names dimensions beyond ndim=%d", dep_mask, p->ndim);
   if (dep_mask & (1u << dim))
     return fail(SLDG_ERR_ARG, "dep_mask 0x%x contains the swept dimension %d", dep_mask, dim);
-  if (!shift || !in_mass || !in_hi || !out_mass || !out_hi)
-    return fail(SLDG_ERR_ARG, "null state or shift pointer");
-  const int64_t mb = p->cells * 8, hb = p->hi_bytes;
-  const void* ins[2] = {in_mass, in_hi};
+  if (!shift) return fail(SLDG_ERR_ARG, "null shift pointer");
+  if (p->n_lo > 0 && (!in_lo || !out_lo)) return fail(SLDG_ERR_ARG, "null FP64-mode (mass) pointer");
+  if (p->n_hi > 0 && (!in_hi || !out_hi)) return fail(SLDG_ERR_ARG, "null state (hi) pointer");
+  const int64_t mb = p->lo_bytes, hb = p->hi_bytes;
+  const void* ins[2] = {in_lo, in_hi};
   const int64_t insz[2] = {mb, hb};
-  const void* outs[2] = {out_mass, out_hi};
+  const void* outs[2] = {out_lo, out_hi};
   const int64_t outsz[2] = {mb, hb};
   for (int i = 0; i < 2; ++i)
     for (int o = 0; o < 2; ++o)
-      if (overlap(ins[i], insz[i], outs[o], outsz[o]))
+      if (insz[i] > 0 && outsz[o] > 0 && overlap(ins[i], insz[i], outs[o], outsz[o]))
         return fail(SLDG_ERR_ALIAS, "output buffer overlaps an input buffer");
-  if (overlap(out_mass, mb, out_hi, hb))
+  if (mb > 0 && hb > 0 && overlap(out_lo, mb, out_hi, hb))
     return fail(SLDG_ERR_ALIAS, "out_mass overlaps out_hi");
   int64_t sb = 8;
   for (int e = 0; e < p->ndim; ++e)
     if (dep_mask & (1u << e)) sb *= p->n[e];
-  if (overlap(shift, sb, out_mass, mb) || overlap(shift, sb, out_hi, hb))
+  if ((mb > 0 && overlap(shift, sb, out_lo, mb)) || (hb > 0 && overlap(shift, sb, out_hi, hb)))
     return fail(SLDG_ERR_ALIAS, "shift overlaps an output buffer");
   return SLDG_OK;
 }
@@ -187,12 +194,13 @@ void free_plan(sldg_plan_s* p) {
   if (p->d_ab) (void)hipFree(p->d_ab);
   if (p->d_mass_part) (void)hipFree(p->d_mass_part);
   if (p->d_mass_out) (void)hipFree(p->d_mass_out);
+  if (p->d_pmap) (void)hipFree(p->d_pmap);
   if (p->h_mass_out) (void)hipHostFree(p->h_mass_out);
   delete p;
 }
 
 sldg_status run_sweep(sldg_plan_s* p, int dim, const double* shift, uint32_t dep_mask,
-                      const double* in_mass, const void* in_hi, double* out_mass, void* out_hi,
+                      const double* in_lo, const void* in_hi, double* out_lo, void* out_hi,
                       bool adjoint = false) {
   SweepArgs a{};
   int64_t ntab = 0;
@@ -203,10 +211,12 @@ sldg_status run_sweep(sldg_plan_s* p, int dim, const double* shift, uint32_t dep
   hipError_t e = launch_line_tables(p->k, ntab, p->n[dim], shift, p->d_s, p->d_ab, true,
                                     adjoint, p->stream);
   if (e != hipSuccess) return device_error(e, "line-table launch");
-  a.in_mass = in_mass;
+  a.in_lo = in_lo;
   a.in_hi = in_hi;
-  a.out_mass = out_mass;
+  a.out_lo = out_lo;
   a.out_hi = out_hi;
+  a.pmap = p->d_pmap;
+  a.wide_fp64 = p->ndouble > 1 ? 1 : 0;
   a.s_tab = p->d_s;
   a.ab_tab = p->d_ab;
   a.ab_cs = ntab;
@@ -257,12 +267,19 @@ const char* sldg_last_error(void) { return last_error_text(); }
 
 sldg_status sldg_plan(sldg_plan_t* out, int ndim, const int64_t* ncells, int k, sldg_tier tier,
                       void* stream) {
+  return sldg_plan_ex(out, ndim, ncells, k, tier, 1, stream);
+}
+
+sldg_status sldg_plan_ex(sldg_plan_t* out, int ndim, const int64_t* ncells, int k,
+                         sldg_tier tier, int ndouble, void* stream) {
   if (!out) return fail(SLDG_ERR_ARG, "plan out-pointer is NULL");
   *out = nullptr;
   if (ndim < 1 || ndim > kMaxDim) return fail(SLDG_ERR_ARG, "ndim %d not in [1, %d]", ndim, kMaxDim);
   if (!ncells) return fail(SLDG_ERR_ARG, "ncells is NULL");
   if (k < 1 || k > 3) return fail(SLDG_ERR_UNSUPPORTED, "degree k=%d not in [1, 3]", k);
   if ((int)tier < 0 || (int)tier > 3) return fail(SLDG_ERR_UNSUPPORTED, "tier %d unknown", (int)tier);
+  if (ndouble < 0 || ndouble > ndim * k + 1)
+    return fail(SLDG_ERR_ARG, "ndouble %d not in [0, %d]", ndouble, ndim * k + 1);
   int64_t cells = 1, min_n = INT64_MAX;
   for (int e = 0; e < ndim; ++e) {
     if (ncells[e] < 1) return fail(SLDG_ERR_ARG, "ncells[%d] = %lld < 1", e, (long long)ncells[e]);
@@ -273,7 +290,7 @@ sldg_status sldg_plan(sldg_plan_t* out, int ndim, const int64_t* ncells, int k, 
       return fail(SLDG_ERR_UNSUPPORTED, "grid of >= 2^31 cells is not supported");
     min_n = std::min(min_n, ncells[e]);
   }
-  sldg_plan_s* p = new (std::nothrow) sldg_plan_s();
+  sldg_plan_s* p = new (std::nothrow) sldg_plan_s{};
   if (!p) return fail(SLDG_ERR_NOMEM, "host allocation failed");
   p->ndim = ndim;
   for (int e = 0; e < ndim; ++e) p->n[e] = ncells[e];
@@ -284,7 +301,16 @@ sldg_status sldg_plan(sldg_plan_t* out, int ndim, const int64_t* ncells, int k, 
   p->cells = cells;
   p->modes = 1;
   for (int e = 0; e < ndim; ++e) p->modes *= p->o;
-  p->hi_bytes = (p->modes - 1) * cells * elem_size(tier);
+  p->ndouble = ndouble;
+  p->h_pmap.resize(p->modes);
+  p->n_lo = p->n_hi = 0;
+  for (int64_t m = 0; m < p->modes; ++m) {
+    int deg = 0;
+    for (int64_t r = m, e = 0; e < ndim; ++e, r /= p->o) deg += (int)(r % p->o);
+    p->h_pmap[m] = deg < ndouble ? (int32_t)(-1 - p->n_lo++) : (int32_t)(p->n_hi++);
+  }
+  p->lo_bytes = p->n_lo * cells * 8;
+  p->hi_bytes = p->n_hi * cells * elem_size(tier);
   p->table_cap = cells / min_n;     // the most lines any sweep can have
   p->rows_per_thread = 2;
   p->tuples_per_thread = 0;
@@ -308,6 +334,9 @@ sldg_status sldg_plan(sldg_plan_t* out, int ndim, const int64_t* ncells, int k, 
   if (e == hipSuccess) e = hipMalloc(&p->d_mass_part, sizeof(double) * 2 * p->mass_nblocks);
   if (e == hipSuccess) e = hipMalloc(&p->d_mass_out, sizeof(double) * 2);
   if (e == hipSuccess) e = hipHostMalloc(&p->h_mass_out, sizeof(double) * 2, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc(&p->d_pmap, sizeof(int32_t) * p->modes);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_pmap, p->h_pmap.data(), sizeof(int32_t) * p->modes, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     const bool nomem = (e == hipErrorOutOfMemory);
     free_plan(p);
@@ -332,6 +361,16 @@ sldg_status sldg_plan_set_stream(sldg_plan_t p, void* stream) {
 }
 
 int64_t sldg_hi_bytes(sldg_plan_t p) { return p ? p->hi_bytes : -1; }
+
+int64_t sldg_lo_planes(sldg_plan_t p) { return p ? p->n_lo : -1; }
+
+int64_t sldg_hi_planes(sldg_plan_t p) { return p ? p->n_hi : -1; }
+
+sldg_status sldg_plane_map(sldg_plan_t p, int32_t* out) {
+  if (!p || !out) return fail(SLDG_ERR_ARG, "null pointer");
+  std::copy(p->h_pmap.begin(), p->h_pmap.end(), out);
+  return ok();
+}
 
 sldg_status sldg_timing_enable(sldg_plan_t p, int enable) {
   if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
@@ -434,6 +473,7 @@ sldg_status sldg_device_copy(const void* src, void* dst, int64_t bytes, void* st
 
 sldg_status sldg_mass_device(sldg_plan_t p, const double* mass, double* out_dev) {
   if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
+  if (p->n_lo < 1) return fail(SLDG_ERR_ARG, "mode 0 is not stored in FP64 (ndouble = 0)");
   if (!mass || !out_dev) return fail(SLDG_ERR_ARG, "null pointer");
   if (overlap(out_dev, 16, mass, p->cells * 8))
     return fail(SLDG_ERR_ALIAS, "out_dev overlaps the mass array");
@@ -444,6 +484,7 @@ sldg_status sldg_mass_device(sldg_plan_t p, const double* mass, double* out_dev)
 
 sldg_status sldg_mass(sldg_plan_t p, const double* mass, double out[2]) {
   if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
+  if (p->n_lo < 1) return fail(SLDG_ERR_ARG, "mode 0 is not stored in FP64 (ndouble = 0)");
   if (!mass || !out) return fail(SLDG_ERR_ARG, "null pointer");
   hipError_t e = launch_mass(mass, p->cells, p->d_mass_part, p->mass_nblocks, p->d_mass_out,
                              p->stream);

@@ -47,10 +47,12 @@ struct LineMap {
 };
 
 struct SweepArgs {
-  const double* in_mass;
-  const void* in_hi;
-  double* out_mass;
+  const double* in_lo;    // FP64 modes (mode-major planes, increasing mode id)
+  const void* in_hi;      // the other modes, in the tier's storage type
+  double* out_lo;
   void* out_hi;
+  const int32_t* pmap;    // per mode id: >= 0 plane in hi, < 0 plane -1-v in lo
+  int32_t wide_fp64;      // 1: more than the cell mean may be FP64 (general kernels)
   const int32_t* s_tab;   // per table entry: s mod N, in [0, N)
   const double* ab_tab;   // per table entry t: A then B, (k+1)^2 each, row-major,
                           // component e of entry t at ab_tab[e * ab_cs + t]

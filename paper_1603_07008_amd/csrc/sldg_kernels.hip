@@ -15,6 +15,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "ab_poly.h"
 #include "sldg_internal.h"
 
@@ -169,17 +171,73 @@ __device__ __forceinline__ int32_t table_index(const LineMap& m, int32_t lo, int
 }
 
 // ---------------------------------------------------------------------------
-// Raw storage of one cell's o modes (along the swept dimension) and the
-// arithmetic on it.  Values stay in their storage type in registers and are
-// widened exactly when used.
+// Modes of one spectator tuple (modes m0 + l * mstride, l = 0..k, the swept
+// index j_d varying) and where they are stored.  The modes of total degree
+// below the plan's "number of FP64 modes" live in the FP64 array `lo`, the
+// others in the storage type of the tier (array `hi`); within a tuple the FP64
+// modes are the leading ones (the total degree grows with j_d).  ND, the
+// number of leading FP64 modes, is a compile-time parameter of the per-tuple
+// code (the paper's mixed-precision scheme keeps c_0 in FP64, section II-A;
+// its experiments vary how many leading coefficients are FP64, section III-A).
+// Values stay in their storage type in registers and are widened exactly when
+// used.
 // ---------------------------------------------------------------------------
 
-template <int K, int TIER, bool MASS>
+struct TupleMap {
+  int32_t idx[4];   // plane index in lo (l < nd) or hi (l >= nd)
+  int32_t nd;       // leading FP64 modes of the tuple
+};
+
+__device__ __forceinline__ TupleMap tuple_map(const SweepArgs& a, int32_t m0, int32_t ms,
+                                              int O) {
+  TupleMap t;
+  t.nd = 0;
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    if (l < O) {
+      // uniform across the wave: keep it (and the plane pointers) scalar
+      const int32_t v = __builtin_amdgcn_readfirstlane(a.pmap[m0 + l * ms]);
+      t.idx[l] = v < 0 ? -1 - v : v;
+      t.nd += v < 0 ? 1 : 0;
+    }
+  }
+  return t;
+}
+
+template <int K, int TIER, int ND>
 struct Raw {
   static constexpr int O = K + 1;
   using T = typename Tier<TIER>::T;
-  double m;   // mode j = 0 when MASS
-  T h[O];     // modes (h[0] unused when MASS)
+  double d[O];   // modes l < ND
+  T h[O];        // modes l >= ND
+};
+
+// Copy of the fields a tuple with ND leading FP64 modes uses (whole-struct
+// copies of partly used register structs end up in scratch memory).
+template <int K, int TIER, int ND>
+__device__ __forceinline__ void copy_raw(Raw<K, TIER, ND>& dst, const Raw<K, TIER, ND>& src) {
+#pragma unroll
+  for (int l = 0; l < K + 1; ++l) {
+    if (l < ND) dst.d[l] = src.d[l];
+    else dst.h[l] = src.h[l];
+  }
+}
+
+// FP64 rows j < ND of A and B (the rows of the modes stored in FP64, whose
+// update is FP64 throughout).
+template <int K, int ND>
+struct Rows64 {
+  static constexpr int O = K + 1;
+  double A[ND > 0 ? ND : 1][O], B[ND > 0 ? ND : 1][O];
+  __device__ __forceinline__ void load(const double* ab, int64_t cs) {
+#pragma unroll
+    for (int j = 0; j < ND; ++j)
+#pragma unroll
+      for (int l = 0; l < O; ++l) {
+        A[j][l] = ab[(j * O + l) * cs];
+        B[j][l] = ab[(O * O + j * O + l) * cs];
+      }
+  }
 };
 
 template <int K, int TIER>
@@ -187,12 +245,13 @@ struct Mat {
   static constexpr int O = K + 1;
   using T = typename Tier<TIER>::T;
   using Acc = typename Tier<TIER>::Acc;
-  double Ad[O], Bd[O];         // mass row in FP64 (used by the tuple holding mode 0)
   Acc Aa[O][O], Ba[O][O];      // all rows in the arithmetic type
+  const double* ab;            // the table entry (component e at ab[e * cs])
+  int64_t cs;
 
-  // Matrices of table entry ab (component e at ab[e * cs]); the FP64 mass row
-  // only when the thread handles the tuple that holds mode 0.
-  __device__ __forceinline__ void load(const double* ab, int64_t cs, bool mass_row) {
+  __device__ __forceinline__ void load(const double* ab_, int64_t cs_) {
+    ab = ab_;
+    cs = cs_;
 #pragma unroll
     for (int j = 0; j < O; ++j)
 #pragma unroll
@@ -200,41 +259,35 @@ struct Mat {
         Aa[j][l] = (Acc)ab[(j * O + l) * cs];
         Ba[j][l] = (Acc)ab[(O * O + j * O + l) * cs];
       }
-    if (mass_row) {
-#pragma unroll
-      for (int l = 0; l < O; ++l) {
-        Ad[l] = ab[l * cs];
-        Bd[l] = ab[(O * O + l) * cs];
-      }
-    }
   }
 
-  template <bool MASS>
-  __device__ __forceinline__ static double wide(const Raw<K, TIER, MASS>& r, int l) {
-    return (MASS && l == 0) ? r.m : widen(r.h[l]);
+  template <int ND>
+  __device__ __forceinline__ static double wide(const Raw<K, TIER, ND>& r, int l) {
+    return l < ND ? r.d[l] : widen(r.h[l]);
   }
-  template <bool MASS>
-  __device__ __forceinline__ static Acc acc_of(const Raw<K, TIER, MASS>& r, int l) {
-    if (MASS && l == 0) return (Acc)r.m;
+  template <int ND>
+  __device__ __forceinline__ static Acc acc_of(const Raw<K, TIER, ND>& r, int l) {
+    if (l < ND) return (Acc)r.d[l];
     if constexpr (sizeof(Acc) == 8) return widen(r.h[l]);
     else return (Acc)r.h[l];
   }
 
   // Output mode j of the update from the two source cells x (cell i-s) and
-  // y (cell i-s-1).  The mass row of the tuple holding mode 0 is FP64 throughout.
-  template <bool MASS>
-  __device__ __forceinline__ double mass_out(const Raw<K, TIER, MASS>& x,
-                                             const Raw<K, TIER, MASS>& y) const {
+  // y (cell i-s-1): FP64 for the FP64-stored modes, else in the arithmetic type.
+  template <int ND>
+  __device__ __forceinline__ static double out64(const Rows64<K, ND>& R, int j,
+                                                 const Raw<K, TIER, ND>& x,
+                                                 const Raw<K, TIER, ND>& y) {
     double acc = 0.0;
 #pragma unroll
-    for (int l = 0; l < O; ++l) acc = fma(Ad[l], wide(x, l), acc);
+    for (int l = 0; l < O; ++l) acc = fma(R.A[j][l], wide(x, l), acc);
 #pragma unroll
-    for (int l = 0; l < O; ++l) acc = fma(Bd[l], wide(y, l), acc);
+    for (int l = 0; l < O; ++l) acc = fma(R.B[j][l], wide(y, l), acc);
     return acc;
   }
-  template <bool MASS>
-  __device__ __forceinline__ T hi_out(int j, const Raw<K, TIER, MASS>& x,
-                                      const Raw<K, TIER, MASS>& y) const {
+  template <int ND>
+  __device__ __forceinline__ T out_t(int j, const Raw<K, TIER, ND>& x,
+                                     const Raw<K, TIER, ND>& y) const {
     Acc acc = 0;
 #pragma unroll
     for (int l = 0; l < O; ++l) acc = fma(Aa[j][l], acc_of(x, l), acc);
@@ -244,42 +297,78 @@ struct Mat {
   }
 };
 
-// Plane pointers of one spectator tuple: mode m0 + l*mstride for l = 0..k.
-template <int K, int TIER, bool MASS>
+// Plane pointers of one spectator tuple.
+template <int K, int TIER, int ND>
 struct Planes {
   static constexpr int O = K + 1;
   using T = typename Tier<TIER>::T;
-  const T* in[O];
-  T* out[O];
-  const double* in_mass;
-  double* out_mass;
+  const double* ind[O];
+  double* outd[O];
+  const T* inh[O];
+  T* outh[O];
 
-  __device__ __forceinline__ void bind(const SweepArgs& a, int64_t m0, int32_t mstride) {
+  __device__ __forceinline__ void bind(const SweepArgs& a, const TupleMap& tm) {
     const T* hin = reinterpret_cast<const T*>(a.in_hi);
     T* hout = reinterpret_cast<T*>(a.out_hi);
 #pragma unroll
     for (int l = 0; l < O; ++l) {
-      const int64_t m = m0 + (int64_t)l * mstride;
-      const int64_t off = (m - 1) * a.cells;      // mode m >= 1 lives at plane m-1
-      in[l] = (MASS && l == 0) ? nullptr : hin + off;
-      out[l] = (MASS && l == 0) ? nullptr : hout + off;
+      const int64_t off = (int64_t)tm.idx[l] * a.cells;
+      if (l < ND) {
+        ind[l] = a.in_lo + off;
+        outd[l] = a.out_lo + off;
+      } else {
+        inh[l] = hin + off;
+        outh[l] = hout + off;
+      }
     }
-    in_mass = a.in_mass;
-    out_mass = a.out_mass;
   }
-  __device__ __forceinline__ void load(int64_t c, Raw<K, TIER, MASS>& r) const {
-    if (MASS) r.m = in_mass[c];
+  __device__ __forceinline__ void load(int64_t c, Raw<K, TIER, ND>& r) const {
 #pragma unroll
-    for (int l = (MASS ? 1 : 0); l < O; ++l) r.h[l] = in[l][c];
+    for (int l = 0; l < O; ++l) {
+      if (l < ND) r.d[l] = ind[l][c];
+      else r.h[l] = inh[l][c];
+    }
   }
-  __device__ __forceinline__ void store(int64_t c, const Mat<K, TIER>& M,
-                                        const Raw<K, TIER, MASS>& x,
-                                        const Raw<K, TIER, MASS>& y) const {
-    if (MASS) out_mass[c] = M.mass_out(x, y);
+  __device__ __forceinline__ void copy_from(const Planes& o) {
 #pragma unroll
-    for (int j = (MASS ? 1 : 0); j < O; ++j) out[j][c] = M.hi_out(j, x, y);
+    for (int l = 0; l < O; ++l) {
+      if (l < ND) {
+        ind[l] = o.ind[l];
+        outd[l] = o.outd[l];
+      } else {
+        inh[l] = o.inh[l];
+        outh[l] = o.outh[l];
+      }
+    }
+  }
+  __device__ __forceinline__ void store(int64_t c, const Mat<K, TIER>& M, const Rows64<K, ND>& R,
+                                        const Raw<K, TIER, ND>& x,
+                                        const Raw<K, TIER, ND>& y) const {
+#pragma unroll
+    for (int j = 0; j < O; ++j) {
+      if (j < ND) outd[j][c] = Mat<K, TIER>::out64(R, j, x, y);
+      else outh[j][c] = M.out_t(j, x, y);
+    }
   }
 };
+
+// Dispatch on the number of leading FP64 modes of a tuple (0 .. NDMAX).
+// Kernels are instantiated with NDMAX = 1 (the cell mean alone in FP64, or
+// nothing) and with NDMAX = k+1 (any number of FP64 modes), so the common
+// case does not carry the register cost of the all-FP64 tuple variants.
+template <int NDMAX, class F>
+__device__ __forceinline__ void dispatch_nd(int nd, F&& f) {
+  if (nd == 0) {
+    f(std::integral_constant<int, 0>{});
+  } else if constexpr (NDMAX == 1) {
+    f(std::integral_constant<int, 1>{});
+  } else {
+    if (nd == 1) f(std::integral_constant<int, 1>{});
+    else if (nd == 2) f(std::integral_constant<int, (NDMAX >= 2 ? 2 : 1)>{});
+    else if (nd == 3) f(std::integral_constant<int, (NDMAX >= 3 ? 3 : 1)>{});
+    else f(std::integral_constant<int, (NDMAX >= 4 ? 4 : 1)>{});
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Sweep along dimension 0, generic form (any N_0, any alignment).  One wave
@@ -287,16 +376,17 @@ struct Planes {
 // registers), lanes walk the line's cells.
 // ---------------------------------------------------------------------------
 
-template <int K, int TIER, bool MASS>
-__device__ __forceinline__ void contig_line(const SweepArgs& a, int64_t line, int32_t sp,
+template <int K, int TIER, int ND>
+__device__ __forceinline__ void contig_line(const SweepArgs& a, int64_t line, const TupleMap& tm,
                                             int lane) {
-  constexpr int O = K + 1;
   Mat<K, TIER> M;
-  Planes<K, TIER, MASS> pl;
+  Rows64<K, ND> R;
+  Planes<K, TIER, ND> pl;
   const int32_t t = __builtin_amdgcn_readfirstlane(table_index(a.map, 0, (int32_t)line));
   const int32_t s = __builtin_amdgcn_readfirstlane(a.s_tab[t]);
-  M.load(a.ab_tab + t, a.ab_cs, sp == 0);
-  pl.bind(a, (int64_t)sp * O, 1);
+  M.load(a.ab_tab + t, a.ab_cs);
+  R.load(a.ab_tab + t, a.ab_cs);
+  pl.bind(a, tm);
   const int32_t N = a.N;
   const int64_t base = line * (int64_t)N;
   for (int32_t i = lane; i < N; i += 64) {
@@ -304,24 +394,32 @@ __device__ __forceinline__ void contig_line(const SweepArgs& a, int64_t line, in
     if (ia < 0) ia += N;
     int32_t ib = ia - 1;
     if (ib < 0) ib += N;
-    Raw<K, TIER, MASS> x, y;
+    Raw<K, TIER, ND> x, y;
     pl.load(base + ia, x);
     pl.load(base + ib, y);
-    pl.store(base + i, M, x, y);
+    pl.store(base + i, M, R, x, y);
   }
 }
 
-template <int K, int TIER>
-__global__ __launch_bounds__(256) void sweep_contig_kernel(SweepArgs a) {
+template <int K, int TIER, int NDMAX>
+__device__ __forceinline__ void contig_generic_item(const SweepArgs& a, int64_t item4) {
+  constexpr int O = K + 1;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int64_t nlines = (int64_t)a.Q;
-  const int64_t item = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t item = item4 * 4 + wave;
   if (item >= nlines * a.nspec) return;
   const int32_t sp = (int32_t)(item / nlines);
   const int64_t line = item - (int64_t)sp * nlines;
-  if (sp == 0) contig_line<K, TIER, true>(a, line, sp, lane);
-  else contig_line<K, TIER, false>(a, line, sp, lane);
+  const TupleMap tm = tuple_map(a, sp * O, 1, O);
+  dispatch_nd<NDMAX>(tm.nd, [&](auto ndc) {
+    contig_line<K, TIER, decltype(ndc)::value>(a, line, tm, lane);
+  });
+}
+
+template <int K, int TIER, int NDMAX>
+__global__ __launch_bounds__(256) void sweep_contig_kernel(SweepArgs a) {
+  contig_generic_item<K, TIER, NDMAX>(a, (int64_t)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -382,73 +480,91 @@ __device__ __forceinline__ void store4(T* dst, const T (&v)[4]) {
 // divergent control flow.
 template <class T>
 __device__ __forceinline__ void window5(const Blk4<T>& b0, const Blk4<T>& b1, int d, T (&w)[5]) {
-  const T t[8] = {b0.v[0], b0.v[1], b0.v[2], b0.v[3], b1.v[0], b1.v[1], b1.v[2], b1.v[3]};
   const bool s1 = (d & 1) != 0, s2 = (d & 2) != 0;
-  T u1[7];
-#pragma unroll
-  for (int i = 0; i < 7; ++i) u1[i] = s1 ? t[i + 1] : t[i];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) w[i] = s2 ? u1[i + 2] : u1[i];
+  const T u0 = s1 ? b0.v[1] : b0.v[0];
+  const T u1 = s1 ? b0.v[2] : b0.v[1];
+  const T u2 = s1 ? b0.v[3] : b0.v[2];
+  const T u3 = s1 ? b1.v[0] : b0.v[3];
+  const T u4 = s1 ? b1.v[1] : b1.v[0];
+  const T u5 = s1 ? b1.v[2] : b1.v[1];
+  const T u6 = s1 ? b1.v[3] : b1.v[2];
+  w[0] = s2 ? u2 : u0;
+  w[1] = s2 ? u3 : u1;
+  w[2] = s2 ? u4 : u2;
+  w[3] = s2 ? u5 : u3;
+  w[4] = s2 ? u6 : u4;
 }
 
-template <int K, int TIER, bool MASS>
+template <int K, int TIER, int ND>
 struct Win {               // the 5-cell source window of one tuple
-  Raw<K, TIER, MASS> w[5];
+  Raw<K, TIER, ND> w[5];
 };
 
-template <int K, int TIER, bool MASS>
-__device__ __forceinline__ void contig_load(const SweepArgs& a, int32_t m0, int64_t lb,
+template <int K, int TIER, int ND>
+__device__ __forceinline__ void contig_load(const Planes<K, TIER, ND>& pl, int64_t lb,
                                             int32_t blk0, int32_t blk1, int d,
-                                            Win<K, TIER, MASS>& W) {
+                                            Win<K, TIER, ND>& W) {
   constexpr int O = K + 1;
   using T = typename Tier<TIER>::T;
-  const T* hin = reinterpret_cast<const T*>(a.in_hi);
-  if (MASS) {
-    double m[5];
-    window5<double>(load4(a.in_mass + lb + 4 * blk0), load4(a.in_mass + lb + 4 * blk1), d, m);
 #pragma unroll
-    for (int u = 0; u < 5; ++u) W.w[u].m = m[u];
-  }
+  for (int l = 0; l < O; ++l) {
+    if (l < ND) {
+      double m[5];
+      window5<double>(load4(pl.ind[l] + lb + 4 * blk0), load4(pl.ind[l] + lb + 4 * blk1), d, m);
 #pragma unroll
-  for (int l = (MASS ? 1 : 0); l < O; ++l) {
-    const T* pin = hin + (int64_t)(m0 + l - 1) * a.cells + lb;
-    T h[5];
-    window5<T>(load4(pin + 4 * blk0), load4(pin + 4 * blk1), d, h);
+      for (int u = 0; u < 5; ++u) W.w[u].d[l] = m[u];
+    } else {
+      T h[5];
+      window5<T>(load4(pl.inh[l] + lb + 4 * blk0), load4(pl.inh[l] + lb + 4 * blk1), d, h);
 #pragma unroll
-    for (int u = 0; u < 5; ++u) W.w[u].h[l] = h[u];
+      for (int u = 0; u < 5; ++u) W.w[u].h[l] = h[u];
+    }
   }
 }
 
-template <int K, int TIER, bool MASS>
-__device__ __forceinline__ void contig_store(const SweepArgs& a, int32_t m0, int64_t c,
-                                             const Mat<K, TIER>& M,
-                                             const Win<K, TIER, MASS>& W) {
+template <int K, int TIER, int ND>
+__device__ __forceinline__ void contig_store(const Planes<K, TIER, ND>& pl, int64_t c,
+                                             const Mat<K, TIER>& M, const Rows64<K, ND>& R,
+                                             const Win<K, TIER, ND>& W) {
   constexpr int O = K + 1;
   using T = typename Tier<TIER>::T;
-  T* hout = reinterpret_cast<T*>(a.out_hi);
-  if (MASS) {
-    double o4[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) o4[u] = M.mass_out(W.w[u + 1], W.w[u]);
-    store4<double>(a.out_mass + c, o4);
-  }
+  for (int j = 0; j < O; ++j) {
+    if (j < ND) {
+      double o4[4];
 #pragma unroll
-  for (int j = (MASS ? 1 : 0); j < O; ++j) {
-    T o4[4];
+      for (int u = 0; u < 4; ++u) o4[u] = Mat<K, TIER>::out64(R, j, W.w[u + 1], W.w[u]);
+      store4<double>(pl.outd[j] + c, o4);
+    } else {
+      T o4[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) o4[u] = M.hi_out(j, W.w[u + 1], W.w[u]);
-    store4<T>(hout + (int64_t)(m0 + j - 1) * a.cells + c, o4);
+      for (int u = 0; u < 4; ++u) o4[u] = M.out_t(j, W.w[u + 1], W.w[u]);
+      store4<T>(pl.outh[j] + c, o4);
+    }
   }
 }
 
-// One thread: 4 consecutive output cells of one line, for a run of
-// `tuples` spectator tuples in turn (the line's s, A and B are loaded once;
-// the loads of the next tuple are issued before the current tuple is computed
-// and stored).  blockIdx.y selects the run of tuples.  When every lane of the
-// wave works on lines that share one table entry (the common case: the
+template <int K, int TIER, int ND>
+__device__ __forceinline__ void contig_single(const SweepArgs& a, const TupleMap& tm,
+                                              const Mat<K, TIER>& M, int64_t lb, int32_t blk0,
+                                              int32_t blk1, int d, int64_t c) {
+  Planes<K, TIER, ND> pl;
+  pl.bind(a, tm);
+  Rows64<K, ND> R;
+  R.load(M.ab, M.cs);
+  Win<K, TIER, ND> W;
+  contig_load<K, TIER, ND>(pl, lb, blk0, blk1, d, W);
+  contig_store<K, TIER, ND>(pl, c, M, R, W);
+}
+
+// One thread: 4 consecutive output cells of one line, for the spectator
+// tuples [q, qe) in turn (the line's s, A and B are loaded once; across a run
+// of tuples without FP64 modes, the loads of the next tuple are issued before
+// the current tuple is computed and stored).  When every lane of the wave
+// works on lines that share one table entry (the common case: the
 // displacement of a dimension-0 sweep rarely depends on dimension 1), the
 // entry is read with scalar loads and the matrices live in scalar registers.
-template <int K, int TIER>
+template <int K, int TIER, int NDMAX>
 __device__ __forceinline__ void contig_body(const SweepArgs& a, int32_t c, int32_t line,
                                             int32_t i0, int32_t t, int32_t q, int32_t qe) {
   constexpr int O = K + 1;
@@ -461,25 +577,44 @@ __device__ __forceinline__ void contig_body(const SweepArgs& a, int32_t c, int32
   const int32_t blk1 = (blk0 + 1 == nb) ? 0 : blk0 + 1;
   const int64_t lb = (int64_t)line * N;
   Mat<K, TIER> M;
-  M.load(a.ab_tab + t, a.ab_cs, q == 0);
-  if (q == 0) {
-    Win<K, TIER, true> W;
-    contig_load<K, TIER, true>(a, 0, lb, blk0, blk1, d, W);
-    contig_store<K, TIER, true>(a, 0, c, M, W);
-    ++q;
-  }
-  if (q >= qe) return;
-  Win<K, TIER, false> cur, nxt;
-  contig_load<K, TIER, false>(a, q * O, lb, blk0, blk1, d, cur);
-  for (; q < qe; ++q) {
-    if (q + 1 < qe) contig_load<K, TIER, false>(a, (q + 1) * O, lb, blk0, blk1, d, nxt);
-    contig_store<K, TIER, false>(a, q * O, c, M, cur);
-    cur = nxt;
+  M.load(a.ab_tab + t, a.ab_cs);
+  while (q < qe) {
+    TupleMap tm = tuple_map(a, q * O, 1, O);
+    if (tm.nd != 0) {
+      dispatch_nd<NDMAX>(tm.nd, [&](auto ndc) {
+        contig_single<K, TIER, decltype(ndc)::value>(a, tm, M, lb, blk0, blk1, d, c);
+      });
+      ++q;
+      continue;
+    }
+    Planes<K, TIER, 0> pc, pn;
+    Rows64<K, 0> R0;
+    pc.bind(a, tm);
+    Win<K, TIER, 0> cur, nxt;
+    contig_load<K, TIER, 0>(pc, lb, blk0, blk1, d, cur);
+    for (;;) {
+      const int32_t q1 = q + 1;
+      bool more = q1 < qe;
+      if (more) {
+        const TupleMap tm1 = tuple_map(a, q1 * O, 1, O);
+        more = tm1.nd == 0;
+        if (more) {
+          pn.bind(a, tm1);
+          contig_load<K, TIER, 0>(pn, lb, blk0, blk1, d, nxt);
+        }
+      }
+      contig_store<K, TIER, 0>(pc, c, M, R0, cur);
+      q = q1;
+      if (!more) break;
+#pragma unroll
+      for (int u = 0; u < 5; ++u) copy_raw(cur.w[u], nxt.w[u]);
+      pc.copy_from(pn);
+    }
   }
 }
 
 // Group g (4 cells) of the dimension-0 sweep, tuples [q, qe).
-template <int K, int TIER>
+template <int K, int TIER, int NDMAX>
 __device__ __forceinline__ void contig_group(const SweepArgs& a, int64_t g, int32_t q,
                                              int32_t qe) {
   if (g >= (a.cells >> 2)) return;
@@ -488,81 +623,76 @@ __device__ __forceinline__ void contig_group(const SweepArgs& a, int64_t g, int3
   const int32_t i0 = c - line * a.N;
   const int32_t t = table_index(a.map, 0, line);
   const int32_t t0 = __builtin_amdgcn_readfirstlane(t);
-  if (__all(t == t0)) contig_body<K, TIER>(a, c, line, i0, t0, q, qe);
-  else contig_body<K, TIER>(a, c, line, i0, t, q, qe);
+  if (__all(t == t0)) contig_body<K, TIER, NDMAX>(a, c, line, i0, t0, q, qe);
+  else contig_body<K, TIER, NDMAX>(a, c, line, i0, t, q, qe);
 }
 
-template <int K, int TIER>
+template <int K, int TIER, int NDMAX>
 __global__ __launch_bounds__(256) void sweep_contig_window_kernel(SweepArgs a) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int32_t q = blockIdx.y * a.tuples;
-  contig_group<K, TIER>(a, g, q, min(a.nspec, q + a.tuples));
+  contig_group<K, TIER, NDMAX>(a, g, q, min(a.nspec, q + a.tuples));
 }
 
 // ---------------------------------------------------------------------------
 // Sweep along a dimension d > 0 (strided).  Lanes take consecutive cells of
 // the flattened lower dimensions (contiguous in memory, coalesced in every
 // plane).  A thread produces L consecutive rows i..i+L-1 along d, for a run of
-// spectator tuples (blockIdx.y selects the run) in turn: its L+1 source rows per plane are loaded before
-// any arithmetic, the loads of the next tuple are issued before the current
-// tuple is computed, and the line's s, A and B (which may differ from lane to
-// lane) are loaded once for all tuples.  Concurrent waves work on
-// neighbouring cells of the same rows of the same planes, which keeps the
-// HBM access stream local; the one extra source row per thread is re-read by
-// the neighbouring chunk shortly afterwards and served by the caches.
+// spectator tuples (blockIdx.y selects the run) in turn: its L+1 source rows
+// per plane are loaded before any arithmetic, across tuples without FP64
+// modes the loads of the next tuple are issued before the current tuple is
+// computed, and the line's s, A and B (which may differ from lane to lane)
+// are loaded once for all tuples.  Concurrent waves work on neighbouring
+// cells of the same rows of the same planes, which keeps the HBM access
+// stream local; the one extra source row per thread is the last row of the
+// neighbouring chunk, loaded by a wave of the same workgroup.
 // ---------------------------------------------------------------------------
 
-template <int K, int TIER, bool MASS, int L>
+template <int K, int TIER, int ND, int L>
 struct Rows {
-  Raw<K, TIER, MASS> v[L + 1];
+  Raw<K, TIER, ND> v[L + 1];
 };
 
-template <int K, int TIER, bool MASS, int L>
-__device__ __forceinline__ void strided_load(const SweepArgs& a, int32_t m0, int32_t ms,
-                                             int64_t base, const int32_t (&roff)[L + 1],
-                                             int32_t n, Rows<K, TIER, MASS, L>& R) {
-  constexpr int O = K + 1;
-  using T = typename Tier<TIER>::T;
-  const T* hin = reinterpret_cast<const T*>(a.in_hi);
-  (void)n;   // all L+1 rows are loaded (row offsets wrap), only the stores are cut
+template <int K, int TIER, int ND, int L>
+__device__ __forceinline__ void strided_load(const Planes<K, TIER, ND>& pl, int64_t base,
+                                             const int32_t (&roff)[L + 1],
+                                             Rows<K, TIER, ND, L>& R) {
+  // all L+1 rows are loaded (row offsets wrap); only the stores are cut
 #pragma unroll
-  for (int u = 0; u <= L; ++u) {
-    if (MASS) R.v[u].m = a.in_mass[base + roff[u]];
-#pragma unroll
-    for (int l = (MASS ? 1 : 0); l < O; ++l)
-      R.v[u].h[l] = hin[(int64_t)(m0 + l * ms - 1) * a.cells + base + roff[u]];
-  }
+  for (int u = 0; u <= L; ++u) pl.load(base + roff[u], R.v[u]);
 }
 
-template <int K, int TIER, bool MASS, int L>
-__device__ __forceinline__ void strided_store(const SweepArgs& a, int32_t m0, int32_t ms,
-                                              int64_t base, int32_t r0, int32_t n,
-                                              const Mat<K, TIER>& M,
-                                              const Rows<K, TIER, MASS, L>& R) {
-  constexpr int O = K + 1;
-  using T = typename Tier<TIER>::T;
-  T* hout = reinterpret_cast<T*>(a.out_hi);
+template <int K, int TIER, int ND, int L>
+__device__ __forceinline__ void strided_store(const Planes<K, TIER, ND>& pl, int64_t base,
+                                              int32_t P, int32_t r0, int32_t n,
+                                              const Mat<K, TIER>& M, const Rows64<K, ND>& R64,
+                                              const Rows<K, TIER, ND, L>& R) {
   if (n == L) {            // full chunk: no per-row predicate
 #pragma unroll
-    for (int u = 0; u < L; ++u) {
-      const int64_t c = base + (int64_t)(r0 + u) * a.P;
-      if (MASS) a.out_mass[c] = M.mass_out(R.v[u + 1], R.v[u]);
-#pragma unroll
-      for (int j = (MASS ? 1 : 0); j < O; ++j)
-        hout[(int64_t)(m0 + j * ms - 1) * a.cells + c] = M.hi_out(j, R.v[u + 1], R.v[u]);
-    }
+    for (int u = 0; u < L; ++u)
+      pl.store(base + (int64_t)(r0 + u) * P, M, R64, R.v[u + 1], R.v[u]);
   } else {                 // the last chunk of a line whose length L does not divide
-    for (int u = 0; u < n; ++u) {
-      const int64_t c = base + (int64_t)(r0 + u) * a.P;
-      if (MASS) a.out_mass[c] = M.mass_out(R.v[u + 1], R.v[u]);
 #pragma unroll
-      for (int j = (MASS ? 1 : 0); j < O; ++j)
-        hout[(int64_t)(m0 + j * ms - 1) * a.cells + c] = M.hi_out(j, R.v[u + 1], R.v[u]);
-    }
+    for (int u = 0; u < L; ++u)
+      if (u < n) pl.store(base + (int64_t)(r0 + u) * P, M, R64, R.v[u + 1], R.v[u]);
   }
 }
 
-template <int K, int TIER, int L>
+template <int K, int TIER, int ND, int L>
+__device__ __forceinline__ void strided_single(const SweepArgs& a, const TupleMap& tm,
+                                               const Mat<K, TIER>& M, int64_t base,
+                                               const int32_t (&roff)[L + 1], int32_t r0,
+                                               int32_t n) {
+  Planes<K, TIER, ND> pl;
+  pl.bind(a, tm);
+  Rows64<K, ND> R64;
+  R64.load(M.ab, M.cs);
+  Rows<K, TIER, ND, L> R;
+  strided_load<K, TIER, ND, L>(pl, base, roff, R);
+  strided_store<K, TIER, ND, L>(pl, base, a.P, r0, n, M, R64, R);
+}
+
+template <int K, int TIER, int L, int NDMAX>
 __device__ __forceinline__ void strided_body(const SweepArgs& a, int32_t ilow, int32_t chunk,
                                              int32_t ihigh, int32_t t, int32_t q, int32_t qe) {
   constexpr int O = K + 1;
@@ -580,48 +710,59 @@ __device__ __forceinline__ void strided_body(const SweepArgs& a, int32_t ilow, i
     if (++row == N) row = 0;
   }
   Mat<K, TIER> M;
-  M.load(a.ab_tab + t, a.ab_cs, q == 0);
-  if (q == 0) {
-    Rows<K, TIER, true, L> R;
-    strided_load<K, TIER, true, L>(a, 0, ms, base, roff, n, R);
-    strided_store<K, TIER, true, L>(a, 0, ms, base, r0, n, M, R);
-    ++q;
-  }
-  if (q >= qe) return;
+  M.load(a.ab_tab + t, a.ab_cs);
   // mode base of tuple q, stepped without division: the low part (dims below
   // d) counts to ms, then the base jumps over the swept index's o-1 planes
   int32_t low = q % ms;
   int32_t m0 = low + (q / ms) * ms * O;
-  int32_t low1 = low + 1, m1 = m0 + 1;
-  if (low1 == ms) {
-    low1 = 0;
-    m1 = m0 + 1 + ms * (O - 1);
-  }
-  Rows<K, TIER, false, L> cur, nxt;
-  strided_load<K, TIER, false, L>(a, m0, ms, base, roff, n, cur);
-  for (; q < qe; ++q) {
-    if (q + 1 < qe) strided_load<K, TIER, false, L>(a, m1, ms, base, roff, n, nxt);
-    strided_store<K, TIER, false, L>(a, m0, ms, base, r0, n, M, cur);
-    cur = nxt;
-    m0 = m1;
-    low = low1;
-    ++low1;
-    ++m1;
-    if (low1 == ms) {
-      low1 = 0;
-      m1 += ms * (O - 1);
+  auto advance = [&](int32_t& qq, int32_t& lw, int32_t& mm) {
+    ++qq;
+    ++mm;
+    if (++lw == ms) {
+      lw = 0;
+      mm += ms * (O - 1);
+    }
+  };
+  while (q < qe) {
+    const TupleMap tm = tuple_map(a, m0, ms, O);
+    if (tm.nd != 0) {
+      dispatch_nd<NDMAX>(tm.nd, [&](auto ndc) {
+        strided_single<K, TIER, decltype(ndc)::value, L>(a, tm, M, base, roff, r0, n);
+      });
+      advance(q, low, m0);
+      continue;
+    }
+    Planes<K, TIER, 0> pc, pn;
+    Rows64<K, 0> R64;
+    pc.bind(a, tm);
+    Rows<K, TIER, 0, L> cur, nxt;
+    strided_load<K, TIER, 0, L>(pc, base, roff, cur);
+    for (;;) {
+      int32_t q1 = q, low1 = low, m1 = m0;
+      advance(q1, low1, m1);
+      bool more = q1 < qe;
+      if (more) {
+        const TupleMap tm1 = tuple_map(a, m1, ms, O);
+        more = tm1.nd == 0;
+        if (more) {
+          pn.bind(a, tm1);
+          strided_load<K, TIER, 0, L>(pn, base, roff, nxt);
+        }
+      }
+      strided_store<K, TIER, 0, L>(pc, base, P, r0, n, M, R64, cur);
+      q = q1;
+      low = low1;
+      m0 = m1;
+      if (!more) break;
+#pragma unroll
+      for (int u = 0; u <= L; ++u) copy_raw(cur.v[u], nxt.v[u]);
+      pc.copy_from(pn);
     }
   }
 }
 
-// Work decomposition: a wave takes 64 consecutive columns (column =
-// ihigh * P + ilow, i.e. a cell of the transverse dimensions, consecutive
-// columns contiguous in memory), the waves of a workgroup take consecutive
-// row chunks of the same columns.  The halo row a wave loads is the last row
-// its neighbour wave loads, so it is served by the CU's caches, and the
-// waves share the columns' s, A, B in L1.
 // Column col, row chunk `chunk` of a strided sweep, tuples [q, qe).
-template <int K, int TIER, int L>
+template <int K, int TIER, int L, int NDMAX>
 __device__ __forceinline__ void strided_cell(const SweepArgs& a, int32_t col, int32_t chunk,
                                              int32_t q, int32_t qe) {
   if (col >= a.P * a.Q || chunk >= a.nchunk) return;
@@ -630,36 +771,42 @@ __device__ __forceinline__ void strided_cell(const SweepArgs& a, int32_t col, in
   const int32_t ihigh = (int32_t)ih;
   const int32_t t = table_index(a.map, ilow, ihigh);
   const int32_t t0 = __builtin_amdgcn_readfirstlane(t);
-  if (__all(t == t0)) strided_body<K, TIER, L>(a, ilow, chunk, ihigh, t0, q, qe);
-  else strided_body<K, TIER, L>(a, ilow, chunk, ihigh, t, q, qe);
+  if (__all(t == t0)) strided_body<K, TIER, L, NDMAX>(a, ilow, chunk, ihigh, t0, q, qe);
+  else strided_body<K, TIER, L, NDMAX>(a, ilow, chunk, ihigh, t, q, qe);
 }
 
-template <int K, int TIER, int L>
+// Work decomposition: a wave takes 64 consecutive columns (column =
+// ihigh * P + ilow, i.e. a cell of the transverse dimensions, consecutive
+// columns contiguous in memory), the waves of a workgroup take consecutive
+// row chunks of the same columns.  The halo row a wave loads is the last row
+// its neighbour wave loads, so it is served by the CU's caches, and the
+// waves share the columns' s, A, B in L1.
+template <int K, int TIER, int L, int NDMAX>
 __global__ __launch_bounds__(256) void sweep_strided_kernel(SweepArgs a) {
   const int32_t col = (int32_t)blockIdx.x * 64 + (int32_t)(threadIdx.x & 63);
   const int32_t chunk = (int32_t)blockIdx.z * (int32_t)(blockDim.x >> 6) + (int32_t)(threadIdx.x >> 6);
   const int32_t q = blockIdx.y * a.tuples;
-  strided_cell<K, TIER, L>(a, col, chunk, q, min(a.nspec, q + a.tuples));
+  strided_cell<K, TIER, L, NDMAX>(a, col, chunk, q, min(a.nspec, q + a.tuples));
 }
 
 bool contig_window_ok(const SweepArgs& a) {
-  const uintptr_t align = (uintptr_t)a.in_mass | (uintptr_t)a.in_hi | (uintptr_t)a.out_mass |
+  const uintptr_t align = (uintptr_t)a.in_lo | (uintptr_t)a.in_hi | (uintptr_t)a.out_lo |
                           (uintptr_t)a.out_hi;
   return a.N % 4 == 0 && (align & 15) == 0;
 }
 
-template <int K, int TIER>
-static hipError_t launch_sweep_kt(int dim, const SweepArgs& a, hipStream_t st) {
+template <int K, int TIER, int NDMAX>
+static hipError_t launch_sweep_ktn(int dim, const SweepArgs& a, hipStream_t st) {
   if (dim == 0) {
     if (contig_window_ok(a)) {
       const int64_t groups = a.cells >> 2;
       dim3 grid((unsigned)((groups + 255) / 256), (unsigned)((a.nspec + a.tuples - 1) / a.tuples)),
           block(256);
-      sweep_contig_window_kernel<K, TIER><<<grid, block, 0, st>>>(a);
+      sweep_contig_window_kernel<K, TIER, NDMAX><<<grid, block, 0, st>>>(a);
     } else {
       const int64_t items = (int64_t)a.Q * a.nspec;
       dim3 grid((unsigned)((items + 3) / 4)), block(256);
-      sweep_contig_kernel<K, TIER><<<grid, block, 0, st>>>(a);
+      sweep_contig_kernel<K, TIER, NDMAX><<<grid, block, 0, st>>>(a);
     }
   } else {
     const int64_t ncol = (int64_t)a.P * a.Q;
@@ -670,14 +817,20 @@ static hipError_t launch_sweep_kt(int dim, const SweepArgs& a, hipStream_t st) {
               (unsigned)((a.nchunk + waves - 1) / waves)),
         block(64 * waves);
     switch (a.chunk) {
-      case 1: sweep_strided_kernel<K, TIER, 1><<<grid, block, 0, st>>>(a); break;
-      case 2: sweep_strided_kernel<K, TIER, 2><<<grid, block, 0, st>>>(a); break;
-      case 4: sweep_strided_kernel<K, TIER, 4><<<grid, block, 0, st>>>(a); break;
-      case 8: sweep_strided_kernel<K, TIER, 8><<<grid, block, 0, st>>>(a); break;
+      case 1: sweep_strided_kernel<K, TIER, 1, NDMAX><<<grid, block, 0, st>>>(a); break;
+      case 2: sweep_strided_kernel<K, TIER, 2, NDMAX><<<grid, block, 0, st>>>(a); break;
+      case 4: sweep_strided_kernel<K, TIER, 4, NDMAX><<<grid, block, 0, st>>>(a); break;
+      case 8: sweep_strided_kernel<K, TIER, 8, NDMAX><<<grid, block, 0, st>>>(a); break;
       default: return hipErrorInvalidValue;
     }
   }
   return hipGetLastError();
+}
+
+template <int K, int TIER>
+static hipError_t launch_sweep_kt(int dim, const SweepArgs& a, hipStream_t st) {
+  return a.wide_fp64 ? launch_sweep_ktn<K, TIER, K + 1>(dim, a, st)
+                     : launch_sweep_ktn<K, TIER, 1>(dim, a, st);
 }
 
 template <int K>
@@ -711,19 +864,6 @@ hipError_t launch_sweep(int k, int tier, int dim, const SweepArgs& a, hipStream_
 // columns x (blockDim/64) row chunks.  A run of tuples is part of the item.
 // ---------------------------------------------------------------------------
 
-template <int K, int TIER>
-__device__ __forceinline__ void contig_generic_item(const SweepArgs& a, int64_t item4) {
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int64_t nlines = (int64_t)a.Q;
-  const int64_t item = item4 * 4 + wave;
-  if (item >= nlines * a.nspec) return;
-  const int32_t sp = (int32_t)(item / nlines);
-  const int64_t line = item - (int64_t)sp * nlines;
-  if (sp == 0) contig_line<K, TIER, true>(a, line, sp, lane);
-  else contig_line<K, TIER, false>(a, line, sp, lane);
-}
-
 template <int TIER, int L>
 __global__ __launch_bounds__(256) void batch_sweep_kernel(const SweepArgs* __restrict__ args,
                                                           const int32_t* __restrict__ kdeg,
@@ -737,19 +877,19 @@ __global__ __launch_bounds__(256) void batch_sweep_kernel(const SweepArgs* __res
     const int32_t qe = min(a.nspec, q + a.tuples);
     if (w.kind == 0) {               // dimension 0, window form
       const int64_t g = (int64_t)w.x * blockDim.x + threadIdx.x;
-      if (k == 1) contig_group<1, TIER>(a, g, q, qe);
-      else if (k == 2) contig_group<2, TIER>(a, g, q, qe);
-      else contig_group<3, TIER>(a, g, q, qe);
+      if (k == 1) contig_group<1, TIER, 1>(a, g, q, qe);
+      else if (k == 2) contig_group<2, TIER, 1>(a, g, q, qe);
+      else contig_group<3, TIER, 1>(a, g, q, qe);
     } else if (w.kind == 1) {        // dimension 0, generic form
-      if (k == 1) contig_generic_item<1, TIER>(a, w.x);
-      else if (k == 2) contig_generic_item<2, TIER>(a, w.x);
-      else contig_generic_item<3, TIER>(a, w.x);
+      if (k == 1) contig_generic_item<1, TIER, 1>(a, w.x);
+      else if (k == 2) contig_generic_item<2, TIER, 1>(a, w.x);
+      else contig_generic_item<3, TIER, 1>(a, w.x);
     } else {                         // strided
       const int32_t col = w.x * 64 + (int32_t)(threadIdx.x & 63);
       const int32_t chunk = w.z * (int32_t)(blockDim.x >> 6) + (int32_t)(threadIdx.x >> 6);
-      if (k == 1) strided_cell<1, TIER, L>(a, col, chunk, q, qe);
-      else if (k == 2) strided_cell<2, TIER, L>(a, col, chunk, q, qe);
-      else strided_cell<3, TIER, L>(a, col, chunk, q, qe);
+      if (k == 1) strided_cell<1, TIER, L, 1>(a, col, chunk, q, qe);
+      else if (k == 2) strided_cell<2, TIER, L, 1>(a, col, chunk, q, qe);
+      else strided_cell<3, TIER, L, 1>(a, col, chunk, q, qe);
     }
   }
 }

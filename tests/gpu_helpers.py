@@ -55,19 +55,52 @@ def gamma(tier, k, mass_mode):
     return n * 2.0 ** -24
 
 
-def sweep_bound(want, got, mag, tier, k):
+def sweep_bound(want, got, mag, tier, k, keep=None):
     """Element-wise bound on |got - want| for one sweep from identical inputs:
     both sides round the exact update to the storage format, from values that
-    differ by at most gamma * magnitude."""
+    differ by at most gamma * magnitude.  `keep` marks the FP64 modes (default:
+    mode 0 alone)."""
+    if keep is None:
+        keep = np.zeros(want.shape[0], dtype=bool)
+        keep[0] = True
+    keep = np.asarray(keep, dtype=bool)
     tol = np.empty_like(want)
     big = np.maximum(np.abs(want), np.abs(got))
-    tol[0] = ulp(big[0], "fp64") + gamma("fp64", k, True) * mag[0]
-    tol[1:] = ulp(big[1:], tier) + gamma(tier, k, False) * mag[1:]
+    tol[keep] = ulp(big[keep], "fp64") + gamma("fp64", k, True) * mag[keep]
+    tol[~keep] = ulp(big[~keep], tier) + gamma(tier, k, False) * mag[~keep]
     return tol
 
 
-def assert_sweep_close(got, want, mag, tier, k, what=""):
-    tol = sweep_bound(want, got, mag, tier, k)
+def upload_nd(state, plan):
+    """Oracle state -> (mass, hi) in the plan's layout for any number of FP64
+    modes (plane map from the library)."""
+    import torch
+    import paper_1603_07008_amd as sl
+    pm = plan.plane_map()
+    lo = sorted((-1 - v, m) for m, v in enumerate(pm) if v < 0)
+    hi = sorted((v, m) for m, v in enumerate(pm) if v >= 0)
+    mass = torch.from_numpy(np.ascontiguousarray(state[[m for _, m in lo]])).cuda()
+    if len(lo) == 1:
+        mass = mass.reshape(-1)
+    h64 = torch.from_numpy(np.ascontiguousarray(state[[m for _, m in hi]]).reshape(len(hi), state.shape[1]))
+    h = h64.to(sl.hi_dtype(plan.tier))
+    assert torch.equal(h.to(torch.float64), h64), "state not representable in the tier"
+    return mass.contiguous(), h.cuda().contiguous()
+
+
+def download_nd(mass, hi, plan):
+    import torch
+    pm = plan.plane_map()
+    m = mass.detach().to("cpu", torch.float64).numpy().reshape(plan.n_lo, plan.cells)
+    h = hi.detach().to("cpu").to(torch.float64).numpy().reshape(plan.n_hi, plan.cells)
+    out = np.empty((plan.modes, plan.cells))
+    for mode, v in enumerate(pm):
+        out[mode] = m[-1 - v] if v < 0 else h[v]
+    return out
+
+
+def assert_sweep_close(got, want, mag, tier, k, what="", keep=None):
+    tol = sweep_bound(want, got, mag, tier, k, keep)
     err = np.abs(got - want)
     bad = err > tol
     if np.any(bad):
@@ -75,8 +108,11 @@ def assert_sweep_close(got, want, mag, tier, k, what=""):
         msg = ", ".join(f"(m={m}, c={c}): got {got[m, c]!r} want {want[m, c]!r} tol {tol[m, c]:.3g}"
                         for m, c in idx)
         raise AssertionError(f"{what}: {int(bad.sum())} of {bad.size} elements out of bound: {msg}")
-    # fraction of the rounded (non-mass) coefficients that are not bit-identical
-    return float(np.mean(got[1:] != want[1:]))
+    # fraction of the rounded (non-FP64) coefficients that are not bit-identical
+    if keep is None:
+        return float(np.mean(got[1:] != want[1:]))
+    rk = ~np.asarray(keep, dtype=bool)
+    return float(np.mean(got[rk] != want[rk])) if rk.any() else 0.0
 
 
 def weighted_rel_l2(got, want, ndim, k):

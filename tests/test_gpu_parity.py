@@ -339,3 +339,43 @@ def test_device_copy_and_kernel_timing(sl):
     nd1, _ = p.timing_read(1)
     assert (n0, n1, nd1) == (4, 2, 2) and ms0 > 0 and ms1 > 0
     p.timing_enable(False)
+
+
+ND_CASES = [((50,), 3, 0), ((52,), 3, 2), ((50,), 3, 3), ((48,), 3, 4), ((24, 10), 2, 0),
+            ((24, 10), 2, 2), ((37, 9), 2, 3), ((16, 6, 5), 1, 2), ((8, 6, 4, 5), 2, 3)]
+
+
+@pytest.mark.parametrize("tier", ["fp32", "bf16"])
+@pytest.mark.parametrize("case", ND_CASES, ids=["x".join(map(str, c[0])) + f"-k{c[1]}-nd{c[2]}" for c in ND_CASES])
+def test_leading_fp64_modes_sweeps(sl, case, tier):
+    # the paper's "number of coefficients in double precision" axis: the modes
+    # of total degree < ndouble are stored and updated in FP64
+    import torch
+    from gpu_helpers import download_nd, upload_nd
+    ns, k, nd = case
+    ndim = len(ns)
+    cells = int(np.prod(ns))
+    p = sl.Plan(ns, k, tier, ndouble=nd)
+    keep = O.fp64_modes(ndim, k, nd).astype(bool)
+    assert [v < 0 for v in p.plane_map()] == list(keep)
+    rng = np.random.default_rng(zlib.crc32(repr(case).encode()) + len(tier))
+    state = O.to_tier(inputs.random_coefficients(ndim, k, cells, seed=int(rng.integers(1 << 30))),
+                      tier, nd, k=k, ndim=ndim)
+    m_in, h_in = upload_nd(state, p)
+    m_out, h_out = p.empty_state()
+    for dim in range(ndim):
+        dep = tuple(e for e in range(ndim) if e != dim)[:1]
+        nsig = int(np.prod([ns[e] for e in dep])) if dep else 1
+        sig = rng.uniform(-1.7 * ns[dim], 1.7 * ns[dim], nsig)
+        p.advect_dim(dim, _dev(sig), sum(1 << e for e in dep), m_in, h_in, m_out, h_out)
+        torch.cuda.synchronize()
+        got = download_nd(m_out, h_out, p)
+        want = O.sweep(state, ns, k, dim, sig, dep, tier, ndouble=nd)
+        mag = O.sweep(state, ns, k, dim, sig, dep, absolute=True)
+        assert_sweep_close(got, want, mag, tier, k, what=f"{case} {tier} dim={dim}", keep=keep)
+        # integer shift: exact permutation in every storage
+        sig_i = np.round(sig)
+        p.advect_dim(dim, _dev(sig_i), sum(1 << e for e in dep), m_in, h_in, m_out, h_out)
+        torch.cuda.synchronize()
+        assert np.array_equal(download_nd(m_out, h_out, p),
+                              O.sweep(state, ns, k, dim, sig_i, dep, tier, ndouble=nd))

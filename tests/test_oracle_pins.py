@@ -460,3 +460,45 @@ def test_adjoint_equals_weighted_reflected_forward(k):
     sigma = 2.6
     via_forward = W @ O.sweep(Wi @ g, (n,), k, 0, -sigma)
     assert np.allclose(O.sweep_adjoint(g, (n,), k, 0, sigma), via_forward, atol=1e-13, rtol=0)
+
+
+# --------------------------------------------------------------------------
+# number of leading coefficients in FP64 (section III-A, Table II axis)
+# --------------------------------------------------------------------------
+
+def test_fp64_modes_follow_total_degree():
+    keep = O.fp64_modes(2, 2, 2)          # 2D, k = 2: modes with j0 + j1 < 2
+    assert [m for m in range(9) if keep[m]] == [0, 1, 3]
+    assert O.fp64_modes(1, 3, 4).all() and not O.fp64_modes(3, 1, 0).any()
+    assert list(O.fp64_modes(1, 3, 2)) == [1, 1, 0, 0]
+
+
+def test_all_fp64_modes_equal_the_fp64_tier():
+    k, ns = 2, (9, 7)
+    rng = np.random.default_rng(17)
+    state = rng.standard_normal((9, 63))
+    sig = rng.uniform(-3, 3, 7)
+    a = O.sweep(state, ns, k, 0, sig, (1,), "fp32", ndouble=2 * k + 1)
+    b = O.sweep(state, ns, k, 0, sig, (1,), "fp64")
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("ndouble,tier", [(0, "fp32"), (1, "fp32"), (2, "fp32"), (1, "bf16")])
+def test_mass_is_conserved_iff_the_cell_mean_is_fp64(ndouble, tier):
+    # section III-A: with c_0 in double precision the mass is conserved to
+    # double precision; with every coefficient in single precision it is not
+    n, k, steps = 64, 3, 3000
+    rng = np.random.default_rng(1603)
+    m = np.arange(1, n // 4 + 1)
+    r = rng.uniform(0, 1, m.size) / m
+    ph = rng.uniform(0, 2 * np.pi, m.size)
+    f = lambda x: 1.0 + np.sum(r[:, None, None] * np.sin(2 * np.pi * m[:, None, None] * x[None] + ph[:, None, None]), axis=0)
+    c = O.to_tier(O.project_1d(f, n, 0.0, 1.0, k), tier, ndouble, k=k, ndim=1)
+    M0 = O.mass(c, (n,), (0.0,), (1.0,))
+    for _ in range(steps):
+        c = O.sweep(c, (n,), k, 0, 0.37, tier=tier, ndouble=ndouble)
+    drift = abs(O.mass(c, (n,), (0.0,), (1.0,)) - M0) / abs(M0)
+    if ndouble >= 1:
+        assert drift <= 1e-14
+    else:
+        assert drift >= 1e-10
