@@ -121,7 +121,7 @@ def run_tier(sl, torch, prob, tier, init, steps, warmup):
     p.timing_enable(False)
     tid = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}[tier]
     contig = "sweep_contig_window_kernel" if prob.ns[0] % 4 == 0 else "sweep_contig_kernel"
-    rows = int(os.environ.get("SLDG_STRIDED_ROWS", "2"))
+    rows = int(os.environ.get("SLDG_STRIDED_ROWS", "4"))
     kern = {
         f"sldg::{contig}<{prob.k}, {tid}>": p.timing_read(-1),
         f"sldg::sweep_strided_kernel<{prob.k}, {tid}, {rows}>": p.timing_read(-2),

@@ -312,8 +312,8 @@ sldg_status sldg_plan_ex(sldg_plan_t* out, int ndim, const int64_t* ncells, int 
   p->lo_bytes = p->n_lo * cells * 8;
   p->hi_bytes = p->n_hi * cells * elem_size(tier);
   p->table_cap = cells / min_n;     // the most lines any sweep can have
-  p->rows_per_thread = 2;
-  p->tuples_per_thread = 0;
+  p->rows_per_thread = 4;      // measured best on MI355X for the 4D k = 2 workload
+  p->tuples_per_thread = 9;
   if (const char* env = getenv("SLDG_TUPLES")) {
     const int g = atoi(env);
     if (g >= 0) p->tuples_per_thread = g;
