@@ -123,8 +123,8 @@ def run_tier(sl, torch, prob, tier, init, steps, warmup):
     contig = "sweep_contig_window_kernel" if prob.ns[0] % 4 == 0 else "sweep_contig_kernel"
     rows = int(os.environ.get("SLDG_STRIDED_ROWS", "4"))
     kern = {
-        f"sldg::{contig}<{prob.k}, {tid}>": p.timing_read(-1),
-        f"sldg::sweep_strided_kernel<{prob.k}, {tid}, {rows}>": p.timing_read(-2),
+        f"sldg::{contig}<{prob.k}, {tid}, 1>": p.timing_read(-1),
+        f"sldg::sweep_strided_kernel<{prob.k}, {tid}, {rows}, 1>": p.timing_read(-2),
     }
     per_dim = {d: p.timing_read(d) for d in range(prob.ndim)}
     m_end = p.mass(bufs[cur][0])
@@ -148,12 +148,18 @@ def cpu_baseline(prob, tier, seconds, seed):
     # warm the A/B cache of the oracle, then calibrate the sample size
     for sw in prob.seq:
         O.line_tables(sw.sigma, prob.k)
-    probe = np.sort(rng.choice(prob.cells, 4096, replace=False))
-    t0 = time.perf_counter()
-    for sw in prob.seq:
-        O.sweep(state, prob.ns, prob.k, sw.dim, sw.sigma, sw.dep, tier, sel=probe)
-    dt = time.perf_counter() - t0
-    nsel = int(min(prob.cells, max(4096, 4096 * seconds / max(dt, 1e-6))))
+    # two probe sizes give the marginal cost per sampled cell (a small probe
+    # alone is dominated by the fixed cost of each call)
+    def timed(n):
+        probe = np.sort(rng.choice(prob.cells, n, replace=False))
+        t = time.perf_counter()
+        for sw in prob.seq:
+            O.sweep(state, prob.ns, prob.k, sw.dim, sw.sigma, sw.dep, tier, sel=probe)
+        return time.perf_counter() - t
+    n1, n2 = min(prob.cells, 16384), min(prob.cells, 131072)
+    d1, d2 = timed(n1), timed(n2)
+    per = max((d2 - d1) / max(n2 - n1, 1), d2 / n2 * 0.05, 1e-12)
+    nsel = int(min(prob.cells, max(n2, (seconds - min(d1, seconds / 2)) / per)))
     sel = np.sort(rng.choice(prob.cells, nsel, replace=False))
     t0 = time.perf_counter()
     for sw in prob.seq:
