@@ -58,7 +58,7 @@ def _load():
         lib.oracle_sweep.argtypes = [
             ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
-            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
         lib.oracle_sweep_adjoint.restype = None
         lib.oracle_sweep_adjoint.argtypes = [
             ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
@@ -227,7 +227,17 @@ def fp64_modes(ndim, k, ndouble=1):
     return keep
 
 
-def sweep(state, ns, k, dim, sigma, dep=(), tier="fp64", sel=None, absolute=False, ndouble=1):
+def _scale_array(scale, M):
+    if scale is None:
+        return None
+    e = np.ascontiguousarray(scale, dtype=np.int32).ravel()
+    if e.size != M:
+        raise ValueError(f"need {M} storage exponents, got {e.size}")
+    return e
+
+
+def sweep(state, ns, k, dim, sigma, dep=(), tier="fp64", sel=None, absolute=False, ndouble=1,
+          scale=None):
     """One sLdG projection sweep along `dim`.
 
     state  float64 [o^ndim, cells] (mode-major, cells dimension-0 fastest)
@@ -237,6 +247,8 @@ def sweep(state, ns, k, dim, sigma, dep=(), tier="fp64", sel=None, absolute=Fals
     sel    optional int64 array of output cells; then the result is
            [o^ndim, len(sel)]
     ndouble number of leading modes kept in FP64 (fp64_modes)
+    scale  optional int [o^ndim]: narrow mode m is stored as c * 2^scale[m],
+           so its emulated value is round(c * 2^e) * 2^-e
     absolute  use |A|, |B| and |state| (no rounding): gives the magnitude
            sum_l |A_jl x_l| + |B_jl y_l| of every output, which bounds the
            rounding error of any evaluation order of the update
@@ -267,8 +279,10 @@ def sweep(state, ns, k, dim, sigma, dep=(), tier="fp64", sel=None, absolute=Fals
         nsel, selp = sel.size, sel.ctypes.data
     nsarr = np.asarray(ns, dtype=np.int64)
     keep = fp64_modes(ndim, k, ndouble)
+    sc = _scale_array(scale, M)
     _load().oracle_sweep(ndim, nsarr.ctypes.data, k, dim, stride.ctypes.data,
                          s_tab.ctypes.data, ab_tab.ctypes.data, TIERS[tier], keep.ctypes.data,
+                         None if sc is None else sc.ctypes.data,
                          state.ctypes.data, out.ctypes.data, nsel, selp)
     return out
 
@@ -313,11 +327,24 @@ def round_tier(x, tier):
     return x
 
 
-def to_tier(state, tier, ndouble=1, k=None, ndim=None):
+def to_tier(state, tier, ndouble=1, k=None, ndim=None, scale=None):
     """Emulated storage of a state: the FP64 modes (by default mode 0 alone)
-    stay, the others are rounded.  k and ndim are needed when ndouble != 1."""
+    stay, the others are rounded (scaled by 2^scale[m] first and back after,
+    when storage exponents are given).  k and ndim are needed when
+    ndouble != 1."""
     out = np.array(state, dtype=np.float64, copy=True)
-    if tier != "fp64":
+    if tier != "fp64" and scale is not None:
+        e = _scale_array(scale, out.shape[0])
+        keep = np.zeros(out.shape[0], dtype=bool)
+        if ndouble == 1:
+            keep[0] = True
+        else:
+            if k is None or ndim is None:
+                raise ValueError("to_tier needs k and ndim when ndouble != 1")
+            keep = fp64_modes(ndim, k, ndouble).astype(bool)
+        for m in np.nonzero(~keep)[0]:
+            out[m] = np.ldexp(round_tier(np.ldexp(out[m], int(e[m])), tier), -int(e[m]))
+    elif tier != "fp64":
         if ndouble == 1:
             keep = np.zeros(out.shape[0], dtype=bool)
             keep[0] = True
@@ -329,13 +356,100 @@ def to_tier(state, tier, ndouble=1, k=None, ndim=None):
     return out
 
 
-def run_sequence(state, ns, k, seq, tier="fp64", steps=1, ndouble=1):
+def run_sequence(state, ns, k, seq, tier="fp64", steps=1, ndouble=1, scale=None):
     """Apply a list of sweeps (dim, sigma, dep) `steps` times (section II,
     eq. (1): the split step is a composition of 1D advections)."""
     for _ in range(steps):
         for dim, sigma, dep in seq:
-            state = sweep(state, ns, k, dim, sigma, dep, tier, ndouble=ndouble)
+            state = sweep(state, ns, k, dim, sigma, dep, tier, ndouble=ndouble, scale=scale)
     return state
+
+
+# ---------------------------------------------------------------------------
+# FP16 storage with per-mode power-of-two scaling
+#
+# FP16 keeps 11 significant bits but only the exponents -14..15 in its normal
+# range, so the small higher Legendre modes (c_j ~ h^|j| for smooth data,
+# section II-A) fall into its subnormal range or flush to zero.  A narrow
+# mode m is therefore stored as c * 2^e[m]; e[m] is chosen from the mode's
+# absolute maximum `amax[m]` so that the stored values sit a fixed number of
+# binades (the headroom) below 2^15.  A sweep predicts the exponents of its
+# outputs from the absmax of its inputs (same mode), records the absmax of
+# what it computes, and a mode whose values reach 2^15 at the predicted
+# exponent (growth beyond the headroom in one sweep) is stored again at the
+# exponent of its own absmax.  The absmax is kept rounded to FP32.
+# ---------------------------------------------------------------------------
+
+FP16_TOP = 15                 # 2^15 <= 65504 (largest finite FP16) < 2^16
+SCALE_HEADROOM = 8            # binades kept free above a mode's absmax
+SCALE_REPAIR_HEADROOM = 1     # headroom of a mode stored again after growth
+SCALE_EMIN, SCALE_EMAX = -100, 100
+
+
+def storage_exponent(amax, headroom):
+    """The exponent e with 2^(14 - headroom) <= amax * 2^e < 2^(15 - headroom)
+    (clamped to [-100, 100]); None when amax is 0 or not finite."""
+    amax = float(amax)
+    if not (amax > 0.0 and math.isfinite(amax)):
+        return None
+    _, x = math.frexp(amax)              # amax = f 2^x, 0.5 <= f < 1
+    return min(max(FP16_TOP - headroom - x, SCALE_EMIN), SCALE_EMAX)
+
+
+def _f32(x):
+    return float(np.float32(x))
+
+
+def to_scaled(state, k, ndim, ndouble=1, headroom=SCALE_HEADROOM):
+    """FP16 storage of an FP64 state with per-mode scaling.  Returns
+    (values, exps, amax): the values the stored numbers represent, the
+    storage exponent of every mode (0 for the FP64 modes) and every narrow
+    mode's absmax, rounded to FP32."""
+    state = np.asarray(state, dtype=np.float64)
+    keep = fp64_modes(ndim, k, ndouble).astype(bool)
+    M = state.shape[0]
+    e = np.zeros(M, dtype=np.int32)
+    amax = np.zeros(M)
+    for m in range(M):
+        if keep[m] or state.shape[1] == 0:
+            continue
+        amax[m] = _f32(np.max(np.abs(state[m])))
+        em = storage_exponent(amax[m], headroom)
+        e[m] = 0 if em is None else em
+    return to_tier(state, "fp16", ndouble, k, ndim, scale=e), e, amax
+
+
+def sweep_scaled(state, exps, amax, ns, k, dim, sigma, dep=(), ndouble=1,
+                 headroom=SCALE_HEADROOM):
+    """One sweep of a scaled FP16 state (values, exps, amax as to_scaled
+    returns them); returns the output in the same form."""
+    ndim = len(ns)
+    keep = fp64_modes(ndim, k, ndouble).astype(bool)
+    acc = sweep(state, ns, k, dim, sigma, dep, "fp64")      # the update, unrounded
+    M = acc.shape[0]
+    e_out = np.array(exps, dtype=np.int32, copy=True)
+    a_out = np.zeros(M)
+    for m in range(M):
+        if keep[m]:
+            continue
+        pred = storage_exponent(amax[m], headroom)
+        if pred is None:
+            pred = int(exps[m])
+        a = _f32(np.max(np.abs(acc[m]))) if acc.shape[1] else 0.0
+        a_out[m] = a
+        if math.isfinite(a) and math.ldexp(a, pred) >= 2.0 ** FP16_TOP:
+            pred = storage_exponent(a, SCALE_REPAIR_HEADROOM)
+        e_out[m] = pred
+    return to_tier(acc, "fp16", ndouble, k, ndim, scale=e_out), e_out, a_out
+
+
+def run_sequence_scaled(scaled, ns, k, seq, steps=1, ndouble=1, headroom=SCALE_HEADROOM):
+    """run_sequence for a scaled FP16 state (values, exps, amax)."""
+    st, e, a = scaled
+    for _ in range(steps):
+        for dim, sigma, dep in seq:
+            st, e, a = sweep_scaled(st, e, a, ns, k, dim, sigma, dep, ndouble, headroom)
+    return st, e, a
 
 
 # ---------------------------------------------------------------------------

@@ -25,6 +25,10 @@
  * coefficients kept in double precision varies) is emulated: every mode not
  * marked `keep` is rounded to nearest-even onto the storage format after each
  * sweep, the kept modes (by default the cell mean m = 0 alone) stay FP64.
+ * A narrow mode may also be stored scaled by a power of two 2^e[m] (the
+ * per-mode scaling that keeps FP16 away from its underflow range): its value
+ * is then round(c * 2^e) * 2^-e, i.e. the rounding onto the format with its
+ * exponent range moved by -e; the scaling itself is exact.
  *
  * Plain loops, no blocking, no reordering; OpenMP only splits the independent
  * output cells between threads and does not change any result.
@@ -87,6 +91,7 @@ static int64_t wrap(int64_t i, int64_t n)
  *                   A = ab_tab[t*2*o*o ...], B = A + o*o, row-major [j][l]
  *   tier            storage emulation of the modes with keep[m] == 0
  *   keep            [o^ndim] 1 for the modes stored (and updated) in FP64
+ *   scale_exp       [o^ndim] storage exponent e of every mode, or NULL (all 0)
  *   in              [o^ndim][cells]
  *   out             [o^ndim][n_sel]  (n_sel = cells when sel == NULL)
  *   sel             optional list of output cells to compute
@@ -94,7 +99,8 @@ static int64_t wrap(int64_t i, int64_t n)
 void oracle_sweep(int ndim, const int64_t* n, int k, int dim,
                   const int64_t* line_stride, const int32_t* s_tab,
                   const double* ab_tab, int tier, const unsigned char* keep,
-                  const double* in, double* out, int64_t n_sel, const int64_t* sel)
+                  const int* scale_exp, const double* in, double* out, int64_t n_sel,
+                  const int64_t* sel)
 {
     const int o = k + 1;
     int64_t cells = 1, modes = 1, mstride = 1;
@@ -135,7 +141,12 @@ void oracle_sweep(int ndim, const int64_t* n, int k, int dim,
                 acc += A[j * o + l] * in[(m0 + l * mstride) * cells + ca];
             for (int l = 0; l < o; ++l)
                 acc += B[j * o + l] * in[(m0 + l * mstride) * cells + cb];
-            out[m * nout + q] = keep[m] ? acc : oracle_round_tier(acc, tier);
+            if (keep[m]) {
+                out[m * nout + q] = acc;
+            } else {
+                const int e = scale_exp ? scale_exp[m] : 0;
+                out[m * nout + q] = ldexp(oracle_round_tier(ldexp(acc, e), tier), -e);
+            }
         }
     }
 }
