@@ -87,7 +87,7 @@ def measured_copy_bandwidth(sl, torch, nbytes, reps=10):
     return 2 * n * 16 / (ms * 1e-3) / 1e9
 
 
-def run_tier(sl, torch, prob, tier, init, steps, warmup):
+def run_tier(sl, torch, prob, tier, init, steps, warmup, tune_cache=None):
     """Time `steps` split steps (after `warmup`) of `prob` in `tier`."""
     p = sl.Plan(prob.ns, prob.k, tier)
     mass0, hi0 = init
@@ -104,6 +104,12 @@ def run_tier(sl, torch, prob, tier, init, steps, warmup):
         cur = cur if res == 0 else 1 - cur
         p.mass_device(bufs[cur][0], mout)
 
+    # launch shapes: the plan's autotuner, once, outside the timed region
+    # (or shapes tuned earlier, from a JSON cache)
+    if tune_cache:
+        shapes, _ = p.tune_cached(tune_cache, seq, s0, s1, reps=3)
+    else:
+        shapes, _ = p.tune(seq, s0, s1, reps=3)
     m_start = p.mass(bufs[cur][0])
     for _ in range(warmup):
         step()
@@ -121,17 +127,18 @@ def run_tier(sl, torch, prob, tier, init, steps, warmup):
     p.timing_enable(False)
     tid = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}[tier]
     contig = "sweep_contig_window_kernel" if prob.ns[0] % 4 == 0 else "sweep_contig_kernel"
-    rows = int(os.environ.get("SLDG_STRIDED_ROWS", "4"))
-    kern = {
-        f"sldg::{contig}<{prob.k}, {tid}, 1>": p.timing_read(-1),
-        f"sldg::sweep_strided_kernel<{prob.k}, {tid}, {rows}, 1>": p.timing_read(-2),
-    }
     per_dim = {d: p.timing_read(d) for d in range(prob.ndim)}
+    kern = {}                       # kernel (template instance) -> (launches, total ms)
+    for d, (n, tot) in per_dim.items():
+        name = (f"sldg::{contig}<{prob.k}, {tid}, 1>" if d == 0 else
+                f"sldg::sweep_strided_kernel<{prob.k}, {tid}, {shapes[d]['rows']}, 1>")
+        n0, t0 = kern.get(name, (0, 0.0))
+        kern[name] = (n0 + n, t0 + tot)
     m_end = p.mass(bufs[cur][0])
     drift = abs((m_end[0] + m_end[1]) - (m_start[0] + m_start[1])) / abs(m_start[0] + m_start[1])
     final = bufs[cur]
     return {"plan": p, "ms_per_step": ms, "kernels": kern, "per_dim": per_dim,
-            "mass_drift": drift, "final": final}
+            "mass_drift": drift, "final": final, "shapes": shapes}
 
 
 def cpu_baseline(prob, tier, seconds, seed):
@@ -186,6 +193,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=1603)
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON cache of tuned launch shapes (read if it has the plan, else written)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -214,7 +223,8 @@ def main():
     results = {}
     for t in tiers:
         log(f"bench: timing tier {t}")
-        results[t] = run_tier(sl, torch, prob, t, (mass0, hi0), args.steps, args.warmup)
+        results[t] = run_tier(sl, torch, prob, t, (mass0, hi0), args.steps, args.warmup,
+                              args.tune_cache)
         log(f"bench: {t}: {results[t]['ms_per_step']:.3f} ms/step")
 
     main_r = results[args.tier]
@@ -242,7 +252,8 @@ def main():
             a = tot_d / n
             per_sweep[names.get(d, str(d))] = {
                 "avg_ms": round(a, 4), "GB/s": round(launch_bytes / (a * 1e-3) / 1e9, 1),
-                "frac_hbm_peak": round(launch_bytes / (a * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                "frac_hbm_peak": round(launch_bytes / (a * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "launch_shape": main_r["shapes"][d]}
 
     # mixed vs FP64: speedup and the error of the mixed run against the FP64 run
     tiers_out = {}

@@ -186,6 +186,104 @@ sldg_status sldg_mass(sldg_plan_t plan, const double* mass, double out[2]);
 sldg_status sldg_mass_device(sldg_plan_t plan, const double* mass, double* out_dev);
 
 /*
+ * Launch shape of the sweeps along one dimension.  It changes how the work is
+ * split between threads, never the arithmetic of an output: results are
+ * bitwise the same for every shape.
+ *   rows      strided sweeps (dim > 0): consecutive rows per thread, 1/2/4/8
+ *   tuples    spectator mode tuples per thread (0: all)
+ *   colwaves  strided sweeps: waves of a workgroup side by side along the
+ *             columns (1, 2 or 4; the others stack along the rows)
+ * Plans start from a shape measured on MI355X; sldg_plan_tune picks one per
+ * dimension.  Errors: SLDG_ERR_ARG.
+ */
+sldg_status sldg_plan_set_shape(sldg_plan_t plan, int dim, int rows, int tuples, int colwaves);
+sldg_status sldg_plan_get_shape(sldg_plan_t plan, int dim, int* rows, int* tuples,
+                                int* colwaves);
+
+/* Candidate i of the shapes sldg_plan_tune tries, for dimension-0 (strided =
+ * 0) or strided (strided = 1) sweeps; SLDG_ERR_ARG past the last one. */
+sldg_status sldg_tune_candidate(int strided, int i, int* rows, int* tuples, int* colwaves);
+
+/*
+ * Autotuner: for every dimension swept in `seq`, time each candidate shape
+ * (one warm-up and `reps` timed sweeps from buffer 0 into buffer 1, HIP
+ * events on the plan's stream) and keep the fastest.  Buffer 1 is
+ * overwritten; buffer 0 is only read.  Shapes a grid cannot launch are
+ * skipped.  best_ms (host [nseq], optional) receives the kept time of each
+ * sweep.  Synchronises the plan's stream.
+ */
+sldg_status sldg_plan_tune(sldg_plan_t plan, const sldg_sweep_desc* seq, int nseq,
+                           const double* mass0, const void* hi0, double* mass1, void* hi1,
+                           int reps, double* best_ms);
+
+/*
+ * FP16 storage with per-plane power-of-two scaling (FP16 tier only).
+ *
+ * FP16 has 11 significant bits but only the exponents -14..15 in its normal
+ * range, so the small higher Legendre modes (c_j ~ h^|j| for smooth data,
+ * section II-A) of a state in physical units lose their precision to the
+ * subnormal range or flush to zero.  A scaled FP16 state stores hi plane p
+ * as c * 2^exp[p] and carries a *scale block* beside its mass and hi arrays:
+ *     int32 exp[n_hi]    storage exponent of every hi plane
+ *     float amax[n_hi]   absolute maximum of the values c of every hi plane
+ * (device memory, 8 * n_hi bytes, sldg_scale_bytes; caller-owned like the
+ * state).  The exponent of a plane is chosen so that its absmax sits
+ * `headroom` binades below 2^15: 2^(14-h) <= amax * 2^e < 2^(15-h), clamped
+ * to [-100, 100].  The scaling is exact (powers of two), so the stored value
+ * is the round-to-nearest-even of c onto FP16 with its exponent range moved
+ * by -e, and results do not depend on the units of the state.
+ */
+
+/* Bytes of a scale block of this plan (8 * n_hi); -1 for a NULL plan. */
+int64_t sldg_scale_bytes(sldg_plan_t plan);
+
+/* Headroom h in binades (0..14) of the exponents chosen from now on; the
+ * default is 8. */
+sldg_status sldg_set_scale_headroom(sldg_plan_t plan, int binades);
+
+/*
+ * Scaled FP16 state from FP64 values: for every hi plane, the absmax (rounded
+ * to FP32), the exponent with the plan's headroom (0 for an all-zero plane),
+ * and the FP16 values round(c * 2^e), correctly rounded from FP64.
+ *   hi64   device double [n_hi][cells] (the values of the narrow modes)
+ *   hi     device FP16 [n_hi][cells] (out)
+ *   scale  device scale block (out)
+ * Asynchronous on the plan's stream.  Errors: SLDG_ERR_ARG,
+ * SLDG_ERR_UNSUPPORTED (not an FP16 plan), SLDG_ERR_ALIAS, SLDG_ERR_DEVICE.
+ */
+sldg_status sldg_scaled_import(sldg_plan_t plan, const double* hi64, void* hi, void* scale);
+
+/* The values a scaled FP16 state represents, hi[p][c] * 2^-exp[p], exactly,
+ * into device double [n_hi][cells].  Asynchronous. */
+sldg_status sldg_scaled_export(sldg_plan_t plan, const void* hi, const void* scale,
+                               double* hi64);
+
+/*
+ * sldg_advect_dim on scaled FP16 states.  The exponent of every output plane
+ * is predicted from the input's absmax of the same plane with the plan's
+ * headroom (kept from the input when that absmax is 0); the sweep records the
+ * absmax of what it computes; a plane whose absmax reaches 2^15 at its
+ * predicted exponent (growth by more than the headroom in one sweep) is
+ * recomputed with the exponent of its own absmax and one binade of headroom,
+ * so no value overflows.  The FP64 modes are as in sldg_advect_dim.  Uses a
+ * per-plan partial buffer, grown (hipMalloc) on the first call that needs
+ * more; asynchronous; four launches besides the line tables (predict, sweep,
+ * decide, repair).  Errors as sldg_advect_dim, plus SLDG_ERR_UNSUPPORTED for
+ * a plan that is not FP16 and SLDG_ERR_NOMEM.
+ */
+sldg_status sldg_advect_dim_scaled(sldg_plan_t plan, int dim, const double* shift,
+                                   uint32_t dep_mask, const double* in_mass,
+                                   const void* in_hi, const void* in_scale,
+                                   double* out_mass, void* out_hi, void* out_scale);
+
+/* sldg_split_steps on scaled FP16 states (buffers 0 and 1 each with their
+ * scale block). */
+sldg_status sldg_split_steps_scaled(sldg_plan_t plan, const sldg_sweep_desc* seq, int nseq,
+                                    int nsteps, double* mass0, void* hi0, void* scale0,
+                                    double* mass1, void* hi1, void* scale1,
+                                    int* result_buffer);
+
+/*
  * Kernel timing.  While enabled, every sweep kernel launch of the plan is
  * bracketed by a pair of HIP events recorded on the plan's stream (the line
  * table kernel is outside the pair), up to 4096 launches after enabling.

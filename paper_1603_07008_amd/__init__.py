@@ -22,7 +22,10 @@ EXPORTS = ("sldg_plan", "sldg_plan_destroy", "sldg_plan_set_stream", "sldg_line_
            "sldg_mass_device", "sldg_device_copy", "sldg_advect_dim_adjoint",
            "sldg_batch_create", "sldg_batch_destroy", "sldg_batch_bind", "sldg_batch_set_sequence",
            "sldg_batch_run", "sldg_batch_tune", "sldg_batch_get_tuning", "sldg_batch_set_tuning",
-           "sldg_plan_ex", "sldg_lo_planes", "sldg_hi_planes", "sldg_plane_map")
+           "sldg_plan_ex", "sldg_lo_planes", "sldg_hi_planes", "sldg_plane_map",
+           "sldg_scale_bytes", "sldg_set_scale_headroom", "sldg_scaled_import",
+           "sldg_scaled_export", "sldg_advect_dim_scaled", "sldg_split_steps_scaled",
+           "sldg_plan_set_shape", "sldg_plan_get_shape", "sldg_tune_candidate", "sldg_plan_tune")
 
 
 class SldgError(RuntimeError):
@@ -82,6 +85,30 @@ def lib():
     L.sldg_timing_enable.restype = i32
     L.sldg_timing_read.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
     L.sldg_timing_read.restype = i32
+    L.sldg_scale_bytes.argtypes = [vp]
+    L.sldg_scale_bytes.restype = i64
+    L.sldg_set_scale_headroom.argtypes = [vp, i32]
+    L.sldg_set_scale_headroom.restype = i32
+    L.sldg_scaled_import.argtypes = [vp, vp, vp, vp]
+    L.sldg_scaled_import.restype = i32
+    L.sldg_scaled_export.argtypes = [vp, vp, vp, vp]
+    L.sldg_scaled_export.restype = i32
+    L.sldg_advect_dim_scaled.argtypes = [vp, i32, vp, u32, vp, vp, vp, vp, vp, vp]
+    L.sldg_advect_dim_scaled.restype = i32
+    L.sldg_split_steps_scaled.argtypes = [vp, ctypes.POINTER(SweepDesc), i32, i32, vp, vp, vp,
+                                          vp, vp, vp, ctypes.POINTER(i32)]
+    L.sldg_split_steps_scaled.restype = i32
+    L.sldg_plan_set_shape.argtypes = [vp, i32, i32, i32, i32]
+    L.sldg_plan_set_shape.restype = i32
+    L.sldg_plan_get_shape.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                      ctypes.POINTER(i32)]
+    L.sldg_plan_get_shape.restype = i32
+    L.sldg_tune_candidate.argtypes = [i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                      ctypes.POINTER(i32)]
+    L.sldg_tune_candidate.restype = i32
+    L.sldg_plan_tune.argtypes = [vp, ctypes.POINTER(SweepDesc), i32, vp, vp, vp, vp, i32,
+                                 ctypes.POINTER(ctypes.c_double)]
+    L.sldg_plan_tune.restype = i32
     L.sldg_status_string.argtypes = [i32]
     L.sldg_status_string.restype = ctypes.c_char_p
     L.sldg_last_error.argtypes = []
@@ -254,6 +281,153 @@ class Plan:
                                       _ptr(state1[1]), ctypes.byref(res)), "sldg_split_steps")
         return res.value
 
+    # --- launch shapes and the autotuner -----------------------------------
+
+    def set_shape(self, dim, rows, tuples, colwaves=1):
+        """Launch shape of the sweeps along `dim` (sldg_plan_set_shape)."""
+        _check(lib().sldg_plan_set_shape(self.handle, int(dim), int(rows), int(tuples),
+                                         int(colwaves)), "sldg_plan_set_shape")
+
+    def shape(self, dim):
+        r, t, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().sldg_plan_get_shape(self.handle, int(dim), ctypes.byref(r), ctypes.byref(t),
+                                         ctypes.byref(c)), "sldg_plan_get_shape")
+        return {"rows": r.value, "tuples": t.value, "colwaves": c.value}
+
+    def shapes(self):
+        return [self.shape(d) for d in range(self.ndim)]
+
+    def tune(self, seq, state0, state1, reps=3):
+        """Time the candidate shapes of every swept dimension from state0 into
+        state1 (overwritten) and keep the fastest (sldg_plan_tune).  Returns
+        the per-dimension shapes and the kept time of each sweep of seq."""
+        descs = (SweepDesc * max(1, len(seq)))()
+        for q, (dim, mask, shift) in enumerate(seq):
+            self._check_shift(shift, mask, "tune")
+            descs[q] = SweepDesc(int(dim), int(mask), _ptr(shift))
+        self._check_state(*state0[:2], "tune state0")
+        self._check_state(*state1[:2], "tune state1")
+        ms = (ctypes.c_double * max(1, len(seq)))()
+        _check(lib().sldg_plan_tune(self.handle, descs, len(seq), _ptr(state0[0]),
+                                    _ptr(state0[1]), _ptr(state1[0]), _ptr(state1[1]), int(reps),
+                                    ms), "sldg_plan_tune")
+        return self.shapes(), [ms[q] for q in range(len(seq))]
+
+    def signature(self, seq):
+        """Shape signature (grid, degree, tier, FP64 modes, swept dims and
+        masks) for tuning caches."""
+        import hashlib
+        import json
+        txt = json.dumps([list(self.ncells), self.k, self.tier, self.ndouble,
+                          [(int(d), int(m)) for d, m, _ in seq]])
+        return hashlib.sha256(txt.encode()).hexdigest()[:24]
+
+    def tune_cached(self, path, seq, state0, state1, reps=3):
+        """Shapes from the JSON cache at `path` if it holds this plan's
+        signature, else tune now and store them.  Returns (shapes, cached)."""
+        import json
+        cache = {}
+        if os.path.exists(path):
+            with open(path) as f:
+                cache = json.load(f)
+        key = self.signature(seq)
+        if key in cache:
+            for d, sh in enumerate(cache[key]):
+                self.set_shape(d, sh["rows"], sh["tuples"], sh["colwaves"])
+            return cache[key], True
+        shapes, _ = self.tune(seq, state0, state1, reps)
+        cache[key] = shapes
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1)
+        os.replace(tmp, path)
+        return shapes, False
+
+    # --- FP16 storage with per-plane power-of-two scaling ------------------
+
+    def empty_scale(self, device="cuda"):
+        """An uninitialised scale block: int32 [2, n_hi], row 0 the storage
+        exponents, row 1 the absmax values (float32 bits; see scale_parts)."""
+        import torch
+        return torch.empty((2, self.n_hi), dtype=torch.int32, device=device)
+
+    @staticmethod
+    def scale_parts(scale):
+        """(exponents int32 [n_hi], absmax float32 [n_hi]) views of a scale block."""
+        return scale[0], scale[1].view(__import__("torch").float32)
+
+    def _check_hi(self, hi, what):
+        import torch
+        if not isinstance(hi, torch.Tensor) or not hi.is_cuda or \
+                hi.dtype != hi_dtype(self.tier) or not hi.is_contiguous() or \
+                hi.numel() * hi.element_size() < self.hi_bytes():
+            raise ValueError(f"{what}: hi must be a contiguous {hi_dtype(self.tier)} device "
+                             f"tensor of {self.hi_bytes()} bytes")
+
+    def _check_scale(self, scale, what):
+        import torch
+        if not isinstance(scale, torch.Tensor) or not scale.is_cuda or \
+                scale.dtype != torch.int32 or not scale.is_contiguous() or \
+                scale.numel() < 2 * self.n_hi:
+            raise ValueError(f"{what}: scale block must be a contiguous int32 device tensor of "
+                             f">= {2 * self.n_hi} elements")
+
+    def set_scale_headroom(self, binades):
+        _check(lib().sldg_set_scale_headroom(self.handle, int(binades)), "sldg_set_scale_headroom")
+
+    def scaled_import(self, hi64, hi, scale):
+        """Scaled FP16 planes and scale block from FP64 values [n_hi, cells]."""
+        import torch
+        if not isinstance(hi64, torch.Tensor) or not hi64.is_cuda or \
+                hi64.dtype != torch.float64 or not hi64.is_contiguous() or \
+                hi64.numel() < self.n_hi * self.cells:
+            raise ValueError("scaled_import: hi64 must be contiguous float64 [n_hi, cells] on the device")
+        self._check_hi(hi, "scaled_import")
+        self._check_scale(scale, "scaled_import")
+        _check(lib().sldg_scaled_import(self.handle, _ptr(hi64), _ptr(hi), _ptr(scale)),
+               "sldg_scaled_import")
+
+    def scaled_export(self, hi, scale, hi64=None):
+        """The FP64 values a scaled FP16 state's narrow planes represent."""
+        import torch
+        self._check_hi(hi, "scaled_export")
+        self._check_scale(scale, "scaled_export")
+        if hi64 is None:
+            hi64 = torch.empty((self.n_hi, self.cells), dtype=torch.float64, device=hi.device)
+        _check(lib().sldg_scaled_export(self.handle, _ptr(hi), _ptr(scale), _ptr(hi64)),
+               "sldg_scaled_export")
+        return hi64
+
+    def advect_dim_scaled(self, dim, shift, dep_mask, in_mass, in_hi, in_scale, out_mass,
+                          out_hi, out_scale):
+        """One projection sweep of scaled FP16 states (sldg_advect_dim_scaled)."""
+        self._check_shift(shift, dep_mask, "advect_dim_scaled")
+        self._check_state(in_mass, in_hi, "advect_dim_scaled input")
+        self._check_state(out_mass, out_hi, "advect_dim_scaled output")
+        self._check_scale(in_scale, "advect_dim_scaled input")
+        self._check_scale(out_scale, "advect_dim_scaled output")
+        _check(lib().sldg_advect_dim_scaled(self.handle, int(dim), _ptr(shift), int(dep_mask),
+                                            _ptr(in_mass), _ptr(in_hi), _ptr(in_scale),
+                                            _ptr(out_mass), _ptr(out_hi), _ptr(out_scale)),
+               "sldg_advect_dim_scaled")
+
+    def split_steps_scaled(self, seq, nsteps, state0, state1):
+        """split_steps on scaled FP16 states (mass, hi, scale); returns the
+        index of the state that holds the result."""
+        descs = (SweepDesc * max(1, len(seq)))()
+        for q, (dim, mask, shift) in enumerate(seq):
+            self._check_shift(shift, mask, "split_steps_scaled")
+            descs[q] = SweepDesc(int(dim), int(mask), _ptr(shift))
+        for i, st in enumerate((state0, state1)):
+            self._check_state(st[0], st[1], f"split_steps_scaled state{i}")
+            self._check_scale(st[2], f"split_steps_scaled state{i}")
+        res = ctypes.c_int(-1)
+        _check(lib().sldg_split_steps_scaled(self.handle, descs, len(seq), int(nsteps),
+                                             _ptr(state0[0]), _ptr(state0[1]), _ptr(state0[2]),
+                                             _ptr(state1[0]), _ptr(state1[1]), _ptr(state1[2]),
+                                             ctypes.byref(res)), "sldg_split_steps_scaled")
+        return res.value
+
     def mass(self, mass):
         """Sum of the mass array as a double-double (hi, lo) (sldg_mass);
         synchronises the plan's stream."""
@@ -299,6 +473,21 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def tune_candidates(strided):
+    """The launch shapes sldg_plan_tune tries for dimension-0 (False) or
+    strided (True) sweeps, as dicts."""
+    out = []
+    i = 0
+    while True:
+        r, t, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        st = lib().sldg_tune_candidate(1 if strided else 0, i, ctypes.byref(r), ctypes.byref(t),
+                                       ctypes.byref(c))
+        if st != SLDG_OK:
+            return out
+        out.append({"rows": r.value, "tuples": t.value, "colwaves": c.value})
+        i += 1
 
 
 def device_copy(src, dst, nbytes=None, stream=None):

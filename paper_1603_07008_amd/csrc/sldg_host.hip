@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -38,8 +39,18 @@ struct sldg_plan_s {
   double* d_mass_part;    // [2 * mass_nblocks]
   double* d_mass_out;     // [2]
   double* h_mass_out;     // pinned [2]
-  int rows_per_thread;    // strided sweep: rows per thread (1, 2, 4 or 8)
-  int tuples_per_thread;  // spectator tuples per thread (0: all)
+  // launch shape of the sweeps along each dimension
+  int rows_d[kMaxDim];    // strided sweep: rows per thread (1, 2, 4 or 8)
+  int tuples_d[kMaxDim];  // spectator tuples per thread (0: all)
+  int colwaves_d[kMaxDim];// strided sweep: waves of a workgroup along the columns (1, 2, 4)
+  int xcd_contig;         // XCD-aware tile order (run length) of the dimension-0 sweep
+  int xcd_strided;        // ... and of the strided sweeps
+  // scaled FP16 storage
+  int scale_headroom;     // binades between a plane's absmax and 2^15
+  int32_t* d_hmode;       // [n_hi] mode id of every hi plane
+  int32_t* d_redo;        // [n_hi] planes to recompute after a scaled sweep
+  float* d_part;          // absmax partials, grown on demand
+  int64_t part_cap;       // floats in d_part
   // kernel timing (sldg_timing_*)
   bool timing;
   int ntimed;
@@ -127,6 +138,7 @@ void describe_grid(int ndim, const int64_t* n, int o, int64_t modes, int dim, ui
   a.map = m;
   ntab = str;
   a.tuples = (tuples_per_thread > 0 && tuples_per_thread < a.nspec) ? tuples_per_thread : a.nspec;
+  a.colwaves = 1;
   // strided sweep: rows per thread (one-shot chunks along the swept dim)
   if (dim > 0) {
     int rows = rows_per_thread;
@@ -182,9 +194,21 @@ sldg_status check_sweep(const sldg_plan_s* p, int dim, const double* shift, uint
 
 // Describe the sweep along dim for the kernels (everything but the buffers).
 void describe(const sldg_plan_s* p, int dim, uint32_t dep_mask, SweepArgs& a, int64_t& ntab) {
-  describe_grid(p->ndim, p->n, p->o, p->modes, dim, dep_mask, p->rows_per_thread,
-                p->tuples_per_thread, a, ntab);
+  describe_grid(p->ndim, p->n, p->o, p->modes, dim, dep_mask, p->rows_d[dim], p->tuples_d[dim],
+                a, ntab);
+  a.colwaves = dim > 0 ? p->colwaves_d[dim] : 1;
 }
+
+// Launch shapes the tuner tries: (rows, tuples, column waves).  Dimension-0
+// sweeps only use the tuple count.
+constexpr int kTuneContig[][3] = {{4, 3, 1}, {4, 9, 1}, {4, 27, 1}, {4, 0, 1}};
+constexpr int kTuneStrided[][3] = {
+    {2, 3, 1}, {2, 3, 2}, {2, 3, 4}, {2, 9, 1}, {2, 9, 2}, {2, 9, 4}, {2, 27, 1}, {2, 27, 2},
+    {2, 27, 4}, {4, 3, 1}, {4, 3, 2}, {4, 3, 4}, {4, 9, 1}, {4, 9, 2}, {4, 9, 4}, {4, 27, 1},
+    {4, 27, 2}, {4, 27, 4}, {8, 3, 1}, {8, 3, 2}, {8, 3, 4}, {8, 9, 1}, {8, 9, 2}, {8, 9, 4},
+    {8, 27, 1}, {8, 27, 2}, {8, 27, 4}};
+constexpr int kNumTuneContig = sizeof(kTuneContig) / sizeof(kTuneContig[0]);
+constexpr int kNumTuneStrided = sizeof(kTuneStrided) / sizeof(kTuneStrided[0]);
 
 
 void free_plan(sldg_plan_s* p) {
@@ -195,16 +219,80 @@ void free_plan(sldg_plan_s* p) {
   if (p->d_mass_part) (void)hipFree(p->d_mass_part);
   if (p->d_mass_out) (void)hipFree(p->d_mass_out);
   if (p->d_pmap) (void)hipFree(p->d_pmap);
+  if (p->d_hmode) (void)hipFree(p->d_hmode);
+  if (p->d_redo) (void)hipFree(p->d_redo);
+  if (p->d_part) (void)hipFree(p->d_part);
   if (p->h_mass_out) (void)hipHostFree(p->h_mass_out);
   delete p;
 }
 
+// The absmax partial buffer holds at least n floats (grown with hipMalloc;
+// hipFree of the old one waits for the device).
+sldg_status ensure_part(sldg_plan_s* p, int64_t n) {
+  if (n <= p->part_cap) return SLDG_OK;
+  if (p->d_part) (void)hipFree(p->d_part);
+  p->d_part = nullptr;
+  p->part_cap = 0;
+  hipError_t e = hipMalloc(&p->d_part, sizeof(float) * (size_t)n);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? fail(SLDG_ERR_NOMEM, "absmax partials: %s", hipGetErrorString(e))
+                                    : device_error(e, "absmax partials");
+  }
+  p->part_cap = n;
+  return SLDG_OK;
+}
+
+// Scale block views: int32 exp[n_hi], then float amax[n_hi].
+struct ScaleBlock {
+  int32_t* exp;
+  float* amax;
+};
+ScaleBlock scale_view(const sldg_plan_s* p, const void* blk) {
+  int32_t* e = static_cast<int32_t*>(const_cast<void*>(blk));
+  return {e, reinterpret_cast<float*>(e + p->n_hi)};
+}
+
+sldg_status check_scaled(const sldg_plan_s* p, const void* in_scale, const void* out_scale,
+                         const void* const* bufs, const int64_t* sizes, int nbuf) {
+  if (p->tier != SLDG_TIER_FP16)
+    return fail(SLDG_ERR_UNSUPPORTED, "scaled storage needs an FP16-tier plan");
+  if (!in_scale || !out_scale) return fail(SLDG_ERR_ARG, "null scale block");
+  const int64_t sb = 8 * p->n_hi;
+  if (((uintptr_t)in_scale | (uintptr_t)out_scale) & 3)
+    return fail(SLDG_ERR_ARG, "scale blocks must be 4-byte aligned");
+  if (sb > 0 && overlap(in_scale, sb, out_scale, sb))
+    return fail(SLDG_ERR_ALIAS, "input and output scale blocks overlap");
+  for (int i = 0; i < nbuf; ++i)
+    if (sb > 0 && sizes[i] > 0 && bufs[i] &&
+        (overlap(out_scale, sb, bufs[i], sizes[i]) || overlap(in_scale, sb, bufs[i], sizes[i])))
+      return fail(SLDG_ERR_ALIAS, "a scale block overlaps a state buffer");
+  return SLDG_OK;
+}
+
 sldg_status run_sweep(sldg_plan_s* p, int dim, const double* shift, uint32_t dep_mask,
                       const double* in_lo, const void* in_hi, double* out_lo, void* out_hi,
-                      bool adjoint = false) {
+                      bool adjoint = false, const void* in_scale = nullptr,
+                      void* out_scale = nullptr) {
   SweepArgs a{};
   int64_t ntab = 0;
   describe(p, dim, dep_mask, a, ntab);
+  a.xcd = dim == 0 ? p->xcd_contig : p->xcd_strided;
+  const bool scaled = in_scale != nullptr;
+  ScaleBlock sin{}, sout{};
+  if (scaled) {
+    const int64_t nslot = sweep_slots(dim, a);
+    if (nslot < 0 || nslot > INT32_MAX)
+      return fail(SLDG_ERR_UNSUPPORTED, "sweep along dim %d: grid too large for one launch", dim);
+    sldg_status st = ensure_part(p, std::max<int64_t>(1, p->n_hi * nslot));
+    if (st != SLDG_OK) return st;
+    sin = scale_view(p, in_scale);
+    sout = scale_view(p, out_scale);
+    a.in_exp = sin.exp;
+    a.out_exp = sout.exp;
+    a.amax_part = p->d_part;
+    a.nslot = (int32_t)nslot;
+  }
   if (ntab > p->table_cap)
     return fail(SLDG_ERR_ARG, "line table of %lld entries exceeds the plan's %lld",
                 (long long)ntab, (long long)p->table_cap);
@@ -233,10 +321,22 @@ sldg_status run_sweep(sldg_plan_s* p, int dim, const double* shift, uint32_t dep
     e = hipEventRecord(p->ev[2 * i], p->stream);
     if (e != hipSuccess) return device_error(e, "hipEventRecord");
   }
+  if (scaled) {
+    e = launch_scale_predict(p->n_hi, sin.exp, sin.amax, sout.exp, p->scale_headroom, p->d_part,
+                             p->n_hi * (int64_t)a.nslot, p->stream);
+    if (e != hipSuccess) return device_error(e, "scale prediction launch");
+  }
   e = launch_sweep(p->k, (int)p->tier, dim, a, p->stream);
   if (e == hipErrorInvalidConfiguration)
     return fail(SLDG_ERR_UNSUPPORTED, "sweep along dim %d: grid too large for one launch", dim);
   if (e != hipSuccess) return device_error(e, "sweep launch");
+  if (scaled) {
+    e = launch_scale_decide(p->n_hi, p->d_part, a.nslot, sout.exp, sout.amax, p->d_redo,
+                            p->stream);
+    if (e != hipSuccess) return device_error(e, "scale decision launch");
+    e = launch_scale_redo(p->k, dim, a, p->n_hi, p->d_redo, p->d_hmode, p->stream);
+    if (e != hipSuccess) return device_error(e, "scale repair launch");
+  }
   if (timed) {
     const int i = p->ntimed;
     e = hipEventRecord(p->ev[2 * i + 1], p->stream);
@@ -312,15 +412,30 @@ sldg_status sldg_plan_ex(sldg_plan_t* out, int ndim, const int64_t* ncells, int 
   p->lo_bytes = p->n_lo * cells * 8;
   p->hi_bytes = p->n_hi * cells * elem_size(tier);
   p->table_cap = cells / min_n;     // the most lines any sweep can have
-  p->rows_per_thread = 4;      // measured best on MI355X for the 4D k = 2 workload
-  p->tuples_per_thread = 9;
+  // default launch shape (measured on MI355X for the 4D k = 2 workload; the
+  // tuner picks per dimension), overridable from the environment
+  int rows = 4, tuples = 9, colwaves = 1;
+  p->xcd_contig = 8;           // run lengths measured best on MI355X (4D k = 2)
+  p->xcd_strided = 16;
+  if (const char* env = getenv("SLDG_COLWAVES")) {
+    const int c = atoi(env);
+    if (c == 1 || c == 2 || c == 4) colwaves = c;
+  }
+  if (const char* env = getenv("SLDG_XCD_CONTIG")) p->xcd_contig = std::max(-1, atoi(env));
+  if (const char* env = getenv("SLDG_XCD_STRIDED")) p->xcd_strided = std::max(-1, atoi(env));
+  p->scale_headroom = 8;
   if (const char* env = getenv("SLDG_TUPLES")) {
     const int g = atoi(env);
-    if (g >= 0) p->tuples_per_thread = g;
+    if (g >= 0) tuples = g;
   }
   if (const char* env = getenv("SLDG_STRIDED_ROWS")) {
     const int r = atoi(env);
-    if (r == 1 || r == 2 || r == 4 || r == 8) p->rows_per_thread = r;
+    if (r == 1 || r == 2 || r == 4 || r == 8) rows = r;
+  }
+  for (int d = 0; d < kMaxDim; ++d) {
+    p->rows_d[d] = rows;
+    p->tuples_d[d] = tuples;
+    p->colwaves_d[d] = colwaves;
   }
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) {
@@ -337,6 +452,15 @@ sldg_status sldg_plan_ex(sldg_plan_t* out, int ndim, const int64_t* ncells, int 
   if (e == hipSuccess) e = hipMalloc(&p->d_pmap, sizeof(int32_t) * p->modes);
   if (e == hipSuccess)
     e = hipMemcpy(p->d_pmap, p->h_pmap.data(), sizeof(int32_t) * p->modes, hipMemcpyHostToDevice);
+  if (e == hipSuccess && tier == SLDG_TIER_FP16 && p->n_hi > 0) {
+    std::vector<int32_t> hmode((size_t)p->n_hi);
+    for (int64_t m = 0; m < p->modes; ++m)
+      if (p->h_pmap[m] >= 0) hmode[(size_t)p->h_pmap[m]] = (int32_t)m;
+    e = hipMalloc(&p->d_hmode, sizeof(int32_t) * p->n_hi);
+    if (e == hipSuccess) e = hipMalloc(&p->d_redo, sizeof(int32_t) * p->n_hi);
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_hmode, hmode.data(), sizeof(int32_t) * p->n_hi, hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) {
     const bool nomem = (e == hipErrorOutOfMemory);
     free_plan(p);
@@ -457,6 +581,216 @@ sldg_status sldg_split_steps(sldg_plan_t p, const sldg_sweep_desc* seq, int nseq
       cur = 1 - cur;
     }
   }
+  if (result_buffer) *result_buffer = cur;
+  return ok();
+}
+
+sldg_status sldg_plan_set_shape(sldg_plan_t p, int dim, int rows, int tuples, int colwaves) {
+  if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
+  if (dim < 0 || dim >= p->ndim) return fail(SLDG_ERR_ARG, "dim %d out of range", dim);
+  if (!(rows == 1 || rows == 2 || rows == 4 || rows == 8))
+    return fail(SLDG_ERR_ARG, "rows %d not in {1, 2, 4, 8}", rows);
+  if (tuples < 0) return fail(SLDG_ERR_ARG, "tuples %d < 0", tuples);
+  if (!(colwaves == 1 || colwaves == 2 || colwaves == 4))
+    return fail(SLDG_ERR_ARG, "colwaves %d not in {1, 2, 4}", colwaves);
+  p->rows_d[dim] = rows;
+  p->tuples_d[dim] = tuples;
+  p->colwaves_d[dim] = colwaves;
+  return ok();
+}
+
+sldg_status sldg_plan_get_shape(sldg_plan_t p, int dim, int* rows, int* tuples, int* colwaves) {
+  if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
+  if (dim < 0 || dim >= p->ndim) return fail(SLDG_ERR_ARG, "dim %d out of range", dim);
+  if (rows) *rows = p->rows_d[dim];
+  if (tuples) *tuples = p->tuples_d[dim];
+  if (colwaves) *colwaves = p->colwaves_d[dim];
+  return ok();
+}
+
+sldg_status sldg_tune_candidate(int strided, int i, int* rows, int* tuples, int* colwaves) {
+  const int n = strided ? kNumTuneStrided : kNumTuneContig;
+  if (i < 0 || i >= n) return fail(SLDG_ERR_ARG, "candidate %d out of range [0, %d)", i, n);
+  const int* c = strided ? kTuneStrided[i] : kTuneContig[i];
+  if (rows) *rows = c[0];
+  if (tuples) *tuples = c[1];
+  if (colwaves) *colwaves = c[2];
+  return ok();
+}
+
+sldg_status sldg_plan_tune(sldg_plan_t p, const sldg_sweep_desc* seq, int nseq,
+                           const double* mass0, const void* hi0, double* mass1, void* hi1,
+                           int reps, double* best_ms) {
+  if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
+  if (nseq < 0 || (nseq > 0 && !seq) || reps < 1)
+    return fail(SLDG_ERR_ARG, "bad sweep sequence or reps (nseq=%d reps=%d)", nseq, reps);
+  for (int q = 0; q < nseq; ++q) {
+    sldg_status st = check_sweep(p, seq[q].dim, seq[q].shift, seq[q].dep_mask, mass0, hi0, mass1,
+                                 hi1);
+    if (st != SLDG_OK) return st;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return device_error(e, "hipEventCreate");
+  }
+  const bool timing = p->timing;
+  p->timing = false;
+  double tuned_ms[kMaxDim];
+  bool done[kMaxDim] = {};
+  sldg_status st = SLDG_OK;
+  for (int q = 0; q < nseq && st == SLDG_OK; ++q) {
+    const int dim = seq[q].dim;
+    if (done[dim]) {
+      if (best_ms) best_ms[q] = tuned_ms[dim];
+      continue;
+    }
+    const bool strided = dim > 0;
+    const int n = strided ? kNumTuneStrided : kNumTuneContig;
+    const int keep[3] = {p->rows_d[dim], p->tuples_d[dim], p->colwaves_d[dim]};
+    double best = -1.0;
+    int bi = -1;
+    for (int i = 0; i < n && st == SLDG_OK; ++i) {
+      const int* c = strided ? kTuneStrided[i] : kTuneContig[i];
+      p->rows_d[dim] = c[0];
+      p->tuples_d[dim] = c[1];
+      p->colwaves_d[dim] = c[2];
+      st = run_sweep(p, dim, seq[q].shift, seq[q].dep_mask, mass0, hi0, mass1, hi1);
+      if (st == SLDG_ERR_UNSUPPORTED) {    // shape not launchable on this grid: skip it
+        st = SLDG_OK;
+        continue;
+      }
+      if (st != SLDG_OK) break;
+      e = hipEventRecord(e0, p->stream);
+      for (int r = 0; r < reps && st == SLDG_OK && e == hipSuccess; ++r)
+        st = run_sweep(p, dim, seq[q].shift, seq[q].dep_mask, mass0, hi0, mass1, hi1);
+      if (st != SLDG_OK) break;
+      if (e == hipSuccess) e = hipEventRecord(e1, p->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        st = device_error(e, "tuning events");
+        break;
+      }
+      const double avg = ms / reps;
+      if (bi < 0 || avg < best) {
+        best = avg;
+        bi = i;
+      }
+    }
+    if (st == SLDG_OK && bi < 0)
+      st = fail(SLDG_ERR_UNSUPPORTED, "no launch shape fits the sweep along dim %d", dim);
+    if (st != SLDG_OK) {
+      p->rows_d[dim] = keep[0];
+      p->tuples_d[dim] = keep[1];
+      p->colwaves_d[dim] = keep[2];
+      break;
+    }
+    const int* c = strided ? kTuneStrided[bi] : kTuneContig[bi];
+    p->rows_d[dim] = c[0];
+    p->tuples_d[dim] = c[1];
+    p->colwaves_d[dim] = c[2];
+    tuned_ms[dim] = best;
+    done[dim] = true;
+    if (best_ms) best_ms[q] = best;
+  }
+  p->timing = timing;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st == SLDG_OK ? ok() : st;
+}
+
+int64_t sldg_scale_bytes(sldg_plan_t p) { return p ? 8 * p->n_hi : -1; }
+
+sldg_status sldg_set_scale_headroom(sldg_plan_t p, int binades) {
+  if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
+  if (binades < 0 || binades > 14) return fail(SLDG_ERR_ARG, "headroom %d not in [0, 14]", binades);
+  p->scale_headroom = binades;
+  return ok();
+}
+
+sldg_status sldg_scaled_import(sldg_plan_t p, const double* hi64, void* hi, void* scale) {
+  if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
+  if (p->tier != SLDG_TIER_FP16)
+    return fail(SLDG_ERR_UNSUPPORTED, "scaled storage needs an FP16-tier plan");
+  if (p->n_hi == 0) return ok();
+  if (!hi64 || !hi || !scale) return fail(SLDG_ERR_ARG, "null pointer");
+  if ((uintptr_t)scale & 3) return fail(SLDG_ERR_ARG, "scale block must be 4-byte aligned");
+  const int64_t b64 = p->n_hi * p->cells * 8, sb = 8 * p->n_hi;
+  if (overlap(hi64, b64, hi, p->hi_bytes) || overlap(hi64, b64, scale, sb) ||
+      overlap(hi, p->hi_bytes, scale, sb))
+    return fail(SLDG_ERR_ALIAS, "import buffers overlap");
+  if (p->n_hi > 65535) return fail(SLDG_ERR_UNSUPPORTED, "too many planes for the import grid");
+  sldg_status st = ensure_part(p, p->n_hi * (int64_t)kImportSlots);
+  if (st != SLDG_OK) return st;
+  ScaleBlock sc = scale_view(p, scale);
+  hipError_t e = launch_scale_import(hi64, p->n_hi, p->cells, p->scale_headroom, p->d_part,
+                                     kImportSlots, hi, sc.exp, sc.amax, p->stream);
+  if (e != hipSuccess) return device_error(e, "scaled import launch");
+  return ok();
+}
+
+sldg_status sldg_scaled_export(sldg_plan_t p, const void* hi, const void* scale, double* hi64) {
+  if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
+  if (p->tier != SLDG_TIER_FP16)
+    return fail(SLDG_ERR_UNSUPPORTED, "scaled storage needs an FP16-tier plan");
+  if (p->n_hi == 0) return ok();
+  if (!hi64 || !hi || !scale) return fail(SLDG_ERR_ARG, "null pointer");
+  const int64_t b64 = p->n_hi * p->cells * 8;
+  if (overlap(hi64, b64, hi, p->hi_bytes) || overlap(hi64, b64, scale, 8 * p->n_hi))
+    return fail(SLDG_ERR_ALIAS, "export buffers overlap");
+  ScaleBlock sc = scale_view(p, scale);
+  hipError_t e = launch_scale_export(hi, p->n_hi, p->cells, sc.exp, hi64, p->stream);
+  if (e != hipSuccess) return device_error(e, "scaled export launch");
+  return ok();
+}
+
+sldg_status sldg_advect_dim_scaled(sldg_plan_t p, int dim, const double* shift,
+                                   uint32_t dep_mask, const double* in_mass, const void* in_hi,
+                                   const void* in_scale, double* out_mass, void* out_hi,
+                                   void* out_scale) {
+  sldg_status st = check_sweep(p, dim, shift, dep_mask, in_mass, in_hi, out_mass, out_hi);
+  if (st != SLDG_OK) return st;
+  const void* bufs[4] = {in_mass, in_hi, out_mass, out_hi};
+  const int64_t sizes[4] = {p->lo_bytes, p->hi_bytes, p->lo_bytes, p->hi_bytes};
+  st = check_scaled(p, in_scale, out_scale, bufs, sizes, 4);
+  if (st != SLDG_OK) return st;
+  st = run_sweep(p, dim, shift, dep_mask, in_mass, in_hi, out_mass, out_hi, false, in_scale,
+                 out_scale);
+  return st == SLDG_OK ? ok() : st;
+}
+
+sldg_status sldg_split_steps_scaled(sldg_plan_t p, const sldg_sweep_desc* seq, int nseq,
+                                    int nsteps, double* mass0, void* hi0, void* scale0,
+                                    double* mass1, void* hi1, void* scale1,
+                                    int* result_buffer) {
+  if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
+  if (nseq < 0 || nsteps < 0 || (nseq > 0 && !seq))
+    return fail(SLDG_ERR_ARG, "bad sweep sequence (nseq=%d nsteps=%d)", nseq, nsteps);
+  double* m[2] = {mass0, mass1};
+  void* h[2] = {hi0, hi1};
+  void* sc[2] = {scale0, scale1};
+  const void* bufs[4] = {mass0, hi0, mass1, hi1};
+  const int64_t sizes[4] = {p->lo_bytes, p->hi_bytes, p->lo_bytes, p->hi_bytes};
+  sldg_status st = check_scaled(p, scale0, scale1, bufs, sizes, 4);
+  if (st != SLDG_OK) return st;
+  for (int q = 0; q < nseq; ++q)
+    for (int b = 0; b < 2; ++b) {
+      st = check_sweep(p, seq[q].dim, seq[q].shift, seq[q].dep_mask, m[b], h[b], m[1 - b],
+                       h[1 - b]);
+      if (st != SLDG_OK) return st;
+    }
+  int cur = 0;
+  for (int n = 0; n < nsteps; ++n)
+    for (int q = 0; q < nseq; ++q) {
+      st = run_sweep(p, seq[q].dim, seq[q].shift, seq[q].dep_mask, m[cur], h[cur], m[1 - cur],
+                     h[1 - cur], false, sc[cur], sc[1 - cur]);
+      if (st != SLDG_OK) return st;
+      cur = 1 - cur;
+    }
   if (result_buffer) *result_buffer = cur;
   return ok();
 }

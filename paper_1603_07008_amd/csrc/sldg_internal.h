@@ -66,10 +66,17 @@ struct SweepArgs {
   int32_t nchunk;         // strided sweep: chunks along the swept dim
   int32_t chunk;          // strided sweep: rows per thread (1, 2, 4 or 8)
   int32_t tuples;         // spectator tuples per thread (a run; blockIdx.y picks it)
+  int32_t colwaves;       // strided sweep: waves of a workgroup side by side (1, 2 or 4)
   FastDiv fP;             // division by P
   FastDiv fN;             // division by N
   FastDiv fchunk;         // division by nchunk
   LineMap map;
+  int32_t xcd;            // XCD-aware tile order: run length G (0 off, -1 one range per XCD)
+  // FP16 storage with per-plane power-of-two scaling (all null: unscaled)
+  const int32_t* in_exp;  // [n_hi] storage exponent of every input hi plane
+  const int32_t* out_exp; // [n_hi] exponent every output hi plane is written with
+  float* amax_part;       // [n_hi][nslot] per-wave absmax of the outputs (before scaling)
+  int32_t nslot;          // partial slots per plane of the launch (sweep_slots)
 };
 
 // One workgroup-sized tile of one problem of a batched sweep.
@@ -93,6 +100,34 @@ hipError_t launch_batch_sweep(int tier, int rows, const SweepArgs* args, const i
                               const BatchItem* items, int32_t nitems, int32_t grid,
                               hipStream_t st);
 bool contig_window_ok(const SweepArgs& a);
+// Waves of one sweep launch that compute a given output plane (the absmax
+// partial slots per plane of a scaled FP16 sweep).
+int64_t sweep_slots(int dim, const SweepArgs& a);
+
+// Scaled FP16 storage (sldg_kernels.hip).  A scale block holds int32 exp[n_hi]
+// followed by float amax[n_hi].
+//   predict: out exp from the input's absmax (or the input exp when that is
+//            0) with `headroom` binades; zeroes the partials.
+//   decide:  out amax = max of the partials; a plane whose absmax reaches
+//            2^15 at its predicted exponent gets the exponent of its absmax
+//            with one binade of headroom and is flagged in redo[].
+//   redo:    recomputes the flagged planes with their final exponents.
+hipError_t launch_scale_predict(int64_t n_hi, const int32_t* in_exp, const float* in_amax,
+                                int32_t* out_exp, int headroom, float* part, int64_t npart,
+                                hipStream_t st);
+hipError_t launch_scale_decide(int64_t n_hi, const float* part, int32_t nslot, int32_t* out_exp,
+                               float* out_amax, int32_t* redo, hipStream_t st);
+hipError_t launch_scale_redo(int k, int dim, const SweepArgs& a, int64_t n_hi,
+                             const int32_t* redo, const int32_t* hi_mode, hipStream_t st);
+// import: absmax and exponent of every plane of an FP64 array [n_hi][cells],
+// then the scaled RNE conversion to FP16.  export: the values the FP16 planes
+// represent, in FP64.
+hipError_t launch_scale_import(const double* src, int64_t n_hi, int64_t cells, int headroom,
+                               float* part, int32_t nslot, void* dst, int32_t* exp, float* amax,
+                               hipStream_t st);
+hipError_t launch_scale_export(const void* src, int64_t n_hi, int64_t cells, const int32_t* exp,
+                               double* dst, hipStream_t st);
+constexpr int kImportSlots = 256;
 hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t st);
 
 int mass_blocks(int64_t n);

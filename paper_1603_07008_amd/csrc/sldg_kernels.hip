@@ -15,6 +15,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "ab_poly.h"
@@ -26,11 +27,14 @@ namespace sldg {
 // Storage tiers (section II-A: c_0 in FP64, the higher modes narrower)
 // ---------------------------------------------------------------------------
 
+// T: storage type of the narrow modes; Acc: arithmetic type of their update;
+// R: register type of a loaded narrow value (the FP16 tier widens on load,
+// where its per-mode storage scale is removed).
 template <int TIER> struct Tier;
-template <> struct Tier<0> { using T = double;   using Acc = double; };
-template <> struct Tier<1> { using T = float;    using Acc = double; };
-template <> struct Tier<2> { using T = __bf16;   using Acc = float;  };
-template <> struct Tier<3> { using T = _Float16; using Acc = float;  };
+template <> struct Tier<0> { using T = double;   using Acc = double; using R = double; };
+template <> struct Tier<1> { using T = float;    using Acc = double; using R = float;  };
+template <> struct Tier<2> { using T = __bf16;   using Acc = float;  using R = __bf16; };
+template <> struct Tier<3> { using T = _Float16; using Acc = float;  using R = float;  };
 
 // Exact widening of a stored value to FP64 / FP32.
 __device__ __forceinline__ double widen(double v) { return v; }
@@ -207,9 +211,9 @@ __device__ __forceinline__ TupleMap tuple_map(const SweepArgs& a, int32_t m0, in
 template <int K, int TIER, int ND>
 struct Raw {
   static constexpr int O = K + 1;
-  using T = typename Tier<TIER>::T;
+  using R = typename Tier<TIER>::R;
   double d[O];   // modes l < ND
-  T h[O];        // modes l >= ND
+  R h[O];        // modes l >= ND
 };
 
 // Copy of the fields a tuple with ND leading FP64 modes uses (whole-struct
@@ -286,16 +290,43 @@ struct Mat {
     return acc;
   }
   template <int ND>
-  __device__ __forceinline__ T out_t(int j, const Raw<K, TIER, ND>& x,
-                                     const Raw<K, TIER, ND>& y) const {
+  __device__ __forceinline__ Acc out_acc(int j, const Raw<K, TIER, ND>& x,
+                                         const Raw<K, TIER, ND>& y) const {
     Acc acc = 0;
 #pragma unroll
     for (int l = 0; l < O; ++l) acc = fma(Aa[j][l], acc_of(x, l), acc);
 #pragma unroll
     for (int l = 0; l < O; ++l) acc = fma(Ba[j][l], acc_of(y, l), acc);
-    return narrow<T>(acc);
+    return acc;
   }
 };
+
+// ---------------------------------------------------------------------------
+// FP16 storage with per-mode power-of-two scaling.  A narrow plane p of an
+// FP16 state may hold c * 2^e[p]: loads multiply by 2^-e of the input plane
+// (exact), stores by 2^e of the output plane before the RNE conversion (exact
+// scaling, so the stored value is the rounding of c onto FP16 with its
+// exponent range moved by -e).  With scaling on, every wave also records the
+// absolute maximum of each output plane it computed (before scaling) in a
+// partial array [plane][slot], one slot per wave, from which a follow-up
+// kernel takes the plane's absmax.  Unscaled FP16 runs the same code with
+// factors 1.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float pow2f(int32_t e) { return __builtin_amdgcn_ldexpf(1.0f, e); }
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Stored value -> register value (the FP16 tier widens and unscales).
+template <int TIER, class T>
+__device__ __forceinline__ typename Tier<TIER>::R to_reg(T v, float fin) {
+  if constexpr (TIER == 3) return (float)v * fin;
+  else return v;
+}
 
 // Plane pointers of one spectator tuple.
 template <int K, int TIER, int ND>
@@ -306,6 +337,8 @@ struct Planes {
   double* outd[O];
   const T* inh[O];
   T* outh[O];
+  float fin[O], fout[O];   // FP16 tier: 2^-e of the input planes, 2^e of the output planes
+  int32_t hp[O];           // FP16 tier: hi plane of mode l (absmax partials)
 
   __device__ __forceinline__ void bind(const SweepArgs& a, const TupleMap& tm) {
     const T* hin = reinterpret_cast<const T*>(a.in_hi);
@@ -319,6 +352,16 @@ struct Planes {
       } else {
         inh[l] = hin + off;
         outh[l] = hout + off;
+        if constexpr (TIER == 3) {
+          hp[l] = tm.idx[l];
+          if (a.in_exp) {
+            fin[l] = pow2f(-a.in_exp[tm.idx[l]]);
+            fout[l] = pow2f(a.out_exp[tm.idx[l]]);
+          } else {
+            fin[l] = 1.0f;
+            fout[l] = 1.0f;
+          }
+        }
       }
     }
   }
@@ -326,7 +369,7 @@ struct Planes {
 #pragma unroll
     for (int l = 0; l < O; ++l) {
       if (l < ND) r.d[l] = ind[l][c];
-      else r.h[l] = inh[l][c];
+      else r.h[l] = to_reg<TIER>(inh[l][c], fin[l]);
     }
   }
   __device__ __forceinline__ void copy_from(const Planes& o) {
@@ -338,19 +381,62 @@ struct Planes {
       } else {
         inh[l] = o.inh[l];
         outh[l] = o.outh[l];
+        if constexpr (TIER == 3) {
+          fin[l] = o.fin[l];
+          fout[l] = o.fout[l];
+          hp[l] = o.hp[l];
+        }
       }
     }
   }
+  // Narrow output j: the FP16 tier records |acc| in am[j] and stores acc * 2^e.
+  __device__ __forceinline__ T put(int j, typename Tier<TIER>::Acc acc, float (&am)[O]) const {
+    if constexpr (TIER == 3) {
+      am[j] = fmaxf(am[j], fabsf(acc));
+      return (T)(acc * fout[j]);
+    } else {
+      return narrow<T>(acc);
+    }
+  }
   __device__ __forceinline__ void store(int64_t c, const Mat<K, TIER>& M, const Rows64<K, ND>& R,
-                                        const Raw<K, TIER, ND>& x,
-                                        const Raw<K, TIER, ND>& y) const {
+                                        const Raw<K, TIER, ND>& x, const Raw<K, TIER, ND>& y,
+                                        float (&am)[O], bool active) const {
 #pragma unroll
     for (int j = 0; j < O; ++j) {
-      if (j < ND) outd[j][c] = Mat<K, TIER>::out64(R, j, x, y);
-      else outh[j][c] = M.out_t(j, x, y);
+      if (j < ND) {
+        const double v = Mat<K, TIER>::out64(R, j, x, y);
+        if (active) outd[j][c] = v;
+      } else {
+        const T v = put(j, M.out_acc(j, x, y), am);
+        if (active) outh[j][c] = v;
+      }
     }
   }
 };
+
+// End of one tuple of a wave in a scaled FP16 sweep: the wave's absmax of
+// each narrow output plane goes to slot `slot` of that plane's partials.
+// Every lane of the wave must be here (lanes beyond the grid work on a
+// duplicate of a valid cell and do not store).
+template <int K, int TIER, int ND>
+__device__ __forceinline__ void flush_amax(const SweepArgs& a, const Planes<K, TIER, ND>& pl,
+                                           const float (&am)[K + 1], int32_t slot) {
+  if constexpr (TIER == 3) {
+    if (a.amax_part) {
+#pragma unroll
+      for (int l = ND; l < K + 1; ++l) {
+        const float m = wave_max(am[l]);
+        if ((threadIdx.x & 63) == 0) a.amax_part[(int64_t)pl.hp[l] * a.nslot + slot] = m;
+      }
+    }
+  }
+}
+
+template <int O>
+__device__ __forceinline__ void zero_amax(float (&am)[O]) {
+#pragma unroll
+  for (int l = 0; l < O; ++l) am[l] = 0.0f;
+}
 
 // Dispatch on the number of leading FP64 modes of a tuple (0 .. NDMAX).
 // Kernels are instantiated with NDMAX = 1 (the cell mean alone in FP64, or
@@ -379,6 +465,8 @@ __device__ __forceinline__ void dispatch_nd(int nd, F&& f) {
 template <int K, int TIER, int ND>
 __device__ __forceinline__ void contig_line(const SweepArgs& a, int64_t line, const TupleMap& tm,
                                             int lane) {
+  float am[K + 1];
+  zero_amax(am);
   Mat<K, TIER> M;
   Rows64<K, ND> R;
   Planes<K, TIER, ND> pl;
@@ -397,8 +485,9 @@ __device__ __forceinline__ void contig_line(const SweepArgs& a, int64_t line, co
     Raw<K, TIER, ND> x, y;
     pl.load(base + ia, x);
     pl.load(base + ib, y);
-    pl.store(base + i, M, R, x, y);
+    pl.store(base + i, M, R, x, y, am, true);
   }
+  flush_amax<K, TIER, ND>(a, pl, am, (int32_t)line);   // one wave per (line, tuple)
 }
 
 template <int K, int TIER, int NDMAX>
@@ -517,44 +606,49 @@ __device__ __forceinline__ void contig_load(const Planes<K, TIER, ND>& pl, int64
       T h[5];
       window5<T>(load4(pl.inh[l] + lb + 4 * blk0), load4(pl.inh[l] + lb + 4 * blk1), d, h);
 #pragma unroll
-      for (int u = 0; u < 5; ++u) W.w[u].h[l] = h[u];
+      for (int u = 0; u < 5; ++u) W.w[u].h[l] = to_reg<TIER>(h[u], pl.fin[l]);
     }
   }
 }
 
 template <int K, int TIER, int ND>
-__device__ __forceinline__ void contig_store(const Planes<K, TIER, ND>& pl, int64_t c,
-                                             const Mat<K, TIER>& M, const Rows64<K, ND>& R,
-                                             const Win<K, TIER, ND>& W) {
+__device__ __forceinline__ void contig_store(const SweepArgs& a, const Planes<K, TIER, ND>& pl,
+                                             int64_t c, const Mat<K, TIER>& M,
+                                             const Rows64<K, ND>& R, const Win<K, TIER, ND>& W,
+                                             int32_t slot, bool active) {
   constexpr int O = K + 1;
   using T = typename Tier<TIER>::T;
+  float am[O];
+  zero_amax(am);
 #pragma unroll
   for (int j = 0; j < O; ++j) {
     if (j < ND) {
       double o4[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) o4[u] = Mat<K, TIER>::out64(R, j, W.w[u + 1], W.w[u]);
-      store4<double>(pl.outd[j] + c, o4);
+      if (active) store4<double>(pl.outd[j] + c, o4);
     } else {
       T o4[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) o4[u] = M.out_t(j, W.w[u + 1], W.w[u]);
-      store4<T>(pl.outh[j] + c, o4);
+      for (int u = 0; u < 4; ++u) o4[u] = pl.put(j, M.out_acc(j, W.w[u + 1], W.w[u]), am);
+      if (active) store4<T>(pl.outh[j] + c, o4);
     }
   }
+  flush_amax<K, TIER, ND>(a, pl, am, slot);
 }
 
 template <int K, int TIER, int ND>
 __device__ __forceinline__ void contig_single(const SweepArgs& a, const TupleMap& tm,
                                               const Mat<K, TIER>& M, int64_t lb, int32_t blk0,
-                                              int32_t blk1, int d, int64_t c) {
+                                              int32_t blk1, int d, int64_t c, int32_t slot,
+                                              bool active) {
   Planes<K, TIER, ND> pl;
   pl.bind(a, tm);
   Rows64<K, ND> R;
   R.load(M.ab, M.cs);
   Win<K, TIER, ND> W;
   contig_load<K, TIER, ND>(pl, lb, blk0, blk1, d, W);
-  contig_store<K, TIER, ND>(pl, c, M, R, W);
+  contig_store<K, TIER, ND>(a, pl, c, M, R, W, slot, active);
 }
 
 // One thread: 4 consecutive output cells of one line, for the spectator
@@ -566,7 +660,8 @@ __device__ __forceinline__ void contig_single(const SweepArgs& a, const TupleMap
 // entry is read with scalar loads and the matrices live in scalar registers.
 template <int K, int TIER, int NDMAX>
 __device__ __forceinline__ void contig_body(const SweepArgs& a, int32_t c, int32_t line,
-                                            int32_t i0, int32_t t, int32_t q, int32_t qe) {
+                                            int32_t i0, int32_t t, int32_t q, int32_t qe,
+                                            int32_t slot, bool active) {
   constexpr int O = K + 1;
   const int32_t N = a.N;
   const int32_t s = a.s_tab[t];
@@ -582,7 +677,8 @@ __device__ __forceinline__ void contig_body(const SweepArgs& a, int32_t c, int32
     TupleMap tm = tuple_map(a, q * O, 1, O);
     if (tm.nd != 0) {
       dispatch_nd<NDMAX>(tm.nd, [&](auto ndc) {
-        contig_single<K, TIER, decltype(ndc)::value>(a, tm, M, lb, blk0, blk1, d, c);
+        contig_single<K, TIER, decltype(ndc)::value>(a, tm, M, lb, blk0, blk1, d, c, slot,
+                                                     active);
       });
       ++q;
       continue;
@@ -603,7 +699,7 @@ __device__ __forceinline__ void contig_body(const SweepArgs& a, int32_t c, int32
           contig_load<K, TIER, 0>(pn, lb, blk0, blk1, d, nxt);
         }
       }
-      contig_store<K, TIER, 0>(pc, c, M, R0, cur);
+      contig_store<K, TIER, 0>(a, pc, c, M, R0, cur, slot, active);
       q = q1;
       if (!more) break;
 #pragma unroll
@@ -613,25 +709,66 @@ __device__ __forceinline__ void contig_body(const SweepArgs& a, int32_t c, int32
   }
 }
 
-// Group g (4 cells) of the dimension-0 sweep, tuples [q, qe).
+// Group g (4 cells) of the dimension-0 sweep, tuples [q, qe).  In a scaled
+// FP16 sweep, lanes past the last group redo the last group without storing
+// it, so that whole waves reach the absmax reductions.
 template <int K, int TIER, int NDMAX>
 __device__ __forceinline__ void contig_group(const SweepArgs& a, int64_t g, int32_t q,
-                                             int32_t qe) {
-  if (g >= (a.cells >> 2)) return;
+                                             int32_t qe, int32_t slot) {
+  const int64_t groups = a.cells >> 2;
+  bool active = true;
+  if (g >= groups) {
+    if constexpr (TIER != 3) {
+      return;
+    } else {
+      if (!a.amax_part) return;
+      g = groups - 1;
+      active = false;
+    }
+  }
   const int32_t c = (int32_t)(g << 2);
   const int32_t line = (int32_t)a.fN.div((uint32_t)c);
   const int32_t i0 = c - line * a.N;
   const int32_t t = table_index(a.map, 0, line);
   const int32_t t0 = __builtin_amdgcn_readfirstlane(t);
-  if (__all(t == t0)) contig_body<K, TIER, NDMAX>(a, c, line, i0, t0, q, qe);
-  else contig_body<K, TIER, NDMAX>(a, c, line, i0, t, q, qe);
+  if (__all(t == t0)) contig_body<K, TIER, NDMAX>(a, c, line, i0, t0, q, qe, slot, active);
+  else contig_body<K, TIER, NDMAX>(a, c, line, i0, t, q, qe, slot, active);
+}
+
+// XCD-aware tile order.  Workgroups are dispatched round-robin over the 8
+// XCDs (flat workgroup id w goes to XCD w % 8), each with its own L2, so
+// tiles that share cache lines (neighbouring cells of a line, the halo rows
+// of neighbouring row chunks) are fetched from HBM once per XCD that touches
+// them.  With group size G > 0, the XCD's i-th workgroup (i = w / 8) takes
+// tile ((i / G) * 8 + xcd) * G + i % G: runs of G consecutive tiles execute
+// on one XCD one after the other, while the 8 XCDs still work on 8 adjacent
+// runs (which keeps the HBM access stream local).  The tiles of the last,
+// incomplete round keep the dispatch order.  G = -1 gives every XCD one
+// contiguous eighth of the tiles; G = 0 keeps the dispatch order.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t w, uint32_t n, int32_t G) {
+  if (G == 0) return w;
+  const uint32_t xcd = w & 7, i = w >> 3;
+  if (G < 0) {
+    const uint32_t per = n >> 3, rem = n & 7;
+    return xcd * per + min(xcd, rem) + i;
+  }
+  const uint32_t g = (uint32_t)G, round = 8 * g;
+  if (w >= n / round * round) return w;
+  return ((i / g) * 8 + xcd) * g + i % g;
 }
 
 template <int K, int TIER, int NDMAX>
 __global__ __launch_bounds__(256) void sweep_contig_window_kernel(SweepArgs a) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int32_t q = blockIdx.y * a.tuples;
-  contig_group<K, TIER, NDMAX>(a, g, q, min(a.nspec, q + a.tuples));
+  uint32_t bx = blockIdx.x, by = blockIdx.y;
+  if (a.xcd) {                 // tile order: x fastest, then y
+    const uint32_t t = xcd_tile(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y, a.xcd);
+    by = t / gridDim.x;
+    bx = t - by * gridDim.x;
+  }
+  const int64_t g = (int64_t)bx * blockDim.x + threadIdx.x;
+  const int32_t q = by * a.tuples;
+  contig_group<K, TIER, NDMAX>(a, g, q, min(a.nspec, q + a.tuples),
+                               (int32_t)(bx * (blockDim.x >> 6) + (threadIdx.x >> 6)));
 }
 
 // ---------------------------------------------------------------------------
@@ -663,38 +800,44 @@ __device__ __forceinline__ void strided_load(const Planes<K, TIER, ND>& pl, int6
 }
 
 template <int K, int TIER, int ND, int L>
-__device__ __forceinline__ void strided_store(const Planes<K, TIER, ND>& pl, int64_t base,
-                                              int32_t P, int32_t r0, int32_t n,
+__device__ __forceinline__ void strided_store(const SweepArgs& a, const Planes<K, TIER, ND>& pl,
+                                              int64_t base, int32_t r0, int32_t n,
                                               const Mat<K, TIER>& M, const Rows64<K, ND>& R64,
-                                              const Rows<K, TIER, ND, L>& R) {
+                                              const Rows<K, TIER, ND, L>& R, int32_t slot,
+                                              bool active) {
+  const int32_t P = a.P;
+  float am[K + 1];
+  zero_amax(am);
   if (n == L) {            // full chunk: no per-row predicate
 #pragma unroll
     for (int u = 0; u < L; ++u)
-      pl.store(base + (int64_t)(r0 + u) * P, M, R64, R.v[u + 1], R.v[u]);
+      pl.store(base + (int64_t)(r0 + u) * P, M, R64, R.v[u + 1], R.v[u], am, active);
   } else {                 // the last chunk of a line whose length L does not divide
 #pragma unroll
     for (int u = 0; u < L; ++u)
-      if (u < n) pl.store(base + (int64_t)(r0 + u) * P, M, R64, R.v[u + 1], R.v[u]);
+      if (u < n) pl.store(base + (int64_t)(r0 + u) * P, M, R64, R.v[u + 1], R.v[u], am, active);
   }
+  flush_amax<K, TIER, ND>(a, pl, am, slot);
 }
 
 template <int K, int TIER, int ND, int L>
 __device__ __forceinline__ void strided_single(const SweepArgs& a, const TupleMap& tm,
                                                const Mat<K, TIER>& M, int64_t base,
                                                const int32_t (&roff)[L + 1], int32_t r0,
-                                               int32_t n) {
+                                               int32_t n, int32_t slot, bool active) {
   Planes<K, TIER, ND> pl;
   pl.bind(a, tm);
   Rows64<K, ND> R64;
   R64.load(M.ab, M.cs);
   Rows<K, TIER, ND, L> R;
   strided_load<K, TIER, ND, L>(pl, base, roff, R);
-  strided_store<K, TIER, ND, L>(pl, base, a.P, r0, n, M, R64, R);
+  strided_store<K, TIER, ND, L>(a, pl, base, r0, n, M, R64, R, slot, active);
 }
 
 template <int K, int TIER, int L, int NDMAX>
 __device__ __forceinline__ void strided_body(const SweepArgs& a, int32_t ilow, int32_t chunk,
-                                             int32_t ihigh, int32_t t, int32_t q, int32_t qe) {
+                                             int32_t ihigh, int32_t t, int32_t q, int32_t qe,
+                                             int32_t slot, bool active) {
   constexpr int O = K + 1;
   const int32_t s = a.s_tab[t];
   const int32_t N = a.N, P = a.P, ms = a.mstride;
@@ -727,7 +870,8 @@ __device__ __forceinline__ void strided_body(const SweepArgs& a, int32_t ilow, i
     const TupleMap tm = tuple_map(a, m0, ms, O);
     if (tm.nd != 0) {
       dispatch_nd<NDMAX>(tm.nd, [&](auto ndc) {
-        strided_single<K, TIER, decltype(ndc)::value, L>(a, tm, M, base, roff, r0, n);
+        strided_single<K, TIER, decltype(ndc)::value, L>(a, tm, M, base, roff, r0, n, slot,
+                                                         active);
       });
       advance(q, low, m0);
       continue;
@@ -749,7 +893,7 @@ __device__ __forceinline__ void strided_body(const SweepArgs& a, int32_t ilow, i
           strided_load<K, TIER, 0, L>(pn, base, roff, nxt);
         }
       }
-      strided_store<K, TIER, 0, L>(pc, base, P, r0, n, M, R64, cur);
+      strided_store<K, TIER, 0, L>(a, pc, base, r0, n, M, R64, cur, slot, active);
       q = q1;
       low = low1;
       m0 = m1;
@@ -761,18 +905,34 @@ __device__ __forceinline__ void strided_body(const SweepArgs& a, int32_t ilow, i
   }
 }
 
-// Column col, row chunk `chunk` of a strided sweep, tuples [q, qe).
+// Column col, row chunk `chunk` of a strided sweep, tuples [q, qe).  The
+// chunk is uniform across a wave; in a scaled FP16 sweep, lanes past the
+// last column redo the last column without storing it, so that whole waves
+// reach the absmax reductions.
 template <int K, int TIER, int L, int NDMAX>
 __device__ __forceinline__ void strided_cell(const SweepArgs& a, int32_t col, int32_t chunk,
-                                             int32_t q, int32_t qe) {
-  if (col >= a.P * a.Q || chunk >= a.nchunk) return;
+                                             int32_t q, int32_t qe, int32_t slot) {
+  if (chunk >= a.nchunk) return;
+  const int32_t ncol = a.P * a.Q;
+  bool active = true;
+  if (col >= ncol) {
+    if constexpr (TIER != 3) {
+      return;
+    } else {
+      if (!a.amax_part) return;
+      col = ncol - 1;
+      active = false;
+    }
+  }
   const uint32_t ih = a.fP.div((uint32_t)col);
   const int32_t ilow = col - (int32_t)ih * a.P;
   const int32_t ihigh = (int32_t)ih;
   const int32_t t = table_index(a.map, ilow, ihigh);
   const int32_t t0 = __builtin_amdgcn_readfirstlane(t);
-  if (__all(t == t0)) strided_body<K, TIER, L, NDMAX>(a, ilow, chunk, ihigh, t0, q, qe);
-  else strided_body<K, TIER, L, NDMAX>(a, ilow, chunk, ihigh, t, q, qe);
+  if (__all(t == t0))
+    strided_body<K, TIER, L, NDMAX>(a, ilow, chunk, ihigh, t0, q, qe, slot, active);
+  else
+    strided_body<K, TIER, L, NDMAX>(a, ilow, chunk, ihigh, t, q, qe, slot, active);
 }
 
 // Work decomposition: a wave takes 64 consecutive columns (column =
@@ -780,13 +940,34 @@ __device__ __forceinline__ void strided_cell(const SweepArgs& a, int32_t col, in
 // columns contiguous in memory), the waves of a workgroup take consecutive
 // row chunks of the same columns.  The halo row a wave loads is the last row
 // its neighbour wave loads, so it is served by the CU's caches, and the
-// waves share the columns' s, A, B in L1.
+// waves share the columns' s, A, B in L1.  Tiles (x: column block, z: row
+// chunk group, y: tuple run) are ordered z fastest, then x, then y, and laid
+// over the XCDs so that tiles sharing lines (the halo row between row chunk
+// groups, the cache lines split between column blocks when the rows are
+// short) run on one XCD, one after the other.
 template <int K, int TIER, int L, int NDMAX>
 __global__ __launch_bounds__(256) void sweep_strided_kernel(SweepArgs a) {
-  const int32_t col = (int32_t)blockIdx.x * 64 + (int32_t)(threadIdx.x & 63);
-  const int32_t chunk = (int32_t)blockIdx.z * (int32_t)(blockDim.x >> 6) + (int32_t)(threadIdx.x >> 6);
-  const int32_t q = blockIdx.y * a.tuples;
-  strided_cell<K, TIER, L, NDMAX>(a, col, chunk, q, min(a.nspec, q + a.tuples));
+  uint32_t bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+  const uint32_t gx = gridDim.x, gz = gridDim.z;
+  if (a.xcd) {
+    const uint32_t t = xcd_tile(blockIdx.x + gx * (blockIdx.y + gridDim.y * blockIdx.z),
+                                gx * gridDim.y * gz, a.xcd);
+    const uint32_t xz = gx * gz;
+    by = t / xz;
+    const uint32_t r = t - by * xz;
+    bx = r / gz;
+    bz = r - bx * gz;
+  }
+  // the workgroup's waves: cw side by side along the columns, waves / cw
+  // stacked along the row chunks
+  const int32_t waves = (int32_t)(blockDim.x >> 6), wave = (int32_t)(threadIdx.x >> 6);
+  const int32_t cw = a.colwaves, zw = waves / cw;
+  const int32_t wc = wave % cw, wz = wave / cw;
+  const int32_t col = ((int32_t)bx * cw + wc) * 64 + (int32_t)(threadIdx.x & 63);
+  const int32_t chunk = (int32_t)bz * zw + wz;
+  const int32_t q = by * a.tuples;
+  strided_cell<K, TIER, L, NDMAX>(a, col, chunk, q, min(a.nspec, q + a.tuples),
+                                  (int32_t)(bz * gx + bx) * waves + wave);
 }
 
 bool contig_window_ok(const SweepArgs& a) {
@@ -795,27 +976,52 @@ bool contig_window_ok(const SweepArgs& a) {
   return a.N % 4 == 0 && (align & 15) == 0;
 }
 
-template <int K, int TIER, int NDMAX>
-static hipError_t launch_sweep_ktn(int dim, const SweepArgs& a, hipStream_t st) {
+// Launch shape of a sweep: form 0 window, 1 generic dimension-0, 2 strided.
+static bool sweep_grid(int dim, const SweepArgs& a, int& form, dim3& grid, dim3& block) {
   if (dim == 0) {
     if (contig_window_ok(a)) {
       const int64_t groups = a.cells >> 2;
-      dim3 grid((unsigned)((groups + 255) / 256), (unsigned)((a.nspec + a.tuples - 1) / a.tuples)),
-          block(256);
-      sweep_contig_window_kernel<K, TIER, NDMAX><<<grid, block, 0, st>>>(a);
+      form = 0;
+      grid = dim3((unsigned)((groups + 255) / 256), (unsigned)((a.nspec + a.tuples - 1) / a.tuples));
+      block = dim3(256);
     } else {
       const int64_t items = (int64_t)a.Q * a.nspec;
-      dim3 grid((unsigned)((items + 3) / 4)), block(256);
-      sweep_contig_kernel<K, TIER, NDMAX><<<grid, block, 0, st>>>(a);
+      form = 1;
+      grid = dim3((unsigned)((items + 3) / 4));
+      block = dim3(256);
     }
+    return true;
+  }
+  const int64_t ncol = (int64_t)a.P * a.Q;
+  const int cw = a.colwaves;                         // waves side by side (columns)
+  const int zw = std::min(a.nchunk, 4 / cw);         // waves stacked (row chunks)
+  const int64_t gx = (ncol + 64 * cw - 1) / (64 * cw), gz = (a.nchunk + zw - 1) / zw;
+  if (gz > 65535 || gx > 0x7fffffff) return false;
+  form = 2;
+  grid = dim3((unsigned)gx, (unsigned)((a.nspec + a.tuples - 1) / a.tuples), (unsigned)gz);
+  block = dim3(64 * cw * zw);
+  return true;
+}
+
+int64_t sweep_slots(int dim, const SweepArgs& a) {
+  int form;
+  dim3 grid, block;
+  if (!sweep_grid(dim, a, form, grid, block)) return -1;
+  if (form == 0) return (int64_t)grid.x * (block.x / 64);
+  if (form == 1) return a.Q;                           // one wave per (line, tuple)
+  return (int64_t)grid.x * grid.z * (block.x / 64);
+}
+
+template <int K, int TIER, int NDMAX>
+static hipError_t launch_sweep_ktn(int dim, const SweepArgs& a, hipStream_t st) {
+  int form;
+  dim3 grid, block;
+  if (!sweep_grid(dim, a, form, grid, block)) return hipErrorInvalidConfiguration;
+  if (form == 0) {
+    sweep_contig_window_kernel<K, TIER, NDMAX><<<grid, block, 0, st>>>(a);
+  } else if (form == 1) {
+    sweep_contig_kernel<K, TIER, NDMAX><<<grid, block, 0, st>>>(a);
   } else {
-    const int64_t ncol = (int64_t)a.P * a.Q;
-    const int waves = a.nchunk < 4 ? a.nchunk : 4;     // row chunks per workgroup
-    if ((a.nchunk + waves - 1) / waves > 65535 || (ncol + 63) / 64 > 0x7fffffff)
-      return hipErrorInvalidConfiguration;
-    dim3 grid((unsigned)((ncol + 63) / 64), (unsigned)((a.nspec + a.tuples - 1) / a.tuples),
-              (unsigned)((a.nchunk + waves - 1) / waves)),
-        block(64 * waves);
     switch (a.chunk) {
       case 1: sweep_strided_kernel<K, TIER, 1, NDMAX><<<grid, block, 0, st>>>(a); break;
       case 2: sweep_strided_kernel<K, TIER, 2, NDMAX><<<grid, block, 0, st>>>(a); break;
@@ -877,9 +1083,9 @@ __global__ __launch_bounds__(256) void batch_sweep_kernel(const SweepArgs* __res
     const int32_t qe = min(a.nspec, q + a.tuples);
     if (w.kind == 0) {               // dimension 0, window form
       const int64_t g = (int64_t)w.x * blockDim.x + threadIdx.x;
-      if (k == 1) contig_group<1, TIER, 1>(a, g, q, qe);
-      else if (k == 2) contig_group<2, TIER, 1>(a, g, q, qe);
-      else contig_group<3, TIER, 1>(a, g, q, qe);
+      if (k == 1) contig_group<1, TIER, 1>(a, g, q, qe, 0);
+      else if (k == 2) contig_group<2, TIER, 1>(a, g, q, qe, 0);
+      else contig_group<3, TIER, 1>(a, g, q, qe, 0);
     } else if (w.kind == 1) {        // dimension 0, generic form
       if (k == 1) contig_generic_item<1, TIER, 1>(a, w.x);
       else if (k == 2) contig_generic_item<2, TIER, 1>(a, w.x);
@@ -887,9 +1093,9 @@ __global__ __launch_bounds__(256) void batch_sweep_kernel(const SweepArgs* __res
     } else {                         // strided
       const int32_t col = w.x * 64 + (int32_t)(threadIdx.x & 63);
       const int32_t chunk = w.z * (int32_t)(blockDim.x >> 6) + (int32_t)(threadIdx.x >> 6);
-      if (k == 1) strided_cell<1, TIER, L, 1>(a, col, chunk, q, qe);
-      else if (k == 2) strided_cell<2, TIER, L, 1>(a, col, chunk, q, qe);
-      else strided_cell<3, TIER, L, 1>(a, col, chunk, q, qe);
+      if (k == 1) strided_cell<1, TIER, L, 1>(a, col, chunk, q, qe, 0);
+      else if (k == 2) strided_cell<2, TIER, L, 1>(a, col, chunk, q, qe, 0);
+      else strided_cell<3, TIER, L, 1>(a, col, chunk, q, qe, 0);
     }
   }
 }
@@ -919,6 +1125,267 @@ hipError_t launch_batch_sweep(int tier, int rows, const SweepArgs* args, const i
     case 3: return launch_batch_t<3>(rows, args, kdeg, items, nitems, grid, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Scaled FP16 storage: exponent prediction, absmax decision, overflow redo,
+// import from and export to FP64.
+// ---------------------------------------------------------------------------
+
+constexpr int kFp16Top = 15;             // 2^15 <= 65504 < 2^16
+constexpr int kScaleEmin = -100, kScaleEmax = 100;
+constexpr int kRepairHeadroom = 1;
+
+// Exponent e with 2^(14 - h) <= amax 2^e < 2^(15 - h), clamped; `keep` when
+// amax is 0 or not finite.
+__device__ __forceinline__ int32_t storage_exponent(float amax, int headroom, int32_t keep) {
+  if (!(amax > 0.0f) || !isfinite(amax)) return keep;
+  int x;
+  (void)frexpf(amax, &x);                // amax = f 2^x, 0.5 <= f < 1
+  return min(max(kFp16Top - headroom - x, kScaleEmin), kScaleEmax);
+}
+
+__global__ __launch_bounds__(256) void scale_predict_kernel(int64_t n_hi,
+                                                            const int32_t* __restrict__ in_exp,
+                                                            const float* __restrict__ in_amax,
+                                                            int32_t* __restrict__ out_exp,
+                                                            int headroom,
+                                                            float* __restrict__ part,
+                                                            int64_t npart) {
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = i0; p < n_hi; p += stride)
+    out_exp[p] = storage_exponent(in_amax[p], headroom, in_exp[p]);
+  for (int64_t i = i0; i < npart; i += stride) part[i] = 0.0f;
+}
+
+hipError_t launch_scale_predict(int64_t n_hi, const int32_t* in_exp, const float* in_amax,
+                                int32_t* out_exp, int headroom, float* part, int64_t npart,
+                                hipStream_t st) {
+  const int64_t need = std::max(n_hi, npart);
+  const unsigned blocks = (unsigned)std::min<int64_t>(2048, std::max<int64_t>(1, (need + 255) / 256));
+  scale_predict_kernel<<<blocks, 256, 0, st>>>(n_hi, in_exp, in_amax, out_exp, headroom, part,
+                                               npart);
+  return hipGetLastError();
+}
+
+__device__ __forceinline__ float block_max(float v, float* sh) {
+  v = wave_max(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float r = 0.0f;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = fmaxf(r, sh[w]);
+  return r;
+}
+
+// One workgroup per plane.
+__global__ __launch_bounds__(256) void scale_decide_kernel(const float* __restrict__ part,
+                                                           int32_t nslot,
+                                                           int32_t* __restrict__ out_exp,
+                                                           float* __restrict__ out_amax,
+                                                           int32_t* __restrict__ redo) {
+  __shared__ float sh[4];
+  const int64_t p = blockIdx.x;
+  float m = 0.0f;
+  for (int32_t i = threadIdx.x; i < nslot; i += blockDim.x) m = fmaxf(m, part[p * nslot + i]);
+  m = block_max(m, sh);
+  if (threadIdx.x == 0) {
+    const int32_t e = out_exp[p];
+    int32_t fix = 0;
+    if (isfinite(m) && ldexp((double)m, e) >= (double)(1 << kFp16Top)) {
+      out_exp[p] = storage_exponent(m, kRepairHeadroom, e);
+      fix = 1;
+    }
+    out_amax[p] = m;
+    redo[p] = fix;
+  }
+}
+
+hipError_t launch_scale_decide(int64_t n_hi, const float* part, int32_t nslot, int32_t* out_exp,
+                               float* out_amax, int32_t* redo, hipStream_t st) {
+  if (n_hi <= 0) return hipSuccess;
+  scale_decide_kernel<<<(unsigned)n_hi, 256, 0, st>>>(part, nslot, out_exp, out_amax, redo);
+  return hipGetLastError();
+}
+
+// Recompute the flagged planes (outputs that overflowed their predicted
+// exponent) with their final exponents: every workgroup lists the flagged
+// planes in LDS, exits when there is none, and walks the cells of each with a
+// grid stride.  The update is the same sequence of operations as in the sweep
+// kernels (FP32 accumulation of the widened, unscaled inputs).
+template <int K>
+__global__ __launch_bounds__(256) void scale_redo_kernel(SweepArgs a, int32_t n_hi,
+                                                         const int32_t* __restrict__ redo,
+                                                         const int32_t* __restrict__ hi_mode) {
+  constexpr int O = K + 1;
+  constexpr int kList = 4096;          // >= the most narrow planes of a plan (4^6 - 1)
+  __shared__ int32_t list[kList];
+  __shared__ int32_t count;
+  if (threadIdx.x == 0) count = 0;
+  __syncthreads();
+  for (int32_t p = threadIdx.x; p < n_hi; p += blockDim.x)
+    if (redo[p]) {
+      const int32_t i = atomicAdd(&count, 1);
+      if (i < kList) list[i] = p;
+    }
+  __syncthreads();
+  const int32_t nfix = min(count, kList);
+  if (nfix == 0) return;
+  const _Float16* hin = reinterpret_cast<const _Float16*>(a.in_hi);
+  _Float16* hout = reinterpret_cast<_Float16*>(a.out_hi);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int32_t ms = a.mstride;
+  for (int32_t f = 0; f < nfix; ++f) {
+    const int32_t p = list[f];
+    const int32_t m = hi_mode[p];
+    const int32_t j = (m / ms) % O;
+    const int32_t m0 = m - j * ms;
+    int32_t src[O];
+    float fin[O];
+#pragma unroll
+    for (int l = 0; l < O; ++l) {
+      src[l] = a.pmap[m0 + l * ms];
+      fin[l] = src[l] >= 0 ? pow2f(-a.in_exp[src[l]]) : 1.0f;
+    }
+    const float fout = pow2f(a.out_exp[p]);
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.cells; c += stride) {
+      const int32_t ilow = (int32_t)(c % a.P);
+      const int64_t rest = c / a.P;
+      const int32_t id = (int32_t)(rest % a.N);
+      const int32_t ihigh = (int32_t)(rest / a.N);
+      const int32_t t = table_index(a.map, ilow, ihigh);
+      const int32_t s = a.s_tab[t];
+      int32_t ia = id - s;
+      if (ia < 0) ia += a.N;
+      int32_t ib = ia - 1;
+      if (ib < 0) ib += a.N;
+      const int64_t base = (int64_t)ihigh * a.P * a.N + ilow;
+      const int64_t ca = base + (int64_t)ia * a.P, cb = base + (int64_t)ib * a.P;
+      float x[O], y[O];
+#pragma unroll
+      for (int l = 0; l < O; ++l) {
+        if (src[l] >= 0) {
+          x[l] = (float)hin[(int64_t)src[l] * a.cells + ca] * fin[l];
+          y[l] = (float)hin[(int64_t)src[l] * a.cells + cb] * fin[l];
+        } else {
+          x[l] = (float)a.in_lo[(int64_t)(-1 - src[l]) * a.cells + ca];
+          y[l] = (float)a.in_lo[(int64_t)(-1 - src[l]) * a.cells + cb];
+        }
+      }
+      float acc = 0.0f;
+#pragma unroll
+      for (int l = 0; l < O; ++l) acc = fma((float)a.ab_tab[(j * O + l) * a.ab_cs + t], x[l], acc);
+#pragma unroll
+      for (int l = 0; l < O; ++l)
+        acc = fma((float)a.ab_tab[(O * O + j * O + l) * a.ab_cs + t], y[l], acc);
+      hout[(int64_t)p * a.cells + c] = (_Float16)(acc * fout);
+    }
+  }
+}
+
+hipError_t launch_scale_redo(int k, int dim, const SweepArgs& a, int64_t n_hi,
+                             const int32_t* redo, const int32_t* hi_mode, hipStream_t st) {
+  (void)dim;
+  if (n_hi <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, (a.cells + 255) / 256));
+  switch (k) {
+    case 1: scale_redo_kernel<1><<<blocks, 256, 0, st>>>(a, (int32_t)n_hi, redo, hi_mode); break;
+    case 2: scale_redo_kernel<2><<<blocks, 256, 0, st>>>(a, (int32_t)n_hi, redo, hi_mode); break;
+    case 3: scale_redo_kernel<3><<<blocks, 256, 0, st>>>(a, (int32_t)n_hi, redo, hi_mode); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// FP64 -> FP16 with one rounding to nearest even: the value is first taken to
+// FP32 by rounding to odd (truncate, then set the last bit when inexact),
+// which keeps enough information for the final RNE step to FP16 (24 > 11 + 1
+// significant bits) to be correctly rounded.
+__device__ __forceinline__ _Float16 f64_to_f16_rne(double v) {
+  float f = (float)v;                              // RNE
+  if (isfinite(f) && (double)f != v) {
+    uint32_t b = __float_as_uint(f);
+    if (fabs((double)f) > fabs(v)) b -= 1;         // rounded away from zero: step back
+    f = __uint_as_float(b | 1u);                   // inexact: odd last bit
+  } else if (!isfinite(f) && isfinite(v)) {
+    f = v > 0 ? 3.4028234663852886e38f : -3.4028234663852886e38f;   // beyond FP32: FP16 inf
+  }
+  return (_Float16)f;
+}
+
+// Absmax partials of an FP64 array [n_hi][cells]: grid (nslot, n_hi).
+__global__ __launch_bounds__(256) void import_absmax_kernel(const double* __restrict__ src,
+                                                            int64_t cells,
+                                                            float* __restrict__ part) {
+  __shared__ float sh[4];
+  const int64_t p = blockIdx.y;
+  double m = 0.0;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells;
+       c += (int64_t)gridDim.x * blockDim.x)
+    m = fmax(m, fabs(src[p * cells + c]));
+  // FP32 rounding is monotonic, so the max of rounded values is the rounded max
+  const float r = block_max((float)m, sh);
+  if (threadIdx.x == 0) part[p * gridDim.x + blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(256) void import_exp_kernel(const float* __restrict__ part,
+                                                         int32_t nslot, int headroom,
+                                                         int32_t* __restrict__ exp,
+                                                         float* __restrict__ amax) {
+  __shared__ float sh[4];
+  const int64_t p = blockIdx.x;
+  float m = 0.0f;
+  for (int32_t i = threadIdx.x; i < nslot; i += blockDim.x) m = fmaxf(m, part[p * nslot + i]);
+  m = block_max(m, sh);
+  if (threadIdx.x == 0) {
+    exp[p] = storage_exponent(m, headroom, 0);
+    amax[p] = m;
+  }
+}
+
+__global__ __launch_bounds__(256) void import_convert_kernel(const double* __restrict__ src,
+                                                             int64_t n, int64_t cells,
+                                                             const int32_t* __restrict__ exp,
+                                                             _Float16* __restrict__ dst) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = f64_to_f16_rne(ldexp(src[i], exp[i / cells]));
+}
+
+hipError_t launch_scale_import(const double* src, int64_t n_hi, int64_t cells, int headroom,
+                               float* part, int32_t nslot, void* dst, int32_t* exp, float* amax,
+                               hipStream_t st) {
+  if (n_hi <= 0) return hipSuccess;
+  if (n_hi > 65535) return hipErrorInvalidConfiguration;
+  import_absmax_kernel<<<dim3((unsigned)nslot, (unsigned)n_hi), 256, 0, st>>>(src, cells, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  import_exp_kernel<<<(unsigned)n_hi, 256, 0, st>>>(part, nslot, headroom, exp, amax);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t n = n_hi * cells;
+  const unsigned blocks = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(1, (n + 255) / 256));
+  import_convert_kernel<<<blocks, 256, 0, st>>>(src, n, cells, exp,
+                                                static_cast<_Float16*>(dst));
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void export_kernel(const _Float16* __restrict__ src, int64_t n,
+                                                     int64_t cells,
+                                                     const int32_t* __restrict__ exp,
+                                                     double* __restrict__ dst) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = ldexp((double)(float)src[i], -exp[i / cells]);
+}
+
+hipError_t launch_scale_export(const void* src, int64_t n_hi, int64_t cells, const int32_t* exp,
+                               double* dst, hipStream_t st) {
+  const int64_t n = n_hi * cells;
+  if (n <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(1, (n + 255) / 256));
+  export_kernel<<<blocks, 256, 0, st>>>(static_cast<const _Float16*>(src), n, cells, exp, dst);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

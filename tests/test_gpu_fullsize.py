@@ -1,0 +1,130 @@
+"""Full-size parity on the benchmark's grid: the 4D workload at 48^4 cells,
+k = 2, 81 coefficients per cell.
+
+* Every sweep direction, in the FP64, FP32-mode and BF16-mode tiers, under
+  every launch shape the autotuner can choose (the shapes the benchmark may
+  time).  Each sweep is compared with the oracle on sampled output cells, with
+  the single-sweep element bound, and each shape must reproduce the first one
+  bitwise (a shape splits the work differently, never the arithmetic).
+* One whole split step (6 sweeps) in FP32-mode and BF16-mode against the
+  oracle's FP64 step, in the weighted L2 norm, with the mass drift.
+
+Inputs: the benchmark's seeded random coefficients (Vlasov magnitude profile)
+and the workload's seeded fields.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import sldg_oracle as O
+from paper_1603_07008_amd import inputs
+from gpu_helpers import assert_sweep_close, have_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sl():
+    if not have_gpu():
+        pytest.skip("no HIP device")
+    import paper_1603_07008_amd as sl
+    sl.lib()
+    return sl
+
+
+@pytest.fixture(scope="module")
+def big():
+    prob = inputs.vlasov_4d(n=48)
+    st = inputs.random_coefficients(prob.ndim, prob.k, prob.cells, seed=1603)
+    return prob, st
+
+
+def _sample(prob, n, seed):
+    """Random output cells plus the cells at both ends of every dimension."""
+    rng = np.random.default_rng(seed)
+    cells = set(rng.choice(prob.cells, n, replace=False).tolist())
+    ns = prob.ns
+    for corner in range(1 << prob.ndim):
+        idx, stride = 0, 1
+        for e in range(prob.ndim):
+            idx += (ns[e] - 1 if corner >> e & 1 else 0) * stride
+            stride *= ns[e]
+        cells.add(idx)
+    return np.array(sorted(cells), dtype=np.int64)
+
+
+def _upload(sl, torch, state, tier):
+    mass = torch.from_numpy(np.ascontiguousarray(state[0])).cuda()
+    h64 = torch.from_numpy(state[1:]).cuda()
+    hi = h64.to(sl.hi_dtype(tier)).contiguous()
+    assert torch.equal(hi.to(torch.float64), h64), "state not representable in the tier"
+    del h64
+    return mass, hi
+
+
+def _gather(torch, mass, hi, sel_d):
+    m = mass.index_select(0, sel_d).to(torch.float64)
+    h = hi.index_select(1, sel_d).to(torch.float64)
+    return torch.cat([m[None], h], 0).cpu().numpy()
+
+
+@pytest.mark.parametrize("tier", ["fp32", "fp64", "bf16"])
+def test_full_size_sweeps_every_direction_and_launch_shape(sl, big, tier):
+    import torch
+    prob, st0 = big
+    state = O.to_tier(st0, tier)
+    plan = sl.Plan(prob.ns, prob.k, tier)
+    m_in, h_in = _upload(sl, torch, state, tier)
+    m_out, h_out = plan.empty_state()
+    sel = _sample(prob, 3000, 7)
+    sel_d = torch.from_numpy(sel).cuda()
+    seen = set()
+    for sw in prob.seq:
+        if sw.dim in seen:
+            continue
+        seen.add(sw.dim)
+        want = O.sweep(state, prob.ns, prob.k, sw.dim, sw.sigma, sw.dep, tier, sel=sel)
+        mag = O.sweep(state, prob.ns, prob.k, sw.dim, sw.sigma, sw.dep, sel=sel, absolute=True)
+        shift = torch.from_numpy(sw.sigma).cuda()
+        first = None
+        for shape in sl.tune_candidates(sw.dim > 0):
+            plan.set_shape(sw.dim, shape["rows"], shape["tuples"], shape["colwaves"])
+            plan.advect_dim(sw.dim, shift, sw.dep_mask, m_in, h_in, m_out, h_out)
+            got = _gather(torch, m_out, h_out, sel_d)
+            if first is None:
+                assert_sweep_close(got, want, mag, tier, prob.k, f"{tier} dim {sw.dim} {shape}")
+                first = got
+            else:
+                assert np.array_equal(got, first), f"{tier} dim {sw.dim}: shape {shape} differs"
+    plan.close()
+
+
+@pytest.mark.parametrize("tier,tol", [("fp32", 1e-6), ("bf16", 5e-3)])
+def test_full_size_split_step_against_fp64_oracle(sl, big, tier, tol):
+    import torch
+    prob, st0 = big
+    seq_o = [(s.dim, s.sigma, s.dep) for s in prob.seq]
+    ref = O.run_sequence(st0, prob.ns, prob.k, seq_o, "fp64", 1)
+    state = O.to_tier(st0, tier)
+    plan = sl.Plan(prob.ns, prob.k, tier)
+    s0 = _upload(sl, torch, state, tier)
+    s1 = plan.empty_state()
+    seq = [(s.dim, s.dep_mask, torch.from_numpy(s.sigma).cuda()) for s in prob.seq]
+    plan.tune(seq, s0, s1, reps=1)
+    res = plan.split_steps(seq, 1, s0, s1)
+    mass, hi = (s0, s1)[res]
+    m = mass.cpu().numpy()
+    w = O.mode_weights(prob.ndim, prob.k)
+    num = w[0] * np.sum((m - ref[0]) ** 2)
+    den = w[0] * np.sum(ref[0] ** 2)
+    hcpu = hi.cpu()
+    for p in range(prob.modes - 1):
+        d = hcpu[p].to(torch.float64).numpy()
+        num += w[p + 1] * np.sum((d - ref[p + 1]) ** 2)
+        den += w[p + 1] * np.sum(ref[p + 1] ** 2)
+    rel = math.sqrt(num / den)
+    assert rel < tol, rel
+    m0, m1 = O.mass_sum(state[0]), O.mass_sum(m)
+    assert abs(m1 - m0) <= 1e-14 * abs(m0)
+    plan.close()
