@@ -87,6 +87,31 @@ def measured_copy_bandwidth(sl, torch, nbytes, reps=10):
     return 2 * n * 16 / (ms * 1e-3) / 1e9
 
 
+def measured_plane_copy(sl, torch, cells, nplanes, tiers=(1, 3, 9, 27), reps=10):
+    """Bandwidth of copying nplanes FP32 planes of `cells` values with 16 B
+    per thread, each thread walking T planes in turn: the access pattern of a
+    sweep thread's run of spectator tuples, without arithmetic."""
+    pb = cells * 4 // 16 * 16
+    src = torch.ones(nplanes * pb // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    out = {}
+    for T in tiers:
+        for _ in range(3):
+            sl.device_plane_copy(src, dst, pb, nplanes, T)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            sl.device_plane_copy(src, dst, pb, nplanes, T)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[str(T)] = round(2 * pb * nplanes / (ms * 1e-3) / 1e9, 1)
+    del src, dst
+    return out
+
+
 def run_tier(sl, torch, prob, tier, init, steps, warmup, tune_cache=None):
     """Time `steps` split steps (after `warmup`) of `prob` in `tier`."""
     p = sl.Plan(prob.ns, prob.k, tier)
@@ -181,6 +206,135 @@ def cpu_baseline(prob, tier, seconds, seed):
                       f"{dt:.1f} s)"}
 
 
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def batched_extra(sl, torch, steps, seed):
+    """The batched workload: 512 independent (x, v) problems of seeded extents
+    32..512 and degrees 1..3 in FP32-mode, one persistent launch per sweep,
+    launch shapes from the batch tuner; eager launches and HIP-graph replays
+    of the split step."""
+    from paper_1603_07008_amd import inputs
+    from paper_1603_07008_amd.batch import Batch
+    probs = inputs.batched_landau(nprob=512, seed=4)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b = Batch([p.ns for p in probs], [p.k for p in probs], "fp32", stream=stream.cuda_stream)
+        s0, s1 = [], []
+        for i, p in enumerate(probs):
+            m, h = inputs.random_coefficients_device(2, p.k, p.cells, seed=seed + i)
+            s0.append((m, h.to(torch.float32)))
+            s1.append((torch.empty_like(m), torch.empty_like(s0[-1][1])))
+        b.bind(s0, s1)
+        shifts = [[(sw.dep_mask, torch.from_numpy(sw.sigma).cuda()) for sw in p.seq] for p in probs]
+        b.set_sequence([(probs[0].seq[q].dim, [shifts[i][q] for i in range(len(probs))])
+                        for q in range(3)])
+        init = [(m.clone(), h.clone()) for m, h in s0]
+        tuned = b.tune(reps=2)
+        for i in range(len(probs)):                 # the tuner overwrote buffer 1 only
+            s0[i][0].copy_(init[i][0])
+            s0[i][1].copy_(init[i][1])
+        stream.synchronize()
+        out = {}
+        for mode, graph in (("eager", False), ("graph", True)):
+            b.run(2, use_graph=graph)               # warm-up (and graph capture)
+            stream.synchronize()
+            e0, e1 = _events(torch)
+            e0.record(stream)
+            b.run(steps, use_graph=graph)
+            e1.record(stream)
+            stream.synchronize()
+            out[mode] = e0.elapsed_time(e1) / steps
+    updates = sum(p.cells * p.modes for p in probs) * 3
+    sbytes = sum(state_bytes(p.cells, p.modes, "fp32") for p in probs)
+    best = min(out.values())
+    res = {"workload": "512 Landau-like (x, v) problems, N_x, N_v ~ U{32..512}, k ~ U{1,2,3}, "
+                       "fp32-mode, Strang step = 3 sweeps",
+           "cells": sum(p.cells for p in probs), "coefficients": sum(p.cells * p.modes for p in probs),
+           "ms_per_step_eager": round(out["eager"], 4), "ms_per_step_graph": round(out["graph"], 4),
+           "coeff_updates_per_s": updates / (best * 1e-3),
+           "algorithmic_GBps": round(3 * 2 * sbytes / (best * 1e-3) / 1e9, 1),
+           "frac_hbm_peak": round(3 * 2 * sbytes / (best * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "tuned_shapes": tuned}
+    b.close()
+    return res
+
+
+def adjoint_extra(sl, torch, seed):
+    """The differentiation workload: 512^2 cells, k = 2, FP64, 50 Strang steps
+    forward and the adjoint sweeps backward (checkpoints every 10 steps)."""
+    from paper_1603_07008_amd import inputs
+    from paper_1603_07008_amd import autograd as AG
+    prob = inputs.vlasov_2d_differentiation()
+    p = sl.Plan(prob.ns, prob.k, "fp64")
+    seq = [(sw.dim, sw.dep_mask, torch.from_numpy(sw.sigma).cuda()) for sw in prob.seq]
+    m, h = inputs.random_coefficients_device(2, prob.k, prob.cells, seed=seed)
+    tm, th = inputs.random_coefficients_device(2, prob.k, prob.cells, seed=seed + 1)
+    vol = 1.0
+
+    def once():
+        mm = m.clone().requires_grad_(True)
+        hh = h.clone().requires_grad_(True)
+        fm, fh = AG.split_steps(p, seq, prob.steps, mm, hh, checkpoint_every=10)
+        loss = AG.weighted_l2_misfit(fm, fh, tm, th, 2, prob.k, vol)
+        loss.backward()
+        return mm.grad, hh.grad
+
+    once()
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    e0.record()
+    reps = 3
+    for _ in range(reps):
+        once()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nsw = prob.steps * len(prob.seq)
+    return {"workload": "vlasov-2d 512^2, k=2, fp64, 50 Strang steps forward + adjoint backward, "
+                        "checkpoints every 10 steps",
+            "ms_forward_backward": round(ms, 3),
+            "coeff_updates_per_s": 2 * nsw * prob.cells * prob.modes / (ms * 1e-3)}
+
+
+def scaled_fp16_extra(sl, torch, prob, init, steps, warmup, ref_final):
+    """The headline 4D step with FP16 storage and per-plane scaling."""
+    p = sl.Plan(prob.ns, prob.k, "fp16")
+    mass0, hi0 = init
+    m0 = mass0.clone()
+    h0 = torch.empty((p.n_hi, p.cells), dtype=torch.float16, device="cuda")
+    sc0 = p.empty_scale()
+    p.scaled_import(hi0, h0, sc0)
+    st = [(m0, h0, sc0), (*p.empty_state(), p.empty_scale())]
+    seq = [(sw.dim, sw.dep_mask, torch.from_numpy(sw.sigma).cuda()) for sw in prob.seq]
+    cur = 0
+    m_start = p.mass(m0)
+    for _ in range(warmup):
+        cur = cur if p.split_steps_scaled(seq, 1, st[cur], st[1 - cur]) == 0 else 1 - cur
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    e0.record()
+    for _ in range(steps):
+        cur = cur if p.split_steps_scaled(seq, 1, st[cur], st[1 - cur]) == 0 else 1 - cur
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    m_end = p.mass(st[cur][0])
+    out = {"ms_per_step": round(ms, 4),
+           "mass_drift_rel": abs((m_end[0] + m_end[1]) - (m_start[0] + m_start[1]))
+           / abs(m_start[0] + m_start[1])}
+    if ref_final is not None:
+        fm = st[cur][0]
+        fh = p.scaled_export(st[cur][1], st[cur][2])
+        rm, rh = ref_final
+        num = torch.sum((fm - rm) ** 2) + torch.sum((fh - rh) ** 2)
+        den = torch.sum(rm ** 2) + torch.sum(rh ** 2)
+        out["rel_l2_vs_fp64_gpu_run"] = float(torch.sqrt(num / den))
+    p.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,6 +347,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=1603)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched, adjoint and scaled-FP16 measurements")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON cache of tuned launch shapes (read if it has the plan, else written)")
     args = ap.parse_args()
@@ -219,6 +375,8 @@ def main():
 
     copy_gbs = measured_copy_bandwidth(sl, torch, state_bytes(cells, modes, args.tier))
     log(f"bench: device copy bandwidth {copy_gbs:.0f} GB/s")
+    plane_gbs = measured_plane_copy(sl, torch, cells, modes)
+    log(f"bench: plane copy bandwidth by planes per thread {plane_gbs}")
     tiers = [args.tier] + [t for t in args.compare.split(",") if t and t != args.tier]
     results = {}
     for t in tiers:
@@ -243,7 +401,8 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "kernel": kname, "launches": nl,
                 "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": launch_bytes,
-                "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
+                "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
+                "plane_copy_GBps": plane_gbs}
 
     names = {0: "X1", 1: "X2", 2: "V1", 3: "V2"}
     per_sweep = {}
@@ -293,6 +452,23 @@ def main():
         "per_sweep": per_sweep,
         "tiers": tiers_out,
     }
+    if not args.no_extras:
+        extras = {}
+        log("bench: scaled fp16 tier")
+        ref = results.get("fp64")
+        extras["fp16_scaled"] = scaled_fp16_extra(sl, torch, prob, (mass0, hi0), args.steps,
+                                                  args.warmup, ref["final"] if ref else None)
+        if ref:
+            extras["fp16_scaled"]["speedup_vs_fp64"] = round(
+                ref["ms_per_step"] / extras["fp16_scaled"]["ms_per_step"], 3)
+        for r in results.values():
+            r["plan"].close()
+        results.clear()
+        log("bench: batched workload")
+        extras["batched"] = batched_extra(sl, torch, 20, args.seed)
+        log("bench: differentiation workload")
+        extras["adjoint"] = adjoint_extra(sl, torch, args.seed)
+        out["extras"] = extras
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(prob, args.tier, args.cpu_seconds, args.seed)

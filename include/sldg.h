@@ -305,14 +305,28 @@ sldg_status sldg_timing_read(sldg_plan_t plan, int dim, int64_t* launches, doubl
  */
 sldg_status sldg_device_copy(const void* src, void* dst, int64_t bytes, void* stream);
 
+/*
+ * Plane copy: nplanes planes of plane_bytes each (multiple of 16, 16-byte
+ * aligned) copied with 16 bytes per thread, each thread copying the same
+ * offset of planes_per_thread consecutive planes one after the other, as a
+ * sweep thread walks the planes of its run of spectator tuples.  The
+ * reference bandwidth of that access pattern, for the roofline.  Errors:
+ * SLDG_ERR_ARG, SLDG_ERR_ALIAS, SLDG_ERR_DEVICE.
+ */
+sldg_status sldg_device_plane_copy(const void* src, void* dst, int64_t plane_bytes, int nplanes,
+                                   int planes_per_thread, void* stream);
+
 /* Bytes of one state's `hi` array for this plan, n_hi * cells * sizeof(T). */
 int64_t sldg_hi_bytes(sldg_plan_t plan);
 
 /*
  * Batches: many independent problems advanced together (each with its own
  * grid, degree and displacement fields; one storage tier and dimension count
- * for the whole batch).  Each sweep of a split step is one persistent launch
- * over a work list of tiles of all problems.
+ * for the whole batch).  Each sweep of a split step runs from one work list
+ * of tiles of all problems, sorted by class (tile kind x degree); each class
+ * is one launch of a kernel compiled for that class, and a split step can be
+ * captured into one HIP graph.  The batch allocates its device tables and
+ * work lists; the states are the caller's.
  */
 typedef struct sldg_batch_s* sldg_batch_t;
 
@@ -346,8 +360,8 @@ sldg_status sldg_batch_run(sldg_batch_t batch, int nsteps, int use_graph, int* r
  * {2, 4, 8} (strided sweeps) x tuples-per-thread {1, 3, 9, all} on the bound
  * data (reads buffer 0, overwrites buffer 1) and keeps the fastest. */
 sldg_status sldg_batch_tune(sldg_batch_t batch, int reps);
-/* Read / set the launch shape of sweep q (tuples 0 = all); ms is the tuned
- * time per launch (-1 if not tuned). */
+/* Read / set the launch shape of sweep q (rows 2, 4 or 8; tuples 0 = all);
+ * ms is the tuned time per sweep (-1 if not tuned). */
 sldg_status sldg_batch_get_tuning(sldg_batch_t batch, int q, int* rows, int* tuples, double* ms);
 sldg_status sldg_batch_set_tuning(sldg_batch_t batch, int q, int rows, int tuples);
 

@@ -25,7 +25,8 @@ EXPORTS = ("sldg_plan", "sldg_plan_destroy", "sldg_plan_set_stream", "sldg_line_
            "sldg_plan_ex", "sldg_lo_planes", "sldg_hi_planes", "sldg_plane_map",
            "sldg_scale_bytes", "sldg_set_scale_headroom", "sldg_scaled_import",
            "sldg_scaled_export", "sldg_advect_dim_scaled", "sldg_split_steps_scaled",
-           "sldg_plan_set_shape", "sldg_plan_get_shape", "sldg_tune_candidate", "sldg_plan_tune")
+           "sldg_plan_set_shape", "sldg_plan_get_shape", "sldg_tune_candidate", "sldg_plan_tune",
+           "sldg_device_plane_copy")
 
 
 class SldgError(RuntimeError):
@@ -79,6 +80,8 @@ def lib():
     L.sldg_hi_bytes.restype = i64
     L.sldg_device_copy.argtypes = [vp, vp, i64, vp]
     L.sldg_device_copy.restype = i32
+    L.sldg_device_plane_copy.argtypes = [vp, vp, i64, i32, i32, vp]
+    L.sldg_device_plane_copy.restype = i32
     L.sldg_mass_device.argtypes = [vp, vp, vp]
     L.sldg_mass_device.restype = i32
     L.sldg_timing_enable.argtypes = [vp, i32]
@@ -488,6 +491,18 @@ def tune_candidates(strided):
             return out
         out.append({"rows": r.value, "tuples": t.value, "colwaves": c.value})
         i += 1
+
+
+def device_plane_copy(src, dst, plane_bytes, nplanes, planes_per_thread, stream=None):
+    """Plane copy of nplanes planes (sldg_device_plane_copy): the reference
+    bandwidth of the sweeps' access pattern."""
+    if src.numel() * src.element_size() < plane_bytes * nplanes or \
+            dst.numel() * dst.element_size() < plane_bytes * nplanes:
+        raise ValueError("device_plane_copy: buffers smaller than plane_bytes * nplanes")
+    st = _current_stream() if stream is None else stream
+    _check(lib().sldg_device_plane_copy(_ptr(src), _ptr(dst), int(plane_bytes), int(nplanes),
+                                        int(planes_per_thread), ctypes.c_void_p(st)),
+           "sldg_device_plane_copy")
 
 
 def device_copy(src, dst, nbytes=None, stream=None):

@@ -1,9 +1,11 @@
 // Batched sweeps (C ABI in include/sldg.h): many independent sLdG problems,
 // each with its own grid, degree and displacement fields, advanced together.
 // Every sweep of a split step (section II: Cheng-Knorr splitting into 1D
-// advections) is one persistent launch over a work list of tiles of all
-// problems; the split step can be captured once into a HIP graph and replayed;
-// a tuner times launch shapes on the bound data and keeps the fastest.
+// advections) runs from one work list of tiles of all problems, sorted by
+// class (tile kind and degree): one launch per class, of a kernel compiled
+// for that class alone.  The split step can be captured once into a HIP graph
+// and replayed; a tuner times launch shapes on the bound data and keeps the
+// fastest.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,7 +23,6 @@ struct sldg_batch_s {
   sldg_tier tier = SLDG_TIER_FP64;
   hipStream_t stream = nullptr;
   int device = 0;
-  int grid = 0;                           // persistent grid (workgroups)
   std::vector<int64_t> n;                 // [nprob * ndim]
   std::vector<int> k;
   std::vector<int64_t> cells, modes, hi_bytes;
@@ -35,7 +36,6 @@ struct sldg_batch_s {
   std::vector<int64_t> tab_off, ab_off, tab_n;   // [nseq * nprob]: s / matrix offsets, entries
   int32_t* d_s = nullptr;
   double* d_ab = nullptr;
-  int32_t* d_k = nullptr;
   int32_t* d_pmap = nullptr;              // mode -> plane maps (FP64 cell mean only), per problem
   std::vector<int64_t> pmap_off;
   // launch shape per sweep of the sequence
@@ -45,11 +45,19 @@ struct sldg_batch_s {
   std::vector<SweepArgs*> d_args;
   std::vector<BatchItem*> d_items;
   std::vector<int32_t> nitems;
+  std::vector<int32_t> cls_off;           // [nseq * (kClasses + 1)] class offsets in the list
   bool ready = false;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
 };
 
 namespace {
+
+// Work-list classes: kind (0 window, 1 group, 2 strided) x degree (1..3).
+constexpr int kClasses = 9;
+int class_of(int kind, int k) { return kind * 3 + (k - 1); }
+
+// XCD run lengths of the class launches (as the single-problem sweeps).
+constexpr int32_t kXcdContig = 8, kXcdStrided = 16;
 
 void drop_graphs(sldg_batch_s* b) {
   for (int i = 0; i < 2; ++i)
@@ -65,6 +73,7 @@ void free_work(sldg_batch_s* b) {
   b->d_args.clear();
   b->d_items.clear();
   b->nitems.clear();
+  b->cls_off.clear();
   b->ready = false;
 }
 
@@ -74,7 +83,6 @@ void free_batch(sldg_batch_s* b) {
   free_work(b);
   if (b->d_s) (void)hipFree(b->d_s);
   if (b->d_ab) (void)hipFree(b->d_ab);
-  if (b->d_k) (void)hipFree(b->d_k);
   if (b->d_pmap) (void)hipFree(b->d_pmap);
   delete b;
 }
@@ -87,7 +95,7 @@ bool aligned16(const void* x) { return ((uintptr_t)x & 15) == 0; }
 sldg_status build_sweep(sldg_batch_s* b, int q) {
   const int dim = b->dims[q];
   std::vector<SweepArgs> args[2];
-  std::vector<BatchItem> items;
+  std::vector<BatchItem> bucket[kClasses];
   for (int s = 0; s < 2; ++s) args[s].resize(b->nprob);
   for (int p = 0; p < b->nprob; ++p) {
     const int o = b->k[p] + 1;
@@ -113,23 +121,33 @@ sldg_status build_sweep(sldg_batch_s* b, int q) {
       bool window = a.N % 4 == 0;
       for (int s = 0; s < 2; ++s)
         window = window && aligned16(b->mass[s][p]) && aligned16(b->hi[s][p]);
-      if (window) {
-        const int64_t tiles = (a.cells / 4 + 255) / 256;
-        for (int32_t qg = 0; qg < nq; ++qg)
-          for (int64_t x = 0; x < tiles; ++x) items.push_back({p, 0, (int32_t)x, qg, 0});
-      } else {
-        const int64_t tiles = ((int64_t)a.Q * a.nspec + 3) / 4;
-        for (int64_t x = 0; x < tiles; ++x) items.push_back({p, 1, (int32_t)x, 0, 0});
-      }
+      const int kind = window ? 0 : 1;
+      const int64_t groups = window ? a.cells / 4 : (int64_t)a.Q * ((a.N + 3) / 4);
+      const int64_t tiles = (groups + 255) / 256;
+      auto& bk = bucket[class_of(kind, b->k[p])];
+      for (int32_t qg = 0; qg < nq; ++qg)
+        for (int64_t x = 0; x < tiles; ++x) bk.push_back({p, kind, (int32_t)x, qg, 0});
     } else {
       const int64_t xt = ((int64_t)a.P * a.Q + 63) / 64;
       const int64_t zt = ((int64_t)a.nchunk + 3) / 4;
+      auto& bk = bucket[class_of(2, b->k[p])];
+      // row chunk groups fastest: the halo rows shared between them meet on one XCD
       for (int32_t qg = 0; qg < nq; ++qg)
-        for (int64_t z = 0; z < zt; ++z)
-          for (int64_t x = 0; x < xt; ++x) items.push_back({p, 2, (int32_t)x, qg, (int32_t)z});
+        for (int64_t x = 0; x < xt; ++x)
+          for (int64_t z = 0; z < zt; ++z) bk.push_back({p, 2, (int32_t)x, qg, (int32_t)z});
     }
   }
-  if (items.size() > 0x7fffffff) return fail(SLDG_ERR_UNSUPPORTED, "work list too long");
+  std::vector<BatchItem> items;
+  std::vector<int32_t> off(kClasses + 1, 0);
+  for (int c = 0; c < kClasses; ++c) {
+    off[c] = (int32_t)std::min<size_t>(items.size(), 0x7fffffff);
+    items.insert(items.end(), bucket[c].begin(), bucket[c].end());
+    if (bucket[c].size() > 0x7fffffff || items.size() > 0x7fffffff)
+      return fail(SLDG_ERR_UNSUPPORTED, "work list too long");
+  }
+  off[kClasses] = (int32_t)items.size();
+  b->cls_off.resize((size_t)b->nseq * (kClasses + 1));
+  std::copy(off.begin(), off.end(), b->cls_off.begin() + (size_t)q * (kClasses + 1));
   for (int s = 0; s < 2; ++s) {
     SweepArgs*& d = b->d_args[(size_t)q * 2 + s];
     if (!d) {
@@ -169,11 +187,16 @@ sldg_status build_all(sldg_batch_s* b) {
 }
 
 sldg_status launch(sldg_batch_s* b, int q, int src) {
-  hipError_t e = launch_batch_sweep((int)b->tier, b->rows[q], b->d_args[(size_t)q * 2 + src],
-                                    b->d_k, b->d_items[q], b->nitems[q],
-                                    std::min<int32_t>(b->grid, std::max<int32_t>(1, b->nitems[q])),
-                                    b->stream);
-  if (e != hipSuccess) return device_error(e, "batched sweep launch");
+  const int32_t* off = b->cls_off.data() + (size_t)q * (kClasses + 1);
+  for (int c = 0; c < kClasses; ++c) {
+    const int32_t n = off[c + 1] - off[c];
+    if (n <= 0) continue;
+    const int kind = c / 3, k = c % 3 + 1;
+    hipError_t e = launch_batch_class((int)b->tier, k, kind, b->rows[q],
+                                      b->d_args[(size_t)q * 2 + src], b->d_items[q] + off[c], n,
+                                      kind == 2 ? kXcdStrided : kXcdContig, b->stream);
+    if (e != hipSuccess) return device_error(e, "batched sweep launch");
+  }
   return SLDG_OK;
 }
 
@@ -221,9 +244,6 @@ sldg_status sldg_batch_create(sldg_batch_t* out, int nprob, int ndim, const int6
     b->hi_bytes.push_back((m - 1) * c * elem_size(tier));
   }
   hipError_t e = hipGetDevice(&b->device);
-  int ncu = 0;
-  if (e == hipSuccess)
-    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device);
   // mode -> plane maps: mode 0 in the FP64 array, mode m >= 1 at hi plane m-1
   std::vector<int32_t> pm;
   for (int p = 0; p < nprob; ++p) {
@@ -234,16 +254,10 @@ sldg_status sldg_batch_create(sldg_batch_t* out, int nprob, int ndim, const int6
   if (e == hipSuccess) e = hipMalloc(&b->d_pmap, sizeof(int32_t) * pm.size());
   if (e == hipSuccess)
     e = hipMemcpy(b->d_pmap, pm.data(), sizeof(int32_t) * pm.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMalloc(&b->d_k, sizeof(int32_t) * nprob);
-  if (e == hipSuccess) {
-    std::vector<int32_t> kk(b->k.begin(), b->k.end());
-    e = hipMemcpy(b->d_k, kk.data(), sizeof(int32_t) * nprob, hipMemcpyHostToDevice);
-  }
   if (e != hipSuccess) {
     free_batch(b);
     return device_error(e, "batch create");
   }
-  b->grid = std::max(1, ncu) * 8;
   *out = b;
   return ok();
 }
@@ -383,8 +397,8 @@ sldg_status sldg_batch_run(sldg_batch_t b, int nsteps, int use_graph, int* resul
 sldg_status sldg_batch_set_tuning(sldg_batch_t b, int q, int rows, int tuples) {
   if (!b) return fail(SLDG_ERR_ARG, "batch is NULL");
   if (q < 0 || q >= b->nseq) return fail(SLDG_ERR_ARG, "sweep %d out of range", q);
-  if (!(rows == 1 || rows == 2 || rows == 4 || rows == 8) || tuples < 0)
-    return fail(SLDG_ERR_ARG, "rows %d / tuples %d", rows, tuples);
+  if (!(rows == 2 || rows == 4 || rows == 8) || tuples < 0)
+    return fail(SLDG_ERR_ARG, "rows %d not in {2, 4, 8} or tuples %d < 0", rows, tuples);
   b->rows[q] = rows;
   b->tuples[q] = tuples;
   if (b->bound) {

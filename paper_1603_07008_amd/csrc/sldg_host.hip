@@ -14,6 +14,7 @@
 
 #include "sldg.h"
 #include "sldg_internal.h"
+#include "sldg_ref.h"
 
 using namespace sldg;
 
@@ -152,6 +153,7 @@ void describe_grid(int ndim, const int64_t* n, int o, int64_t modes, int dim, ui
   a.fP = FastDiv::make((uint32_t)a.P);
   a.fN = FastDiv::make((uint32_t)a.N);
   a.fchunk = FastDiv::make((uint32_t)a.nchunk);
+  a.fG = FastDiv::make((uint32_t)((a.N + 3) / 4));
 }
 
 }  // namespace sldg
@@ -201,12 +203,14 @@ void describe(const sldg_plan_s* p, int dim, uint32_t dep_mask, SweepArgs& a, in
 
 // Launch shapes the tuner tries: (rows, tuples, column waves).  Dimension-0
 // sweeps only use the tuple count.
-constexpr int kTuneContig[][3] = {{4, 3, 1}, {4, 9, 1}, {4, 27, 1}, {4, 0, 1}};
+constexpr int kTuneContig[][3] = {{4, 1, 1}, {4, 3, 1}, {4, 9, 1}, {4, 27, 1}, {4, 0, 1}};
 constexpr int kTuneStrided[][3] = {
-    {2, 3, 1}, {2, 3, 2}, {2, 3, 4}, {2, 9, 1}, {2, 9, 2}, {2, 9, 4}, {2, 27, 1}, {2, 27, 2},
-    {2, 27, 4}, {4, 3, 1}, {4, 3, 2}, {4, 3, 4}, {4, 9, 1}, {4, 9, 2}, {4, 9, 4}, {4, 27, 1},
-    {4, 27, 2}, {4, 27, 4}, {8, 3, 1}, {8, 3, 2}, {8, 3, 4}, {8, 9, 1}, {8, 9, 2}, {8, 9, 4},
-    {8, 27, 1}, {8, 27, 2}, {8, 27, 4}};
+    {2, 1, 1},  {2, 1, 2},  {2, 1, 4},  {2, 3, 1},  {2, 3, 2},  {2, 3, 4},  {2, 9, 1},
+    {2, 9, 2},  {2, 9, 4},  {2, 27, 1}, {2, 27, 2}, {2, 27, 4}, {4, 1, 1},  {4, 1, 2},
+    {4, 1, 4},  {4, 3, 1},  {4, 3, 2},  {4, 3, 4},  {4, 9, 1},  {4, 9, 2},  {4, 9, 4},
+    {4, 27, 1}, {4, 27, 2}, {4, 27, 4}, {8, 1, 1},  {8, 1, 2},  {8, 1, 4},  {8, 3, 1},
+    {8, 3, 2},  {8, 3, 4},  {8, 9, 1},  {8, 9, 2},  {8, 9, 4},  {8, 27, 1}, {8, 27, 2},
+    {8, 27, 4}};
 constexpr int kNumTuneContig = sizeof(kTuneContig) / sizeof(kTuneContig[0]);
 constexpr int kNumTuneStrided = sizeof(kTuneStrided) / sizeof(kTuneStrided[0]);
 
@@ -802,6 +806,20 @@ sldg_status sldg_device_copy(const void* src, void* dst, int64_t bytes, void* st
   if (overlap(src, bytes, dst, bytes)) return fail(SLDG_ERR_ALIAS, "copy buffers overlap");
   hipError_t e = launch_copy16(src, dst, bytes / 16, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return device_error(e, "copy launch");
+  return ok();
+}
+
+sldg_status sldg_device_plane_copy(const void* src, void* dst, int64_t plane_bytes, int nplanes,
+                                   int planes_per_thread, void* stream) {
+  if (!src || !dst) return fail(SLDG_ERR_ARG, "null pointer");
+  if (plane_bytes < 0 || (plane_bytes & 15) || nplanes < 0 || planes_per_thread < 1 ||
+      (((uintptr_t)src | (uintptr_t)dst) & 15))
+    return fail(SLDG_ERR_ARG, "plane copy needs 16-byte multiples and alignment, T >= 1");
+  const int64_t bytes = plane_bytes * nplanes;
+  if (overlap(src, bytes, dst, bytes)) return fail(SLDG_ERR_ALIAS, "copy buffers overlap");
+  hipError_t e = launch_plane_copy16(src, dst, plane_bytes / 16, nplanes, planes_per_thread,
+                                     static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_error(e, "plane copy launch");
   return ok();
 }
 

@@ -70,6 +70,7 @@ struct SweepArgs {
   FastDiv fP;             // division by P
   FastDiv fN;             // division by N
   FastDiv fchunk;         // division by nchunk
+  FastDiv fG;             // division by ceil(N / 4) (dimension-0 group form)
   LineMap map;
   int32_t xcd;            // XCD-aware tile order: run length G (0 off, -1 one range per XCD)
   // FP16 storage with per-plane power-of-two scaling (all null: unscaled)
@@ -81,9 +82,9 @@ struct SweepArgs {
 
 // One workgroup-sized tile of one problem of a batched sweep.
 //   kind 0: dimension-0 sweep, window form: groups [x*256, x*256+256) of 4 cells
-//   kind 1: dimension-0 sweep, generic form: (line, tuple) pairs [4x, 4x+4)
+//   kind 1: dimension-0 sweep, group form: groups [x*256, x*256+256)
 //   kind 2: strided sweep: columns [64x, 64x+64), row chunks from z*(blockDim/64)
-// qg selects the run of spectator tuples (kinds 0 and 2).
+// qg selects the run of spectator tuples.
 struct BatchItem {
   int32_t prob, kind, x, qg, z;
 };
@@ -96,8 +97,10 @@ hipError_t launch_sweep(int k, int tier, int dim, const SweepArgs& a, hipStream_
 hipError_t launch_mass(const double* mass, int64_t n, double* partial, int nblocks,
                        double* result, hipStream_t st);
 
-hipError_t launch_batch_sweep(int tier, int rows, const SweepArgs* args, const int32_t* kdeg,
-                              const BatchItem* items, int32_t nitems, int32_t grid,
+// One class (tile kind, degree k) of a batched sweep: nitems workgroups, one
+// per item of `items` (kinds as in BatchItem; rows: 2, 4 or 8 for kind 2).
+hipError_t launch_batch_class(int tier, int k, int kind, int rows, const SweepArgs* args,
+                              const BatchItem* items, int32_t nitems, int32_t xcd,
                               hipStream_t st);
 bool contig_window_ok(const SweepArgs& a);
 // Waves of one sweep launch that compute a given output plane (the absmax

@@ -457,61 +457,6 @@ __device__ __forceinline__ void dispatch_nd(int nd, F&& f) {
 }
 
 // ---------------------------------------------------------------------------
-// Sweep along dimension 0, generic form (any N_0, any alignment).  One wave
-// per (line, spectator tuple): the line's s, A and B are wave-uniform (scalar
-// registers), lanes walk the line's cells.
-// ---------------------------------------------------------------------------
-
-template <int K, int TIER, int ND>
-__device__ __forceinline__ void contig_line(const SweepArgs& a, int64_t line, const TupleMap& tm,
-                                            int lane) {
-  float am[K + 1];
-  zero_amax(am);
-  Mat<K, TIER> M;
-  Rows64<K, ND> R;
-  Planes<K, TIER, ND> pl;
-  const int32_t t = __builtin_amdgcn_readfirstlane(table_index(a.map, 0, (int32_t)line));
-  const int32_t s = __builtin_amdgcn_readfirstlane(a.s_tab[t]);
-  M.load(a.ab_tab + t, a.ab_cs);
-  R.load(a.ab_tab + t, a.ab_cs);
-  pl.bind(a, tm);
-  const int32_t N = a.N;
-  const int64_t base = line * (int64_t)N;
-  for (int32_t i = lane; i < N; i += 64) {
-    int32_t ia = i - s;
-    if (ia < 0) ia += N;
-    int32_t ib = ia - 1;
-    if (ib < 0) ib += N;
-    Raw<K, TIER, ND> x, y;
-    pl.load(base + ia, x);
-    pl.load(base + ib, y);
-    pl.store(base + i, M, R, x, y, am, true);
-  }
-  flush_amax<K, TIER, ND>(a, pl, am, (int32_t)line);   // one wave per (line, tuple)
-}
-
-template <int K, int TIER, int NDMAX>
-__device__ __forceinline__ void contig_generic_item(const SweepArgs& a, int64_t item4) {
-  constexpr int O = K + 1;
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int64_t nlines = (int64_t)a.Q;
-  const int64_t item = item4 * 4 + wave;
-  if (item >= nlines * a.nspec) return;
-  const int32_t sp = (int32_t)(item / nlines);
-  const int64_t line = item - (int64_t)sp * nlines;
-  const TupleMap tm = tuple_map(a, sp * O, 1, O);
-  dispatch_nd<NDMAX>(tm.nd, [&](auto ndc) {
-    contig_line<K, TIER, decltype(ndc)::value>(a, line, tm, lane);
-  });
-}
-
-template <int K, int TIER, int NDMAX>
-__global__ __launch_bounds__(256) void sweep_contig_kernel(SweepArgs a) {
-  contig_generic_item<K, TIER, NDMAX>(a, (int64_t)blockIdx.x);
-}
-
-// ---------------------------------------------------------------------------
 // Sweep along dimension 0, window form (N_0 % 4 == 0, 16-byte aligned
 // buffers).  A thread produces 4 consecutive output cells i0..i0+3 of one line
 // for one spectator tuple.  Their sources are the 5 cells i0-s-1 .. i0-s+3,
@@ -589,40 +534,68 @@ struct Win {               // the 5-cell source window of one tuple
   Raw<K, TIER, ND> w[5];
 };
 
-template <int K, int TIER, int ND>
+// Where the 5 source cells of a thread's output cells lie.  Window form: two
+// aligned 4-cell blocks of the line and the offset in the first.  Group form:
+// the line offsets of the 5 cells and the number n of output cells (the last
+// group of a line holds N_0 % 4 cells when that is not 0).
+template <bool GROUP> struct Geo;
+template <> struct Geo<false> { int32_t blk0, blk1, d; };
+template <> struct Geo<true> { int32_t src[5]; int32_t n; };
+
+template <int K, int TIER, int ND, bool GROUP>
 __device__ __forceinline__ void contig_load(const Planes<K, TIER, ND>& pl, int64_t lb,
-                                            int32_t blk0, int32_t blk1, int d,
-                                            Win<K, TIER, ND>& W) {
+                                            const Geo<GROUP>& g, Win<K, TIER, ND>& W) {
   constexpr int O = K + 1;
   using T = typename Tier<TIER>::T;
 #pragma unroll
   for (int l = 0; l < O; ++l) {
-    if (l < ND) {
+    if constexpr (GROUP) {           // one load per source cell
+#pragma unroll
+      for (int u = 0; u < 5; ++u) {
+        if (l < ND) W.w[u].d[l] = pl.ind[l][lb + g.src[u]];
+        else W.w[u].h[l] = to_reg<TIER>(pl.inh[l][lb + g.src[u]], pl.fin[l]);
+      }
+    } else if (l < ND) {
       double m[5];
-      window5<double>(load4(pl.ind[l] + lb + 4 * blk0), load4(pl.ind[l] + lb + 4 * blk1), d, m);
+      window5<double>(load4(pl.ind[l] + lb + 4 * g.blk0), load4(pl.ind[l] + lb + 4 * g.blk1),
+                      g.d, m);
 #pragma unroll
       for (int u = 0; u < 5; ++u) W.w[u].d[l] = m[u];
     } else {
       T h[5];
-      window5<T>(load4(pl.inh[l] + lb + 4 * blk0), load4(pl.inh[l] + lb + 4 * blk1), d, h);
+      window5<T>(load4(pl.inh[l] + lb + 4 * g.blk0), load4(pl.inh[l] + lb + 4 * g.blk1), g.d, h);
 #pragma unroll
       for (int u = 0; u < 5; ++u) W.w[u].h[l] = to_reg<TIER>(h[u], pl.fin[l]);
     }
   }
 }
 
-template <int K, int TIER, int ND>
+template <int K, int TIER, int ND, bool GROUP>
 __device__ __forceinline__ void contig_store(const SweepArgs& a, const Planes<K, TIER, ND>& pl,
-                                             int64_t c, const Mat<K, TIER>& M,
-                                             const Rows64<K, ND>& R, const Win<K, TIER, ND>& W,
-                                             int32_t slot, bool active) {
+                                             int64_t c, const Geo<GROUP>& g,
+                                             const Mat<K, TIER>& M, const Rows64<K, ND>& R,
+                                             const Win<K, TIER, ND>& W, int32_t slot,
+                                             bool active) {
   constexpr int O = K + 1;
   using T = typename Tier<TIER>::T;
   float am[O];
   zero_amax(am);
 #pragma unroll
   for (int j = 0; j < O; ++j) {
-    if (j < ND) {
+    if constexpr (GROUP) {           // one store per output cell, the last group partial
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (u < g.n) {
+          if (j < ND) {
+            const double v = Mat<K, TIER>::out64(R, j, W.w[u + 1], W.w[u]);
+            if (active) pl.outd[j][c + u] = v;
+          } else {
+            const T v = pl.put(j, M.out_acc(j, W.w[u + 1], W.w[u]), am);
+            if (active) pl.outh[j][c + u] = v;
+          }
+        }
+      }
+    } else if (j < ND) {
       double o4[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) o4[u] = Mat<K, TIER>::out64(R, j, W.w[u + 1], W.w[u]);
@@ -637,18 +610,18 @@ __device__ __forceinline__ void contig_store(const SweepArgs& a, const Planes<K,
   flush_amax<K, TIER, ND>(a, pl, am, slot);
 }
 
-template <int K, int TIER, int ND>
+template <int K, int TIER, int ND, bool GROUP>
 __device__ __forceinline__ void contig_single(const SweepArgs& a, const TupleMap& tm,
-                                              const Mat<K, TIER>& M, int64_t lb, int32_t blk0,
-                                              int32_t blk1, int d, int64_t c, int32_t slot,
+                                              const Mat<K, TIER>& M, int64_t lb,
+                                              const Geo<GROUP>& g, int64_t c, int32_t slot,
                                               bool active) {
   Planes<K, TIER, ND> pl;
   pl.bind(a, tm);
   Rows64<K, ND> R;
   R.load(M.ab, M.cs);
   Win<K, TIER, ND> W;
-  contig_load<K, TIER, ND>(pl, lb, blk0, blk1, d, W);
-  contig_store<K, TIER, ND>(a, pl, c, M, R, W, slot, active);
+  contig_load<K, TIER, ND, GROUP>(pl, lb, g, W);
+  contig_store<K, TIER, ND, GROUP>(a, pl, c, g, M, R, W, slot, active);
 }
 
 // One thread: 4 consecutive output cells of one line, for the spectator
@@ -658,7 +631,7 @@ __device__ __forceinline__ void contig_single(const SweepArgs& a, const TupleMap
 // works on lines that share one table entry (the common case: the
 // displacement of a dimension-0 sweep rarely depends on dimension 1), the
 // entry is read with scalar loads and the matrices live in scalar registers.
-template <int K, int TIER, int NDMAX>
+template <int K, int TIER, int NDMAX, bool GROUP>
 __device__ __forceinline__ void contig_body(const SweepArgs& a, int32_t c, int32_t line,
                                             int32_t i0, int32_t t, int32_t q, int32_t qe,
                                             int32_t slot, bool active) {
@@ -667,9 +640,21 @@ __device__ __forceinline__ void contig_body(const SweepArgs& a, int32_t c, int32
   const int32_t s = a.s_tab[t];
   int32_t w0 = i0 - s - 1;
   if (w0 < 0) w0 += N;
-  const int32_t nb = N >> 2;
-  const int32_t blk0 = w0 >> 2, d = w0 & 3;
-  const int32_t blk1 = (blk0 + 1 == nb) ? 0 : blk0 + 1;
+  Geo<GROUP> geo;
+  if constexpr (GROUP) {
+#pragma unroll
+    for (int u = 0; u < 5; ++u) {
+      int32_t v = w0 + u;
+      while (v >= N) v -= N;           // at most once for N >= 4
+      geo.src[u] = v;
+    }
+    geo.n = min(4, N - i0);
+  } else {
+    const int32_t nb = N >> 2;
+    geo.blk0 = w0 >> 2;
+    geo.d = w0 & 3;
+    geo.blk1 = (geo.blk0 + 1 == nb) ? 0 : geo.blk0 + 1;
+  }
   const int64_t lb = (int64_t)line * N;
   Mat<K, TIER> M;
   M.load(a.ab_tab + t, a.ab_cs);
@@ -677,8 +662,7 @@ __device__ __forceinline__ void contig_body(const SweepArgs& a, int32_t c, int32
     TupleMap tm = tuple_map(a, q * O, 1, O);
     if (tm.nd != 0) {
       dispatch_nd<NDMAX>(tm.nd, [&](auto ndc) {
-        contig_single<K, TIER, decltype(ndc)::value>(a, tm, M, lb, blk0, blk1, d, c, slot,
-                                                     active);
+        contig_single<K, TIER, decltype(ndc)::value, GROUP>(a, tm, M, lb, geo, c, slot, active);
       });
       ++q;
       continue;
@@ -687,7 +671,7 @@ __device__ __forceinline__ void contig_body(const SweepArgs& a, int32_t c, int32
     Rows64<K, 0> R0;
     pc.bind(a, tm);
     Win<K, TIER, 0> cur, nxt;
-    contig_load<K, TIER, 0>(pc, lb, blk0, blk1, d, cur);
+    contig_load<K, TIER, 0, GROUP>(pc, lb, geo, cur);
     for (;;) {
       const int32_t q1 = q + 1;
       bool more = q1 < qe;
@@ -696,10 +680,10 @@ __device__ __forceinline__ void contig_body(const SweepArgs& a, int32_t c, int32
         more = tm1.nd == 0;
         if (more) {
           pn.bind(a, tm1);
-          contig_load<K, TIER, 0>(pn, lb, blk0, blk1, d, nxt);
+          contig_load<K, TIER, 0, GROUP>(pn, lb, geo, nxt);
         }
       }
-      contig_store<K, TIER, 0>(a, pc, c, M, R0, cur, slot, active);
+      contig_store<K, TIER, 0, GROUP>(a, pc, c, geo, M, R0, cur, slot, active);
       q = q1;
       if (!more) break;
 #pragma unroll
@@ -731,8 +715,36 @@ __device__ __forceinline__ void contig_group(const SweepArgs& a, int64_t g, int3
   const int32_t i0 = c - line * a.N;
   const int32_t t = table_index(a.map, 0, line);
   const int32_t t0 = __builtin_amdgcn_readfirstlane(t);
-  if (__all(t == t0)) contig_body<K, TIER, NDMAX>(a, c, line, i0, t0, q, qe, slot, active);
-  else contig_body<K, TIER, NDMAX>(a, c, line, i0, t, q, qe, slot, active);
+  if (__all(t == t0)) contig_body<K, TIER, NDMAX, false>(a, c, line, i0, t0, q, qe, slot, active);
+  else contig_body<K, TIER, NDMAX, false>(a, c, line, i0, t, q, qe, slot, active);
+}
+
+// Group gi of the dimension-0 sweep in the group form (any N_0, any
+// alignment): cells 4g .. min(4g+4, N_0)-1 of line gi / ng, g = gi % ng,
+// ng = ceil(N_0 / 4); tuples [q, qe).  Lanes past the last group act as in
+// contig_group.
+template <int K, int TIER, int NDMAX>
+__device__ __forceinline__ void contig_group_any(const SweepArgs& a, int64_t gi, int32_t q,
+                                                 int32_t qe, int32_t slot) {
+  const int32_t ng = (a.N + 3) >> 2;
+  const int64_t total = (int64_t)a.Q * ng;
+  bool active = true;
+  if (gi >= total) {
+    if constexpr (TIER != 3) {
+      return;
+    } else {
+      if (!a.amax_part) return;
+      gi = total - 1;
+      active = false;
+    }
+  }
+  const int32_t line = (int32_t)a.fG.div((uint32_t)gi);
+  const int32_t i0 = ((int32_t)gi - line * ng) << 2;
+  const int32_t c = line * a.N + i0;
+  const int32_t t = table_index(a.map, 0, line);
+  const int32_t t0 = __builtin_amdgcn_readfirstlane(t);
+  if (__all(t == t0)) contig_body<K, TIER, NDMAX, true>(a, c, line, i0, t0, q, qe, slot, active);
+  else contig_body<K, TIER, NDMAX, true>(a, c, line, i0, t, q, qe, slot, active);
 }
 
 // XCD-aware tile order.  Workgroups are dispatched round-robin over the 8
@@ -769,6 +781,20 @@ __global__ __launch_bounds__(256) void sweep_contig_window_kernel(SweepArgs a) {
   const int32_t q = by * a.tuples;
   contig_group<K, TIER, NDMAX>(a, g, q, min(a.nspec, q + a.tuples),
                                (int32_t)(bx * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+}
+
+template <int K, int TIER, int NDMAX>
+__global__ __launch_bounds__(256) void sweep_contig_group_kernel(SweepArgs a) {
+  uint32_t bx = blockIdx.x, by = blockIdx.y;
+  if (a.xcd) {                 // tile order: x fastest, then y
+    const uint32_t t = xcd_tile(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y, a.xcd);
+    by = t / gridDim.x;
+    bx = t - by * gridDim.x;
+  }
+  const int64_t gi = (int64_t)bx * blockDim.x + threadIdx.x;
+  const int32_t q = by * a.tuples;
+  contig_group_any<K, TIER, NDMAX>(a, gi, q, min(a.nspec, q + a.tuples),
+                                   (int32_t)(bx * (blockDim.x >> 6) + (threadIdx.x >> 6)));
 }
 
 // ---------------------------------------------------------------------------
@@ -985,9 +1011,9 @@ static bool sweep_grid(int dim, const SweepArgs& a, int& form, dim3& grid, dim3&
       grid = dim3((unsigned)((groups + 255) / 256), (unsigned)((a.nspec + a.tuples - 1) / a.tuples));
       block = dim3(256);
     } else {
-      const int64_t items = (int64_t)a.Q * a.nspec;
+      const int64_t groups = (int64_t)a.Q * ((a.N + 3) / 4);
       form = 1;
-      grid = dim3((unsigned)((items + 3) / 4));
+      grid = dim3((unsigned)((groups + 255) / 256), (unsigned)((a.nspec + a.tuples - 1) / a.tuples));
       block = dim3(256);
     }
     return true;
@@ -1007,8 +1033,7 @@ int64_t sweep_slots(int dim, const SweepArgs& a) {
   int form;
   dim3 grid, block;
   if (!sweep_grid(dim, a, form, grid, block)) return -1;
-  if (form == 0) return (int64_t)grid.x * (block.x / 64);
-  if (form == 1) return a.Q;                           // one wave per (line, tuple)
+  if (form == 0 || form == 1) return (int64_t)grid.x * (block.x / 64);
   return (int64_t)grid.x * grid.z * (block.x / 64);
 }
 
@@ -1020,7 +1045,7 @@ static hipError_t launch_sweep_ktn(int dim, const SweepArgs& a, hipStream_t st) 
   if (form == 0) {
     sweep_contig_window_kernel<K, TIER, NDMAX><<<grid, block, 0, st>>>(a);
   } else if (form == 1) {
-    sweep_contig_kernel<K, TIER, NDMAX><<<grid, block, 0, st>>>(a);
+    sweep_contig_group_kernel<K, TIER, NDMAX><<<grid, block, 0, st>>>(a);
   } else {
     switch (a.chunk) {
       case 1: sweep_strided_kernel<K, TIER, 1, NDMAX><<<grid, block, 0, st>>>(a); break;
@@ -1060,69 +1085,85 @@ hipError_t launch_sweep(int k, int tier, int dim, const SweepArgs& a, hipStream_
 }
 
 // ---------------------------------------------------------------------------
-// Batched sweep: many independent problems (own grid, degree and tables) in
-// one persistent launch.  The work list holds one item per workgroup-sized
-// tile of one problem; a fixed grid of workgroups walks the list, so uneven
-// problem sizes and degrees share the launch without idle tails per problem.
-// Items of dimension-0 sweeps are windows of 256 x 4 cells (when the
-// problem's N_0 % 4 == 0 and its buffers are 16-byte aligned) or, otherwise,
-// 4 (line, tuple) pairs of the generic form; items of strided sweeps are 64
-// columns x (blockDim/64) row chunks.  A run of tuples is part of the item.
+// Batched sweep: many independent problems (own grid, degree and tables).
+// The work list of a sweep holds one item per workgroup-sized tile of one
+// problem, grouped by class (tile kind and degree).  Each class is one
+// launch of a kernel compiled for that kind and degree alone (one workgroup
+// per item, XCD-aware order), so no kernel carries the registers of the
+// other code paths; the classes of a split step are captured together in one
+// HIP graph.  Kinds: 0 dimension-0 window form (256 groups of 4 cells),
+// 1 dimension-0 group form (256 groups), 2 strided (64 columns x 4 row
+// chunks).  A run of spectator tuples is part of the item.
 // ---------------------------------------------------------------------------
 
-template <int TIER, int L>
-__global__ __launch_bounds__(256) void batch_sweep_kernel(const SweepArgs* __restrict__ args,
-                                                          const int32_t* __restrict__ kdeg,
+template <int K, int TIER, int KIND, int L>
+__global__ __launch_bounds__(256) void batch_class_kernel(const SweepArgs* __restrict__ args,
                                                           const BatchItem* __restrict__ items,
-                                                          int32_t nitems) {
-  for (int32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const BatchItem w = items[it];
-    const SweepArgs& a = args[w.prob];
-    const int32_t k = kdeg[w.prob];
-    const int32_t q = w.qg * a.tuples;
-    const int32_t qe = min(a.nspec, q + a.tuples);
-    if (w.kind == 0) {               // dimension 0, window form
-      const int64_t g = (int64_t)w.x * blockDim.x + threadIdx.x;
-      if (k == 1) contig_group<1, TIER, 1>(a, g, q, qe, 0);
-      else if (k == 2) contig_group<2, TIER, 1>(a, g, q, qe, 0);
-      else contig_group<3, TIER, 1>(a, g, q, qe, 0);
-    } else if (w.kind == 1) {        // dimension 0, generic form
-      if (k == 1) contig_generic_item<1, TIER, 1>(a, w.x);
-      else if (k == 2) contig_generic_item<2, TIER, 1>(a, w.x);
-      else contig_generic_item<3, TIER, 1>(a, w.x);
-    } else {                         // strided
-      const int32_t col = w.x * 64 + (int32_t)(threadIdx.x & 63);
-      const int32_t chunk = w.z * (int32_t)(blockDim.x >> 6) + (int32_t)(threadIdx.x >> 6);
-      if (k == 1) strided_cell<1, TIER, L, 1>(a, col, chunk, q, qe, 0);
-      else if (k == 2) strided_cell<2, TIER, L, 1>(a, col, chunk, q, qe, 0);
-      else strided_cell<3, TIER, L, 1>(a, col, chunk, q, qe, 0);
-    }
+                                                          int32_t xcd) {
+  const BatchItem w = items[xcd_tile(blockIdx.x, gridDim.x, xcd)];
+  const SweepArgs& a = args[w.prob];
+  const int32_t q = w.qg * a.tuples;
+  const int32_t qe = min(a.nspec, q + a.tuples);
+  if constexpr (KIND == 0) {
+    contig_group<K, TIER, 1>(a, (int64_t)w.x * blockDim.x + threadIdx.x, q, qe, 0);
+  } else if constexpr (KIND == 1) {
+    contig_group_any<K, TIER, 1>(a, (int64_t)w.x * blockDim.x + threadIdx.x, q, qe, 0);
+  } else {
+    const int32_t col = w.x * 64 + (int32_t)(threadIdx.x & 63);
+    const int32_t chunk = w.z * (int32_t)(blockDim.x >> 6) + (int32_t)(threadIdx.x >> 6);
+    strided_cell<K, TIER, L, 1>(a, col, chunk, q, qe, 0);
   }
 }
 
-template <int TIER>
-static hipError_t launch_batch_t(int rows, const SweepArgs* args, const int32_t* kdeg,
-                                 const BatchItem* items, int32_t nitems, int32_t grid,
-                                 hipStream_t st) {
-  switch (rows) {
-    case 1: batch_sweep_kernel<TIER, 1><<<grid, 256, 0, st>>>(args, kdeg, items, nitems); break;
-    case 2: batch_sweep_kernel<TIER, 2><<<grid, 256, 0, st>>>(args, kdeg, items, nitems); break;
-    case 4: batch_sweep_kernel<TIER, 4><<<grid, 256, 0, st>>>(args, kdeg, items, nitems); break;
-    case 8: batch_sweep_kernel<TIER, 8><<<grid, 256, 0, st>>>(args, kdeg, items, nitems); break;
-    default: return hipErrorInvalidValue;
+template <int K, int TIER, int KIND>
+static hipError_t launch_class_ktk(int rows, const SweepArgs* args, const BatchItem* items,
+                                   int32_t nitems, int32_t xcd, hipStream_t st) {
+  if constexpr (KIND != 2) {
+    batch_class_kernel<K, TIER, KIND, 1><<<nitems, 256, 0, st>>>(args, items, xcd);
+  } else {
+    switch (rows) {
+      case 2: batch_class_kernel<K, TIER, 2, 2><<<nitems, 256, 0, st>>>(args, items, xcd); break;
+      case 4: batch_class_kernel<K, TIER, 2, 4><<<nitems, 256, 0, st>>>(args, items, xcd); break;
+      case 8: batch_class_kernel<K, TIER, 2, 8><<<nitems, 256, 0, st>>>(args, items, xcd); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }
 
-hipError_t launch_batch_sweep(int tier, int rows, const SweepArgs* args, const int32_t* kdeg,
-                              const BatchItem* items, int32_t nitems, int32_t grid,
+template <int K, int TIER>
+static hipError_t launch_class_kt(int kind, int rows, const SweepArgs* args,
+                                  const BatchItem* items, int32_t nitems, int32_t xcd,
+                                  hipStream_t st) {
+  switch (kind) {
+    case 0: return launch_class_ktk<K, TIER, 0>(rows, args, items, nitems, xcd, st);
+    case 1: return launch_class_ktk<K, TIER, 1>(rows, args, items, nitems, xcd, st);
+    case 2: return launch_class_ktk<K, TIER, 2>(rows, args, items, nitems, xcd, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int K>
+static hipError_t launch_class_k(int tier, int kind, int rows, const SweepArgs* args,
+                                 const BatchItem* items, int32_t nitems, int32_t xcd,
+                                 hipStream_t st) {
+  switch (tier) {
+    case 0: return launch_class_kt<K, 0>(kind, rows, args, items, nitems, xcd, st);
+    case 1: return launch_class_kt<K, 1>(kind, rows, args, items, nitems, xcd, st);
+    case 2: return launch_class_kt<K, 2>(kind, rows, args, items, nitems, xcd, st);
+    case 3: return launch_class_kt<K, 3>(kind, rows, args, items, nitems, xcd, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_batch_class(int tier, int k, int kind, int rows, const SweepArgs* args,
+                              const BatchItem* items, int32_t nitems, int32_t xcd,
                               hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
-  switch (tier) {
-    case 0: return launch_batch_t<0>(rows, args, kdeg, items, nitems, grid, st);
-    case 1: return launch_batch_t<1>(rows, args, kdeg, items, nitems, grid, st);
-    case 2: return launch_batch_t<2>(rows, args, kdeg, items, nitems, grid, st);
-    case 3: return launch_batch_t<3>(rows, args, kdeg, items, nitems, grid, st);
+  switch (k) {
+    case 1: return launch_class_k<1>(tier, kind, rows, args, items, nitems, xcd, st);
+    case 2: return launch_class_k<2>(tier, kind, rows, args, items, nitems, xcd, st);
+    case 3: return launch_class_k<3>(tier, kind, rows, args, items, nitems, xcd, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -113,3 +113,48 @@ def test_graph_replays_match_eager_and_tuning_keeps_results(sl):
         stream.synchronize()
         for i in range(len(probs)):
             assert np.array_equal(download(*(s0, s1)[res][i]), ref[0][i])
+
+
+def test_full_batched_workload_matches_single_plans_and_oracle(sl):
+    """The batched workload at its full size (512 problems, N_x, N_v in
+    32..512, k in 1..3, FP32-mode) in the launch shapes the batch tuner
+    picks: every problem bitwise equal to its own single-plan run, a sample
+    against the oracle."""
+    import torch
+    probs = inputs.batched_landau(nprob=512, seed=4)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        from paper_1603_07008_amd.batch import Batch
+        b = Batch([p.ns for p in probs], [p.k for p in probs], "fp32", stream=stream.cuda_stream)
+        c0s = [O.to_tier(inputs.random_coefficients(2, p.k, p.cells, seed=100 + i), "fp32")
+               for i, p in enumerate(probs)]
+        s0 = [upload(c, "fp32") for c in c0s]
+        s1 = [(m.clone(), h.clone()) for m, h in s0]
+        b.bind(s0, s1)
+        shifts = [[(sw.dep_mask, _dev(sw.sigma)) for sw in p.seq] for p in probs]
+        b.set_sequence([(probs[0].seq[q].dim, [shifts[i][q] for i in range(len(probs))])
+                        for q in range(3)])
+        b.tune(reps=1)
+        for i in range(len(probs)):            # start from the initial state again
+            m, h = upload(c0s[i], "fp32")
+            s0[i][0].copy_(m)
+            s0[i][1].copy_(h)
+        res = b.run(1, use_graph=True)
+        stream.synchronize()
+        rng = np.random.default_rng(12)
+        sample = set(rng.choice(len(probs), 6, replace=False).tolist())
+        for i, p in enumerate(probs):
+            got = download(*(s0, s1)[res][i])
+            plan = sl.Plan(p.ns, p.k, "fp32", stream=stream.cuda_stream)
+            a = upload(c0s[i], "fp32")
+            c = plan.empty_state()
+            r = plan.split_steps([(sw.dim, sw.dep_mask, shifts[i][q][1])
+                                  for q, sw in enumerate(p.seq)], 1, a, c)
+            stream.synchronize()
+            assert np.array_equal(got, download(*(a, c)[r])), (i, p.ns, p.k)
+            plan.close()
+            if i in sample:
+                want = O.run_sequence(c0s[i], p.ns, p.k, [(s.dim, s.sigma, s.dep) for s in p.seq],
+                                      "fp32", 1)
+                assert weighted_rel_l2(got, want, 2, p.k) <= 2.0 ** -24, (i, p.ns, p.k)
+        b.close()
