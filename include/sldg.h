@@ -356,14 +356,23 @@ sldg_status sldg_batch_set_sequence(sldg_batch_t batch, int nseq, const int* dim
  * use_graph != 0: each step is captured once (per starting buffer) into a
  * HIP graph and replayed. */
 sldg_status sldg_batch_run(sldg_batch_t batch, int nsteps, int use_graph, int* result_buffer);
-/* Launch-shape tuner: for every sweep of the sequence, times rows-per-thread
+/* Launch-shape tuner: for every sweep of the sequence and every class of its
+ * work list (tile kind: 0 dimension-0 window form, 1 dimension-0 group form,
+ * 2 strided; x degree 1..3; class = 3 * kind + k - 1), times rows-per-thread
  * {2, 4, 8} (strided sweeps) x tuples-per-thread {1, 3, 9, all} on the bound
- * data (reads buffer 0, overwrites buffer 1) and keeps the fastest. */
+ * data (reads buffer 0, overwrites buffer 1) and keeps the fastest per class. */
 sldg_status sldg_batch_tune(sldg_batch_t batch, int reps);
-/* Read / set the launch shape of sweep q (rows 2, 4 or 8; tuples 0 = all);
- * ms is the tuned time per sweep (-1 if not tuned). */
+/* Set the launch shape of every class of sweep q (rows 2, 4 or 8; tuples
+ * 0 = all).  get: the shape of the class with the most tiles, and the tuned
+ * time of the whole sweep (-1 if not tuned). */
 sldg_status sldg_batch_get_tuning(sldg_batch_t batch, int q, int* rows, int* tuples, double* ms);
 sldg_status sldg_batch_set_tuning(sldg_batch_t batch, int q, int rows, int tuples);
+/* Shape, tuned time (ms, -1 if not tuned) and tile count of class `cls` (0..8)
+ * of sweep q. */
+sldg_status sldg_batch_get_class_tuning(sldg_batch_t batch, int q, int cls, int* rows,
+                                        int* tuples, double* ms, int* nitems);
+/* Set the launch shape of class `cls` of sweep q alone. */
+sldg_status sldg_batch_set_class_tuning(sldg_batch_t batch, int q, int cls, int rows, int tuples);
 
 const char* sldg_status_string(sldg_status s);
 const char* sldg_last_error(void);

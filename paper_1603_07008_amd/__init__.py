@@ -26,7 +26,7 @@ EXPORTS = ("sldg_plan", "sldg_plan_destroy", "sldg_plan_set_stream", "sldg_line_
            "sldg_scale_bytes", "sldg_set_scale_headroom", "sldg_scaled_import",
            "sldg_scaled_export", "sldg_advect_dim_scaled", "sldg_split_steps_scaled",
            "sldg_plan_set_shape", "sldg_plan_get_shape", "sldg_tune_candidate", "sldg_plan_tune",
-           "sldg_device_plane_copy")
+           "sldg_device_plane_copy", "sldg_batch_get_class_tuning", "sldg_batch_set_class_tuning")
 
 
 class SldgError(RuntimeError):

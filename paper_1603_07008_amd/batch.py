@@ -42,6 +42,13 @@ def _lib():
         L.sldg_batch_get_tuning.restype = i32
         L.sldg_batch_set_tuning.argtypes = [vp, i32, i32, i32]
         L.sldg_batch_set_tuning.restype = i32
+        L.sldg_batch_get_class_tuning.argtypes = [vp, i32, i32, ctypes.POINTER(i32),
+                                                  ctypes.POINTER(i32),
+                                                  ctypes.POINTER(ctypes.c_double),
+                                                  ctypes.POINTER(i32)]
+        L.sldg_batch_get_class_tuning.restype = i32
+        L.sldg_batch_set_class_tuning.argtypes = [vp, i32, i32, i32, i32]
+        L.sldg_batch_set_class_tuning.restype = i32
         _bound = True
     return L
 
@@ -166,19 +173,38 @@ class Batch:
         _check(_lib().sldg_batch_tune(self.handle, int(reps)), "sldg_batch_tune")
         return self.tuning()
 
+    CLASSES = 9         # work-list classes: 3 * kind + k - 1 (kind 0 window, 1 group, 2 strided)
+
     def tuning(self):
+        """Per sweep: the shape of its largest class, the tuned time of the
+        sweep, and the shape, time and tile count of every non-empty class."""
         out = []
         for q in range(self.nseq):
             r, t, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
             _check(_lib().sldg_batch_get_tuning(self.handle, q, ctypes.byref(r), ctypes.byref(t),
                                                 ctypes.byref(ms)), "sldg_batch_get_tuning")
-            out.append({"rows": r.value, "tuples": t.value, "ms": ms.value})
+            classes = {}
+            for c in range(self.CLASSES):
+                cr, ct, cms, n = ctypes.c_int(), ctypes.c_int(), ctypes.c_double(), ctypes.c_int()
+                _check(_lib().sldg_batch_get_class_tuning(self.handle, q, c, ctypes.byref(cr),
+                                                          ctypes.byref(ct), ctypes.byref(cms),
+                                                          ctypes.byref(n)),
+                       "sldg_batch_get_class_tuning")
+                if n.value:
+                    classes[str(c)] = {"rows": cr.value, "tuples": ct.value, "ms": cms.value,
+                                       "tiles": n.value}
+            out.append({"rows": r.value, "tuples": t.value, "ms": ms.value, "classes": classes})
         return out
 
     def set_tuning(self, shapes):
+        """Apply shapes as `tuning()` returns them (per class when given)."""
         for q, sh in enumerate(shapes):
             _check(_lib().sldg_batch_set_tuning(self.handle, q, int(sh["rows"]), int(sh["tuples"])),
                    "sldg_batch_set_tuning")
+            for c, cs in sh.get("classes", {}).items():
+                _check(_lib().sldg_batch_set_class_tuning(self.handle, q, int(c), int(cs["rows"]),
+                                                          int(cs["tuples"])),
+                       "sldg_batch_set_class_tuning")
 
     def tune_cached(self, path, reps=3):
         """Tuned shapes from the JSON cache at `path` if it has this batch's

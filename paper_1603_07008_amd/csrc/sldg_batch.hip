@@ -38,7 +38,7 @@ struct sldg_batch_s {
   double* d_ab = nullptr;
   int32_t* d_pmap = nullptr;              // mode -> plane maps (FP64 cell mean only), per problem
   std::vector<int64_t> pmap_off;
-  // launch shape per sweep of the sequence
+  // launch shape per sweep of the sequence and work-list class, [q * kClasses + c]
   std::vector<int> rows, tuples;
   std::vector<double> tuned_ms;
   // device work description per sweep q: args for source buffer b at [q*2+b]
@@ -100,11 +100,20 @@ sldg_status build_sweep(sldg_batch_s* b, int q) {
   for (int p = 0; p < b->nprob; ++p) {
     const int o = b->k[p] + 1;
     const uint32_t mask = b->masks[(size_t)q * b->nprob + p];
+    // the problem's class: tile kind (window needs N_0 % 4 == 0 and aligned buffers) x degree
+    int kind = 2;
+    if (dim == 0) {
+      bool window = ext(b, p)[0] % 4 == 0;
+      for (int s = 0; s < 2; ++s)
+        window = window && aligned16(b->mass[s][p]) && aligned16(b->hi[s][p]);
+      kind = window ? 0 : 1;
+    }
+    const size_t sc = (size_t)q * kClasses + class_of(kind, b->k[p]);
     for (int src = 0; src < 2; ++src) {
       SweepArgs& a = args[src][p];
       a = SweepArgs{};
       int64_t ntab = 0;
-      describe_grid(b->ndim, ext(b, p), o, b->modes[p], dim, mask, b->rows[q], b->tuples[q], a,
+      describe_grid(b->ndim, ext(b, p), o, b->modes[p], dim, mask, b->rows[sc], b->tuples[sc], a,
                     ntab);
       a.in_lo = b->mass[src][p];
       a.in_hi = b->hi[src][p];
@@ -118,11 +127,7 @@ sldg_status build_sweep(sldg_batch_s* b, int q) {
     const SweepArgs& a = args[0][p];
     const int32_t nq = (a.nspec + a.tuples - 1) / a.tuples;
     if (dim == 0) {
-      bool window = a.N % 4 == 0;
-      for (int s = 0; s < 2; ++s)
-        window = window && aligned16(b->mass[s][p]) && aligned16(b->hi[s][p]);
-      const int kind = window ? 0 : 1;
-      const int64_t groups = window ? a.cells / 4 : (int64_t)a.Q * ((a.N + 3) / 4);
+      const int64_t groups = kind == 0 ? a.cells / 4 : (int64_t)a.Q * ((a.N + 3) / 4);
       const int64_t tiles = (groups + 255) / 256;
       auto& bk = bucket[class_of(kind, b->k[p])];
       for (int32_t qg = 0; qg < nq; ++qg)
@@ -192,7 +197,7 @@ sldg_status launch(sldg_batch_s* b, int q, int src) {
     const int32_t n = off[c + 1] - off[c];
     if (n <= 0) continue;
     const int kind = c / 3, k = c % 3 + 1;
-    hipError_t e = launch_batch_class((int)b->tier, k, kind, b->rows[q],
+    hipError_t e = launch_batch_class((int)b->tier, k, kind, b->rows[(size_t)q * kClasses + c],
                                       b->d_args[(size_t)q * 2 + src], b->d_items[q] + off[c], n,
                                       kind == 2 ? kXcdStrided : kXcdContig, b->stream);
     if (e != hipSuccess) return device_error(e, "batched sweep launch");
@@ -343,9 +348,9 @@ sldg_status sldg_batch_set_sequence(sldg_batch_t b, int nseq, const int* dims,
                              b->stream);
       if (e != hipSuccess) return device_error(e, "batch line tables");
     }
-  b->rows.assign(nseq, 8);
-  b->tuples.assign(nseq, 9);
-  b->tuned_ms.assign(nseq, -1.0);
+  b->rows.assign((size_t)nseq * kClasses, 4);
+  b->tuples.assign((size_t)nseq * kClasses, 9);
+  b->tuned_ms.assign((size_t)nseq * kClasses, -1.0);
   sldg_status st = build_all(b);
   return st == SLDG_OK ? ok() : st;
 }
@@ -399,8 +404,11 @@ sldg_status sldg_batch_set_tuning(sldg_batch_t b, int q, int rows, int tuples) {
   if (q < 0 || q >= b->nseq) return fail(SLDG_ERR_ARG, "sweep %d out of range", q);
   if (!(rows == 2 || rows == 4 || rows == 8) || tuples < 0)
     return fail(SLDG_ERR_ARG, "rows %d not in {2, 4, 8} or tuples %d < 0", rows, tuples);
-  b->rows[q] = rows;
-  b->tuples[q] = tuples;
+  for (int c = 0; c < kClasses; ++c) {
+    b->rows[(size_t)q * kClasses + c] = rows;
+    b->tuples[(size_t)q * kClasses + c] = tuples;
+    b->tuned_ms[(size_t)q * kClasses + c] = -1.0;
+  }
   if (b->bound) {
     drop_graphs(b);
     sldg_status st = build_sweep(b, q);
@@ -409,12 +417,67 @@ sldg_status sldg_batch_set_tuning(sldg_batch_t b, int q, int rows, int tuples) {
   return ok();
 }
 
+sldg_status sldg_batch_set_class_tuning(sldg_batch_t b, int q, int cls, int rows, int tuples) {
+  if (!b) return fail(SLDG_ERR_ARG, "batch is NULL");
+  if (q < 0 || q >= b->nseq) return fail(SLDG_ERR_ARG, "sweep %d out of range", q);
+  if (cls < 0 || cls >= kClasses) return fail(SLDG_ERR_ARG, "class %d out of range", cls);
+  if (!(rows == 2 || rows == 4 || rows == 8) || tuples < 0)
+    return fail(SLDG_ERR_ARG, "rows %d not in {2, 4, 8} or tuples %d < 0", rows, tuples);
+  const size_t i = (size_t)q * kClasses + cls;
+  b->rows[i] = rows;
+  b->tuples[i] = tuples;
+  b->tuned_ms[i] = -1.0;
+  if (b->bound) {
+    drop_graphs(b);
+    sldg_status st = build_sweep(b, q);
+    if (st != SLDG_OK) return st;
+  }
+  return ok();
+}
+
+sldg_status sldg_batch_get_class_tuning(sldg_batch_t b, int q, int cls, int* rows, int* tuples,
+                                        double* ms, int* nitems) {
+  if (!b) return fail(SLDG_ERR_ARG, "batch is NULL");
+  if (q < 0 || q >= b->nseq) return fail(SLDG_ERR_ARG, "sweep %d out of range", q);
+  if (cls < 0 || cls >= kClasses) return fail(SLDG_ERR_ARG, "class %d out of range", cls);
+  const size_t i = (size_t)q * kClasses + cls;
+  if (rows) *rows = b->rows[i];
+  if (tuples) *tuples = b->tuples[i];
+  if (ms) *ms = b->tuned_ms[i];
+  if (nitems) {
+    *nitems = 0;
+    if (b->ready && b->cls_off.size() >= (size_t)(q + 1) * (kClasses + 1)) {
+      const int32_t* off = b->cls_off.data() + (size_t)q * (kClasses + 1);
+      *nitems = off[cls + 1] - off[cls];
+    }
+  }
+  return ok();
+}
+
 sldg_status sldg_batch_get_tuning(sldg_batch_t b, int q, int* rows, int* tuples, double* ms) {
   if (!b) return fail(SLDG_ERR_ARG, "batch is NULL");
   if (q < 0 || q >= b->nseq) return fail(SLDG_ERR_ARG, "sweep %d out of range", q);
-  if (rows) *rows = b->rows[q];
-  if (tuples) *tuples = b->tuples[q];
-  if (ms) *ms = b->tuned_ms[q];
+  // the shape of the class with the most tiles, and the tuned time of the whole sweep
+  int best = 0;
+  int32_t most = -1;
+  double tot = 0.0;
+  bool tuned = true;
+  for (int c = 0; c < kClasses; ++c) {
+    int n = 0;
+    (void)sldg_batch_get_class_tuning(b, q, c, nullptr, nullptr, nullptr, &n);
+    if (n > most) {
+      most = n;
+      best = c;
+    }
+    const double t = b->tuned_ms[(size_t)q * kClasses + c];
+    if (n > 0) {
+      if (t < 0) tuned = false;
+      else tot += t;
+    }
+  }
+  if (rows) *rows = b->rows[(size_t)q * kClasses + best];
+  if (tuples) *tuples = b->tuples[(size_t)q * kClasses + best];
+  if (ms) *ms = tuned ? tot : -1.0;
   return ok();
 }
 
@@ -422,47 +485,70 @@ sldg_status sldg_batch_tune(sldg_batch_t b, int reps) {
   if (!b) return fail(SLDG_ERR_ARG, "batch is NULL");
   if (!b->ready) return fail(SLDG_ERR_ARG, "bind the states and set the sequence first");
   if (reps < 1) reps = 1;
-  hipEvent_t e0, e1;
-  hipError_t e = hipEventCreate(&e0);
-  if (e == hipSuccess) e = hipEventCreate(&e1);
-  if (e != hipSuccess) return device_error(e, "hipEventCreate");
+  hipEvent_t ev[kClasses + 1];
+  int nev = 0;
+  hipError_t e = hipSuccess;
+  for (; nev < kClasses + 1 && e == hipSuccess; ++nev) e = hipEventCreate(&ev[nev]);
+  if (e != hipSuccess) {
+    for (int i = 0; i < nev - 1; ++i) (void)hipEventDestroy(ev[i]);
+    return device_error(e, "hipEventCreate");
+  }
   const int rows_c[3] = {2, 4, 8};
   const int tup_c[4] = {1, 3, 9, 0};
   sldg_status st = SLDG_OK;
   for (int q = 0; q < b->nseq && st == SLDG_OK; ++q) {
-    int best_r = b->rows[q], best_t = b->tuples[q];
-    double best = 1e300;
+    int best_r[kClasses], best_t[kClasses];
+    double best[kClasses];
+    for (int c = 0; c < kClasses; ++c) {
+      best_r[c] = b->rows[(size_t)q * kClasses + c];
+      best_t[c] = b->tuples[(size_t)q * kClasses + c];
+      best[c] = 1e300;
+    }
     const int nr = b->dims[q] == 0 ? 1 : 3;
     for (int ir = 0; ir < nr && st == SLDG_OK; ++ir)
       for (int it = 0; it < 4 && st == SLDG_OK; ++it) {
-        b->rows[q] = b->dims[q] == 0 ? best_r : rows_c[ir];
-        b->tuples[q] = tup_c[it];
+        // every class of the sweep takes the candidate; each class is timed alone
+        for (int c = 0; c < kClasses; ++c) {
+          b->rows[(size_t)q * kClasses + c] = b->dims[q] == 0 ? 4 : rows_c[ir];
+          b->tuples[(size_t)q * kClasses + c] = tup_c[it];
+        }
         st = build_sweep(b, q);
         if (st != SLDG_OK) break;
         st = launch(b, q, 0);                 // warm-up
-        (void)hipEventRecord(e0, b->stream);
-        for (int r = 0; r < reps && st == SLDG_OK; ++r) st = launch(b, q, 0);
-        (void)hipEventRecord(e1, b->stream);
-        e = hipEventSynchronize(e1);
-        if (e != hipSuccess) {
-          st = device_error(e, "tuning");
-          break;
+        const int32_t* off = b->cls_off.data() + (size_t)q * (kClasses + 1);
+        for (int c = 0; c < kClasses && st == SLDG_OK; ++c) {
+          const int32_t n = off[c + 1] - off[c];
+          (void)hipEventRecord(ev[c], b->stream);
+          for (int r = 0; r < reps && n > 0 && st == SLDG_OK; ++r) {
+            e = launch_batch_class((int)b->tier, c % 3 + 1, c / 3,
+                                   b->rows[(size_t)q * kClasses + c],
+                                   b->d_args[(size_t)q * 2], b->d_items[q] + off[c], n,
+                                   c / 3 == 2 ? kXcdStrided : kXcdContig, b->stream);
+            if (e != hipSuccess) st = device_error(e, "tuning launch");
+          }
         }
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms / reps < best) {
-          best = ms / reps;
-          best_r = b->rows[q];
-          best_t = b->tuples[q];
+        (void)hipEventRecord(ev[kClasses], b->stream);
+        e = hipEventSynchronize(ev[kClasses]);
+        if (st == SLDG_OK && e != hipSuccess) st = device_error(e, "tuning");
+        for (int c = 0; c < kClasses && st == SLDG_OK; ++c) {
+          if (off[c + 1] == off[c]) continue;
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, ev[c], ev[c + 1]);
+          if (ms / reps < best[c]) {
+            best[c] = ms / reps;
+            best_r[c] = b->rows[(size_t)q * kClasses + c];
+            best_t[c] = b->tuples[(size_t)q * kClasses + c];
+          }
         }
       }
-    b->rows[q] = best_r;
-    b->tuples[q] = best_t;
-    b->tuned_ms[q] = best;
+    for (int c = 0; c < kClasses; ++c) {
+      b->rows[(size_t)q * kClasses + c] = best_r[c];
+      b->tuples[(size_t)q * kClasses + c] = best_t[c];
+      b->tuned_ms[(size_t)q * kClasses + c] = best[c] < 1e299 ? best[c] : -1.0;
+    }
     if (st == SLDG_OK) st = build_sweep(b, q);
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  for (int i = 0; i < kClasses + 1; ++i) (void)hipEventDestroy(ev[i]);
   drop_graphs(b);
   return st == SLDG_OK ? ok() : st;
 }
