@@ -120,6 +120,7 @@ sldg_status build_sweep(sldg_batch_s* b, int q) {
       a.out_lo = b->mass[1 - src][p];
       a.out_hi = b->hi[1 - src][p];
       a.pmap = b->d_pmap + b->pmap_off[p];
+      a.n_lo = 1;                             // the cell mean in FP64, mode m at hi plane m-1
       a.s_tab = b->d_s + b->tab_off[(size_t)q * b->nprob + p];
       a.ab_tab = b->d_ab + b->ab_off[(size_t)q * b->nprob + p];
       a.ab_cs = ntab;

@@ -308,6 +308,7 @@ sldg_status run_sweep(sldg_plan_s* p, int dim, const double* shift, uint32_t dep
   a.out_lo = out_lo;
   a.out_hi = out_hi;
   a.pmap = p->d_pmap;
+  a.n_lo = (int32_t)p->n_lo;
   a.wide_fp64 = p->ndouble > 1 ? 1 : 0;
   a.s_tab = p->d_s;
   a.ab_tab = p->d_ab;

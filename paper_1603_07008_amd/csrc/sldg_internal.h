@@ -52,6 +52,7 @@ struct SweepArgs {
   double* out_lo;
   void* out_hi;
   const int32_t* pmap;    // per mode id: >= 0 plane in hi, < 0 plane -1-v in lo
+  int32_t n_lo;           // planes in lo (kernels without extra FP64 modes: 0 or 1)
   int32_t wide_fp64;      // 1: more than the cell mean may be FP64 (general kernels)
   const int32_t* s_tab;   // per table entry: s mod N, in [0, N)
   const double* ab_tab;   // per table entry t: A then B, (k+1)^2 each, row-major,

@@ -192,6 +192,13 @@ struct TupleMap {
   int32_t nd;       // leading FP64 modes of the tuple
 };
 
+// Planes of the modes m0 + l * ms, l < O.  With at most the cell mean in
+// FP64 (NDMAX == 1: mode 0 in `lo` when n_lo == 1, mode m at hi plane
+// m - n_lo) the map is arithmetic and needs no memory access: a load here,
+// between the stores of one tuple and the loads of the next, would make the
+// wave wait for those stores (one counter covers all vector memory
+// operations).  Otherwise the plane map is read at a wave-uniform index.
+template <int NDMAX>
 __device__ __forceinline__ TupleMap tuple_map(const SweepArgs& a, int32_t m0, int32_t ms,
                                               int O) {
   TupleMap t;
@@ -199,10 +206,16 @@ __device__ __forceinline__ TupleMap tuple_map(const SweepArgs& a, int32_t m0, in
 #pragma unroll
   for (int l = 0; l < 4; ++l) {
     if (l < O) {
-      // uniform across the wave: keep it (and the plane pointers) scalar
-      const int32_t v = __builtin_amdgcn_readfirstlane(a.pmap[m0 + l * ms]);
-      t.idx[l] = v < 0 ? -1 - v : v;
-      t.nd += v < 0 ? 1 : 0;
+      const int32_t m = __builtin_amdgcn_readfirstlane(m0 + l * ms);
+      if constexpr (NDMAX == 1) {
+        const bool lo = m < a.n_lo;
+        t.idx[l] = lo ? m : m - a.n_lo;
+        t.nd += lo ? 1 : 0;
+      } else {
+        const int32_t v = __builtin_amdgcn_readfirstlane(a.pmap[m]);
+        t.idx[l] = v < 0 ? -1 - v : v;
+        t.nd += v < 0 ? 1 : 0;
+      }
     }
   }
   return t;
@@ -472,18 +485,35 @@ __device__ __forceinline__ void dispatch_nd(int nd, F&& f) {
 template <class T>
 struct Blk4 { T v[4]; };
 
+// An aligned 4-cell block as loaded (vector words), unpacked only when used,
+// so that a fetch does not make the wave wait for its data.
 template <class T>
-__device__ __forceinline__ Blk4<T> load4(const T* p) {
+struct Raw4 {
+  using V = typename std::conditional<
+      sizeof(T) == 8, double2,
+      typename std::conditional<sizeof(T) == 4, float4, uint2>::type>::type;
+  static constexpr int W = sizeof(T) == 8 ? 2 : 1;
+  V v[W];
+};
+
+template <class T>
+__device__ __forceinline__ Raw4<T> fetch4(const T* p) {
+  Raw4<T> r;
+  const auto* q = reinterpret_cast<const typename Raw4<T>::V*>(p);
+#pragma unroll
+  for (int i = 0; i < Raw4<T>::W; ++i) r.v[i] = q[i];
+  return r;
+}
+
+template <class T>
+__device__ __forceinline__ Blk4<T> unpack4(const Raw4<T>& w) {
   Blk4<T> r;
   if constexpr (sizeof(T) == 8) {
-    const double2* q = reinterpret_cast<const double2*>(p);
-    const double2 a = q[0], b = q[1];
-    r.v[0] = a.x; r.v[1] = a.y; r.v[2] = b.x; r.v[3] = b.y;
+    r.v[0] = w.v[0].x; r.v[1] = w.v[0].y; r.v[2] = w.v[1].x; r.v[3] = w.v[1].y;
   } else if constexpr (sizeof(T) == 4) {
-    const float4 a = *reinterpret_cast<const float4*>(p);
-    r.v[0] = a.x; r.v[1] = a.y; r.v[2] = a.z; r.v[3] = a.w;
+    r.v[0] = w.v[0].x; r.v[1] = w.v[0].y; r.v[2] = w.v[0].z; r.v[3] = w.v[0].w;
   } else {
-    const uint2 a = *reinterpret_cast<const uint2*>(p);
+    const uint2 a = w.v[0];
     r.v[0] = __builtin_bit_cast(T, (uint16_t)(a.x & 0xffff));
     r.v[1] = __builtin_bit_cast(T, (uint16_t)(a.x >> 16));
     r.v[2] = __builtin_bit_cast(T, (uint16_t)(a.y & 0xffff));
@@ -542,28 +572,74 @@ template <bool GROUP> struct Geo;
 template <> struct Geo<false> { int32_t blk0, blk1, d; };
 template <> struct Geo<true> { int32_t src[5]; int32_t n; };
 
+// The source cells of one tuple as loaded: two raw 4-cell blocks per plane
+// (window form) or 5 values per plane (group form).
 template <int K, int TIER, int ND, bool GROUP>
-__device__ __forceinline__ void contig_load(const Planes<K, TIER, ND>& pl, int64_t lb,
-                                            const Geo<GROUP>& g, Win<K, TIER, ND>& W) {
-  constexpr int O = K + 1;
+struct Fetched {
   using T = typename Tier<TIER>::T;
+  static constexpr int O = K + 1;
+  static constexpr int NV = GROUP ? 5 : 2;
+  typename std::conditional<GROUP, double, Raw4<double>>::type d[O][NV];   // l < ND
+  typename std::conditional<GROUP, T, Raw4<T>>::type h[O][NV];             // l >= ND
+};
+
+template <int K, int TIER, int ND, bool GROUP>
+__device__ __forceinline__ void contig_fetch(const Planes<K, TIER, ND>& pl, int64_t lb,
+                                             const Geo<GROUP>& g, Fetched<K, TIER, ND, GROUP>& F) {
+  constexpr int O = K + 1;
 #pragma unroll
   for (int l = 0; l < O; ++l) {
     if constexpr (GROUP) {           // one load per source cell
 #pragma unroll
       for (int u = 0; u < 5; ++u) {
-        if (l < ND) W.w[u].d[l] = pl.ind[l][lb + g.src[u]];
-        else W.w[u].h[l] = to_reg<TIER>(pl.inh[l][lb + g.src[u]], pl.fin[l]);
+        if (l < ND) F.d[l][u] = pl.ind[l][lb + g.src[u]];
+        else F.h[l][u] = pl.inh[l][lb + g.src[u]];
+      }
+    } else if (l < ND) {
+      F.d[l][0] = fetch4(pl.ind[l] + lb + 4 * g.blk0);
+      F.d[l][1] = fetch4(pl.ind[l] + lb + 4 * g.blk1);
+    } else {
+      F.h[l][0] = fetch4(pl.inh[l] + lb + 4 * g.blk0);
+      F.h[l][1] = fetch4(pl.inh[l] + lb + 4 * g.blk1);
+    }
+  }
+}
+
+template <int K, int TIER, int ND, bool GROUP>
+__device__ __forceinline__ void copy_fetched(Fetched<K, TIER, ND, GROUP>& dst,
+                                             const Fetched<K, TIER, ND, GROUP>& src) {
+#pragma unroll
+  for (int l = 0; l < K + 1; ++l)
+#pragma unroll
+    for (int u = 0; u < Fetched<K, TIER, ND, GROUP>::NV; ++u) {
+      if (l < ND) dst.d[l][u] = src.d[l][u];
+      else dst.h[l][u] = src.h[l][u];
+    }
+}
+
+// The 5-cell window of each plane from the fetched cells.
+template <int K, int TIER, int ND, bool GROUP>
+__device__ __forceinline__ void contig_select(const Planes<K, TIER, ND>& pl, const Geo<GROUP>& g,
+                                              const Fetched<K, TIER, ND, GROUP>& F,
+                                              Win<K, TIER, ND>& W) {
+  constexpr int O = K + 1;
+  using T = typename Tier<TIER>::T;
+#pragma unroll
+  for (int l = 0; l < O; ++l) {
+    if constexpr (GROUP) {
+#pragma unroll
+      for (int u = 0; u < 5; ++u) {
+        if (l < ND) W.w[u].d[l] = F.d[l][u];
+        else W.w[u].h[l] = to_reg<TIER>(F.h[l][u], pl.fin[l]);
       }
     } else if (l < ND) {
       double m[5];
-      window5<double>(load4(pl.ind[l] + lb + 4 * g.blk0), load4(pl.ind[l] + lb + 4 * g.blk1),
-                      g.d, m);
+      window5<double>(unpack4(F.d[l][0]), unpack4(F.d[l][1]), g.d, m);
 #pragma unroll
       for (int u = 0; u < 5; ++u) W.w[u].d[l] = m[u];
     } else {
       T h[5];
-      window5<T>(load4(pl.inh[l] + lb + 4 * g.blk0), load4(pl.inh[l] + lb + 4 * g.blk1), g.d, h);
+      window5<T>(unpack4(F.h[l][0]), unpack4(F.h[l][1]), g.d, h);
 #pragma unroll
       for (int u = 0; u < 5; ++u) W.w[u].h[l] = to_reg<TIER>(h[u], pl.fin[l]);
     }
@@ -619,8 +695,10 @@ __device__ __forceinline__ void contig_single(const SweepArgs& a, const TupleMap
   pl.bind(a, tm);
   Rows64<K, ND> R;
   R.load(M.ab, M.cs);
+  Fetched<K, TIER, ND, GROUP> F;
+  contig_fetch<K, TIER, ND, GROUP>(pl, lb, g, F);
   Win<K, TIER, ND> W;
-  contig_load<K, TIER, ND, GROUP>(pl, lb, g, W);
+  contig_select<K, TIER, ND, GROUP>(pl, g, F, W);
   contig_store<K, TIER, ND, GROUP>(a, pl, c, g, M, R, W, slot, active);
 }
 
@@ -659,7 +737,7 @@ __device__ __forceinline__ void contig_body(const SweepArgs& a, int32_t c, int32
   Mat<K, TIER> M;
   M.load(a.ab_tab + t, a.ab_cs);
   while (q < qe) {
-    TupleMap tm = tuple_map(a, q * O, 1, O);
+    TupleMap tm = tuple_map<NDMAX>(a, q * O, 1, O);
     if (tm.nd != 0) {
       dispatch_nd<NDMAX>(tm.nd, [&](auto ndc) {
         contig_single<K, TIER, decltype(ndc)::value, GROUP>(a, tm, M, lb, geo, c, slot, active);
@@ -667,28 +745,39 @@ __device__ __forceinline__ void contig_body(const SweepArgs& a, int32_t c, int32
       ++q;
       continue;
     }
-    Planes<K, TIER, 0> pc, pn;
+    // a run of tuples without FP64 modes: the next tuple's loads are issued
+    // before the current tuple is selected, computed and stored, and stay in
+    // flight until its turn
+    // Two register sets in turn (no copies: moving a register whose load is
+    // in flight would wait for it).
+    Planes<K, TIER, 0> pa, pb;
     Rows64<K, 0> R0;
-    pc.bind(a, tm);
-    Win<K, TIER, 0> cur, nxt;
-    contig_load<K, TIER, 0, GROUP>(pc, lb, geo, cur);
+    Fetched<K, TIER, 0, GROUP> fa, fb;
+    pa.bind(a, tm);
+    contig_fetch<K, TIER, 0, GROUP>(pa, lb, geo, fa);
+    // binds and fetches tuple qn if it exists and has no FP64 mode
+    auto next = [&](int32_t qn, Planes<K, TIER, 0>& p, Fetched<K, TIER, 0, GROUP>& f) {
+      if (qn >= qe) return false;
+      const TupleMap t1 = tuple_map<NDMAX>(a, qn * O, 1, O);
+      if (t1.nd != 0) return false;
+      p.bind(a, t1);
+      contig_fetch<K, TIER, 0, GROUP>(p, lb, geo, f);
+      return true;
+    };
+    auto process = [&](const Planes<K, TIER, 0>& p, const Fetched<K, TIER, 0, GROUP>& f) {
+      Win<K, TIER, 0> W;
+      contig_select<K, TIER, 0, GROUP>(p, geo, f, W);
+      contig_store<K, TIER, 0, GROUP>(a, p, c, geo, M, R0, W, slot, active);
+    };
     for (;;) {
-      const int32_t q1 = q + 1;
-      bool more = q1 < qe;
-      if (more) {
-        const TupleMap tm1 = tuple_map(a, q1 * O, 1, O);
-        more = tm1.nd == 0;
-        if (more) {
-          pn.bind(a, tm1);
-          contig_load<K, TIER, 0, GROUP>(pn, lb, geo, nxt);
-        }
-      }
-      contig_store<K, TIER, 0, GROUP>(a, pc, c, geo, M, R0, cur, slot, active);
-      q = q1;
-      if (!more) break;
-#pragma unroll
-      for (int u = 0; u < 5; ++u) copy_raw(cur.w[u], nxt.w[u]);
-      pc.copy_from(pn);
+      const bool mb = next(q + 1, pb, fb);
+      process(pa, fa);
+      ++q;
+      if (!mb) break;
+      const bool ma = next(q + 1, pa, fa);
+      process(pb, fb);
+      ++q;
+      if (!ma) break;
     }
   }
 }
@@ -893,7 +982,7 @@ __device__ __forceinline__ void strided_body(const SweepArgs& a, int32_t ilow, i
     }
   };
   while (q < qe) {
-    const TupleMap tm = tuple_map(a, m0, ms, O);
+    const TupleMap tm = tuple_map<NDMAX>(a, m0, ms, O);
     if (tm.nd != 0) {
       dispatch_nd<NDMAX>(tm.nd, [&](auto ndc) {
         strided_single<K, TIER, decltype(ndc)::value, L>(a, tm, M, base, roff, r0, n, slot,
@@ -902,31 +991,31 @@ __device__ __forceinline__ void strided_body(const SweepArgs& a, int32_t ilow, i
       advance(q, low, m0);
       continue;
     }
-    Planes<K, TIER, 0> pc, pn;
+    // Two register sets in turn (no copies: moving a register whose load is
+    // in flight would wait for it).
+    Planes<K, TIER, 0> pa, pb;
     Rows64<K, 0> R64;
-    pc.bind(a, tm);
-    Rows<K, TIER, 0, L> cur, nxt;
-    strided_load<K, TIER, 0, L>(pc, base, roff, cur);
+    Rows<K, TIER, 0, L> ra, rb;
+    pa.bind(a, tm);
+    strided_load<K, TIER, 0, L>(pa, base, roff, ra);
+    // the tuple after (q, low, m0): binds and loads it if it exists and has no
+    // FP64 mode; (q, low, m0) move on to it either way
+    auto next = [&](Planes<K, TIER, 0>& p, Rows<K, TIER, 0, L>& r) {
+      advance(q, low, m0);
+      if (q >= qe) return false;
+      const TupleMap t1 = tuple_map<NDMAX>(a, m0, ms, O);
+      if (t1.nd != 0) return false;
+      p.bind(a, t1);
+      strided_load<K, TIER, 0, L>(p, base, roff, r);
+      return true;
+    };
     for (;;) {
-      int32_t q1 = q, low1 = low, m1 = m0;
-      advance(q1, low1, m1);
-      bool more = q1 < qe;
-      if (more) {
-        const TupleMap tm1 = tuple_map(a, m1, ms, O);
-        more = tm1.nd == 0;
-        if (more) {
-          pn.bind(a, tm1);
-          strided_load<K, TIER, 0, L>(pn, base, roff, nxt);
-        }
-      }
-      strided_store<K, TIER, 0, L>(a, pc, base, r0, n, M, R64, cur, slot, active);
-      q = q1;
-      low = low1;
-      m0 = m1;
-      if (!more) break;
-#pragma unroll
-      for (int u = 0; u <= L; ++u) copy_raw(cur.v[u], nxt.v[u]);
-      pc.copy_from(pn);
+      const bool mb = next(pb, rb);
+      strided_store<K, TIER, 0, L>(a, pa, base, r0, n, M, R64, ra, slot, active);
+      if (!mb) break;
+      const bool ma = next(pa, ra);
+      strided_store<K, TIER, 0, L>(a, pb, base, r0, n, M, R64, rb, slot, active);
+      if (!ma) break;
     }
   }
 }
