@@ -1075,7 +1075,10 @@ __global__ __launch_bounds__(256) void sweep_strided_kernel(SweepArgs a) {
   }
   // the workgroup's waves: cw side by side along the columns, waves / cw
   // stacked along the row chunks
-  const int32_t waves = (int32_t)(blockDim.x >> 6), wave = (int32_t)(threadIdx.x >> 6);
+  // the wave index is uniform across the wave: said so, the row chunk and
+  // its length are scalar and the full-chunk test is a scalar branch
+  const int32_t waves = (int32_t)(blockDim.x >> 6);
+  const int32_t wave = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
   const int32_t cw = a.colwaves, zw = waves / cw;
   const int32_t wc = wave % cw, wz = wave / cw;
   const int32_t col = ((int32_t)bx * cw + wc) * 64 + (int32_t)(threadIdx.x & 63);
@@ -1199,7 +1202,8 @@ __global__ __launch_bounds__(256) void batch_class_kernel(const SweepArgs* __res
     contig_group_any<K, TIER, 1>(a, (int64_t)w.x * blockDim.x + threadIdx.x, q, qe, 0);
   } else {
     const int32_t col = w.x * 64 + (int32_t)(threadIdx.x & 63);
-    const int32_t chunk = w.z * (int32_t)(blockDim.x >> 6) + (int32_t)(threadIdx.x >> 6);
+    const int32_t chunk = w.z * (int32_t)(blockDim.x >> 6) +
+                          __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
     strided_cell<K, TIER, L, 1>(a, col, chunk, q, qe, 0);
   }
 }
