@@ -453,6 +453,69 @@ def run_sequence_scaled(scaled, ns, k, seq, steps=1, ndouble=1, headroom=SCALE_H
 
 
 # ---------------------------------------------------------------------------
+# Self-consistent field of a 1D-1V problem (x = dimension 0, v = dimension 1)
+#
+# The paper states the Vlasov equation with a given field E(x) (section II) and
+# no field equation.  Reading taken: Gauss's law of the normalised
+# Vlasov-Poisson system with a neutralising background, in the paper's sign
+# convention (+E d_v f): dE/dx = rho - mean(rho), E periodic with zero mean,
+# rho(x) = int f dv.  The v-sweep displacement of the line through x cell i is
+# E at the cell centre times dt / h_v (lines use their transverse cell centre).
+# ---------------------------------------------------------------------------
+
+def density_moments(state, ns, k, hv):
+    """rho in x cell i as a Legendre expansion: r[j, i] = h_v sum_iv c(i, iv;
+    mode (j, 0)) (only the j_v = 0 modes integrate to non-zero over a v cell)."""
+    nx, nv = ns
+    o = k + 1
+    st = np.asarray(state, dtype=np.float64)
+    r = np.empty((o, nx))
+    for j in range(o):
+        plane = st[j].reshape(nv, nx)                  # cell = i_x + nx * i_v
+        for i in range(nx):
+            r[j, i] = hv * math.fsum(plane[:, i].tolist())
+    return r
+
+
+def _half_cell_left_integral(j):
+    """int_{-1}^{0} P_j(xi) d xi, exactly."""
+    p = legendre_monomial(j)
+    acc = Fraction(0)
+    for e, c in enumerate(p):
+        acc += c * (Fraction(0) - Fraction((-1) ** (e + 1), e + 1))
+    return acc
+
+
+def poisson_field(state, ns, k, hx, hv):
+    """E at the x cell centres, from dE/dx = rho - mean(rho), zero mean.
+    Steps: the density moments; the mean density; the face values of the
+    antiderivative of rho - mean(rho) (starting at 0); the cell means of that
+    antiderivative; the constant that makes the mean zero; the centre values."""
+    nx = ns[0]
+    r = density_moments(state, ns, k, hv)
+    rbar = math.fsum(r[0].tolist()) / nx
+    faces = np.empty(nx + 1)
+    faces[0] = 0.0
+    for i in range(nx):
+        faces[i + 1] = faces[i] + hx * (r[0, i] - rbar)
+    # cell mean of the antiderivative: (1/h) int_cell F = F_i + h/2 (r0 - rbar) - h/6 r1
+    means = [faces[i] + 0.5 * hx * (r[0, i] - rbar) - (hx / 6.0 * r[1, i] if k >= 1 else 0.0)
+             for i in range(nx)]
+    C = -math.fsum(means) / nx
+    half = [float(_half_cell_left_integral(j)) for j in range(k + 1)]
+    out = np.empty(nx)
+    for i in range(nx):
+        g = (r[0, i] - rbar) * half[0] + math.fsum(r[j, i] * half[j] for j in range(1, k + 1))
+        out[i] = faces[i] + C + 0.5 * hx * g
+    return out
+
+
+def poisson_shift(state, ns, k, hx, hv, dt):
+    """The v-sweep displacement (cells) per x line: E(x_i) dt / h_v."""
+    return poisson_field(state, ns, k, hx, hv) * dt / hv
+
+
+# ---------------------------------------------------------------------------
 # Initial projection, eq. (cj)
 # ---------------------------------------------------------------------------
 
