@@ -284,6 +284,41 @@ sldg_status sldg_split_steps_scaled(sldg_plan_t plan, const sldg_sweep_desc* seq
                                     int* result_buffer);
 
 /*
+ * Self-consistent field of an (x, v) problem (ndim = 2; dimension 0 is x,
+ * dimension 1 is v), for the v-sweep of the split step.  The paper states the
+ * Vlasov equation with a field E(x) (section II) but no field equation; the
+ * one taken is Gauss's law of the normalised Vlasov-Poisson system in the
+ * paper's sign convention (+E d_v f): dE/dx = rho - mean(rho), E periodic
+ * with zero mean, rho(x) = int f dv.  rho is exact for the piecewise
+ * polynomial state (in x cell i its Legendre moments are h_v times the sums
+ * over the v cells of the modes (j, 0)); E is its zero-mean antiderivative,
+ * evaluated at the x cell centres.
+ *   mass, hi    the state (device; the plan's layout and tier, unscaled)
+ *   hx, hv      cell widths in x and v
+ *   dt          time step of the v-sweep
+ *   shift_out   device double [N_x]: E(x_i) * dt / hv, the displacement of the
+ *               v-sweep line through x cell i (use dep_mask = 1)
+ *   field_out   optional device double [N_x]: E(x_i)
+ * Asynchronous on the plan's stream.  Grows a plan-owned scratch buffer
+ * (hipMalloc) on the first call that needs more.  Errors: SLDG_ERR_ARG,
+ * SLDG_ERR_ALIAS, SLDG_ERR_NOMEM, SLDG_ERR_DEVICE.
+ */
+sldg_status sldg_poisson_shift(sldg_plan_t plan, const double* mass, const void* hi, double hx,
+                               double hv, double dt, double* shift_out, double* field_out);
+
+/*
+ * nsteps self-consistent Strang steps of an (x, v) plan: X(dt/2) with the
+ * displacements shift_x (device [N_v], per v line, dep_mask = 2), the field of
+ * the state into shift_v (device [N_x], overwritten), V(dt) with shift_v,
+ * X(dt/2).  Buffers as in sldg_split_steps; *result_buffer receives the buffer
+ * holding the result.  Asynchronous on the plan's stream.
+ */
+sldg_status sldg_vlasov_poisson_steps(sldg_plan_t plan, int nsteps, const double* shift_x,
+                                      double hx, double hv, double dt, double* shift_v,
+                                      double* mass0, void* hi0, double* mass1, void* hi1,
+                                      int* result_buffer);
+
+/*
  * Kernel timing.  While enabled, every sweep kernel launch of the plan is
  * bracketed by a pair of HIP events recorded on the plan's stream (the line
  * table kernel is outside the pair), up to 4096 launches after enabling.

@@ -26,7 +26,8 @@ EXPORTS = ("sldg_plan", "sldg_plan_destroy", "sldg_plan_set_stream", "sldg_line_
            "sldg_scale_bytes", "sldg_set_scale_headroom", "sldg_scaled_import",
            "sldg_scaled_export", "sldg_advect_dim_scaled", "sldg_split_steps_scaled",
            "sldg_plan_set_shape", "sldg_plan_get_shape", "sldg_tune_candidate", "sldg_plan_tune",
-           "sldg_device_plane_copy", "sldg_batch_get_class_tuning", "sldg_batch_set_class_tuning")
+           "sldg_device_plane_copy", "sldg_batch_get_class_tuning", "sldg_batch_set_class_tuning",
+           "sldg_poisson_shift", "sldg_vlasov_poisson_steps")
 
 
 class SldgError(RuntimeError):
@@ -112,6 +113,12 @@ def lib():
     L.sldg_plan_tune.argtypes = [vp, ctypes.POINTER(SweepDesc), i32, vp, vp, vp, vp, i32,
                                  ctypes.POINTER(ctypes.c_double)]
     L.sldg_plan_tune.restype = i32
+    dbl = ctypes.c_double
+    L.sldg_poisson_shift.argtypes = [vp, vp, vp, dbl, dbl, dbl, vp, vp]
+    L.sldg_poisson_shift.restype = i32
+    L.sldg_vlasov_poisson_steps.argtypes = [vp, i32, vp, dbl, dbl, dbl, vp, vp, vp, vp, vp,
+                                            ctypes.POINTER(i32)]
+    L.sldg_vlasov_poisson_steps.restype = i32
     L.sldg_status_string.argtypes = [i32]
     L.sldg_status_string.restype = ctypes.c_char_p
     L.sldg_last_error.argtypes = []
@@ -282,6 +289,45 @@ class Plan:
         _check(lib().sldg_split_steps(self.handle, descs, len(seq), int(nsteps),
                                       _ptr(state0[0]), _ptr(state0[1]), _ptr(state1[0]),
                                       _ptr(state1[1]), ctypes.byref(res)), "sldg_split_steps")
+        return res.value
+
+    # --- self-consistent field of (x, v) problems ---------------------------
+
+    def poisson_shift(self, mass, hi, hx, hv, dt, shift_out=None, field_out=None):
+        """The v-sweep displacements E(x_i) dt / hv of the state's field
+        (sldg_poisson_shift); returns shift_out (device float64 [N_x])."""
+        import torch
+        self._check_state(mass, hi, "poisson_shift")
+        nx = self.ncells[0]
+        if shift_out is None:
+            shift_out = torch.empty(nx, dtype=torch.float64, device=mass.device)
+        for t, nm in ((shift_out, "shift_out"), (field_out, "field_out")):
+            if t is not None and (not t.is_cuda or t.dtype != torch.float64 or
+                                  not t.is_contiguous() or t.numel() < nx):
+                raise ValueError(f"poisson_shift: {nm} must be a contiguous float64 device "
+                                 f"tensor of >= {nx} elements")
+        _check(lib().sldg_poisson_shift(self.handle, _ptr(mass), _ptr(hi), float(hx), float(hv),
+                                        float(dt), _ptr(shift_out),
+                                        None if field_out is None else _ptr(field_out)),
+               "sldg_poisson_shift")
+        return shift_out
+
+    def vlasov_poisson_steps(self, nsteps, shift_x, hx, hv, dt, state0, state1, shift_v=None):
+        """nsteps self-consistent Strang steps (sldg_vlasov_poisson_steps);
+        returns the index (0 or 1) of the state holding the result."""
+        import torch
+        self._check_shift(shift_x, 2, "vlasov_poisson_steps")
+        self._check_state(*state0, "vlasov_poisson_steps state0")
+        self._check_state(*state1, "vlasov_poisson_steps state1")
+        if shift_v is None:
+            shift_v = torch.empty(self.ncells[0], dtype=torch.float64, device=state0[0].device)
+        self._check_shift(shift_v, 1, "vlasov_poisson_steps")
+        res = ctypes.c_int(-1)
+        _check(lib().sldg_vlasov_poisson_steps(self.handle, int(nsteps), _ptr(shift_x), float(hx),
+                                               float(hv), float(dt), _ptr(shift_v),
+                                               _ptr(state0[0]), _ptr(state0[1]),
+                                               _ptr(state1[0]), _ptr(state1[1]),
+                                               ctypes.byref(res)), "sldg_vlasov_poisson_steps")
         return res.value
 
     # --- launch shapes and the autotuner -----------------------------------

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -15,6 +16,7 @@
 #include "sldg.h"
 #include "sldg_internal.h"
 #include "sldg_ref.h"
+#include "sldg_field.h"
 
 using namespace sldg;
 
@@ -52,6 +54,8 @@ struct sldg_plan_s {
   int32_t* d_redo;        // [n_hi] planes to recompute after a scaled sweep
   float* d_part;          // absmax partials, grown on demand
   int64_t part_cap;       // floats in d_part
+  double* d_field;        // scratch of the field solve, grown on demand
+  int64_t field_cap;      // doubles in d_field
   // kernel timing (sldg_timing_*)
   bool timing;
   int ntimed;
@@ -226,6 +230,7 @@ void free_plan(sldg_plan_s* p) {
   if (p->d_hmode) (void)hipFree(p->d_hmode);
   if (p->d_redo) (void)hipFree(p->d_redo);
   if (p->d_part) (void)hipFree(p->d_part);
+  if (p->d_field) (void)hipFree(p->d_field);
   if (p->h_mass_out) (void)hipHostFree(p->h_mass_out);
   delete p;
 }
@@ -235,6 +240,7 @@ void free_plan(sldg_plan_s* p) {
 sldg_status ensure_part(sldg_plan_s* p, int64_t n) {
   if (n <= p->part_cap) return SLDG_OK;
   if (p->d_part) (void)hipFree(p->d_part);
+  if (p->d_field) (void)hipFree(p->d_field);
   p->d_part = nullptr;
   p->part_cap = 0;
   hipError_t e = hipMalloc(&p->d_part, sizeof(float) * (size_t)n);
@@ -807,6 +813,91 @@ sldg_status sldg_device_copy(const void* src, void* dst, int64_t bytes, void* st
   if (overlap(src, bytes, dst, bytes)) return fail(SLDG_ERR_ALIAS, "copy buffers overlap");
   hipError_t e = launch_copy16(src, dst, bytes / 16, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return device_error(e, "copy launch");
+  return ok();
+}
+
+sldg_status sldg_poisson_shift(sldg_plan_t p, const double* mass, const void* hi, double hx,
+                               double hv, double dt, double* shift_out, double* field_out) {
+  if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
+  if (p->ndim != 2) return fail(SLDG_ERR_ARG, "the field solve needs an (x, v) plan (ndim = 2)");
+  if (!(hx > 0.0) || !(hv > 0.0) || !std::isfinite(dt))
+    return fail(SLDG_ERR_ARG, "hx, hv must be > 0 and dt finite");
+  if (!shift_out) return fail(SLDG_ERR_ARG, "null shift_out");
+  if (p->n_lo > 0 && !mass) return fail(SLDG_ERR_ARG, "null mass");
+  if (p->n_hi > 0 && !hi) return fail(SLDG_ERR_ARG, "null hi");
+  const int32_t nx = (int32_t)p->n[0], nv = (int32_t)p->n[1];
+  const int64_t ob = 8LL * nx;
+  const void* outs[2] = {shift_out, field_out};
+  for (int i = 0; i < 2; ++i) {
+    if (!outs[i]) continue;
+    if ((p->lo_bytes > 0 && overlap(outs[i], ob, mass, p->lo_bytes)) ||
+        (p->hi_bytes > 0 && overlap(outs[i], ob, hi, p->hi_bytes)))
+      return fail(SLDG_ERR_ALIAS, "field output overlaps the state");
+  }
+  if (field_out && overlap(shift_out, ob, field_out, ob))
+    return fail(SLDG_ERR_ALIAS, "shift_out overlaps field_out");
+  // planes of the modes (j, 0): mode id j
+  FieldPlanes fp{};
+  for (int j = 0; j < p->o; ++j) {
+    const int32_t v = p->h_pmap[j];
+    fp.lo[j] = v < 0 ? 1 : 0;
+    fp.plane[j] = v < 0 ? static_cast<const void*>(mass + (int64_t)(-1 - v) * p->cells)
+                        : static_cast<const void*>(static_cast<const char*>(hi) +
+                                                   (int64_t)v * p->cells * elem_size(p->tier));
+  }
+  const int64_t need = field_scratch_doubles(p->o, nx, nv);
+  if (need > p->field_cap) {
+    if (p->d_field) (void)hipFree(p->d_field);
+    p->d_field = nullptr;
+    p->field_cap = 0;
+    hipError_t e = hipMalloc(&p->d_field, sizeof(double) * (size_t)need);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SLDG_ERR_NOMEM, "field scratch: %s", hipGetErrorString(e));
+    }
+    p->field_cap = need;
+  }
+  hipError_t e = launch_field((int)p->tier, fp, p->o, nx, nv, hx, hv, dt, p->d_field, shift_out,
+                              field_out, p->stream);
+  if (e != hipSuccess) return device_error(e, "field launch");
+  return ok();
+}
+
+sldg_status sldg_vlasov_poisson_steps(sldg_plan_t p, int nsteps, const double* shift_x, double hx,
+                                      double hv, double dt, double* shift_v, double* mass0,
+                                      void* hi0, double* mass1, void* hi1, int* result_buffer) {
+  if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
+  if (p->ndim != 2) return fail(SLDG_ERR_ARG, "Vlasov-Poisson steps need an (x, v) plan");
+  if (nsteps < 0) return fail(SLDG_ERR_ARG, "nsteps %d < 0", nsteps);
+  if (!shift_x || !shift_v) return fail(SLDG_ERR_ARG, "null shift pointer");
+  double* m[2] = {mass0, mass1};
+  void* h[2] = {hi0, hi1};
+  for (int b = 0; b < 2; ++b) {
+    sldg_status st = check_sweep(p, 0, shift_x, 2u, m[b], h[b], m[1 - b], h[1 - b]);
+    if (st == SLDG_OK) st = check_sweep(p, 1, shift_v, 1u, m[b], h[b], m[1 - b], h[1 - b]);
+    if (st != SLDG_OK) return st;
+  }
+  const int64_t ob = 8 * p->n[0];
+  for (int b = 0; b < 2; ++b)
+    if ((p->lo_bytes > 0 && overlap(shift_v, ob, m[b], p->lo_bytes)) ||
+        (p->hi_bytes > 0 && overlap(shift_v, ob, h[b], p->hi_bytes)))
+      return fail(SLDG_ERR_ALIAS, "shift_v overlaps a state buffer");
+  int cur = 0;
+  for (int n = 0; n < nsteps; ++n) {
+    // X(dt/2), field from the state, V(dt), X(dt/2)
+    sldg_status st = run_sweep(p, 0, shift_x, 2u, m[cur], h[cur], m[1 - cur], h[1 - cur]);
+    if (st != SLDG_OK) return st;
+    cur = 1 - cur;
+    st = sldg_poisson_shift(p, m[cur], h[cur], hx, hv, dt, shift_v, nullptr);
+    if (st != SLDG_OK) return st;
+    st = run_sweep(p, 1, shift_v, 1u, m[cur], h[cur], m[1 - cur], h[1 - cur]);
+    if (st != SLDG_OK) return st;
+    cur = 1 - cur;
+    st = run_sweep(p, 0, shift_x, 2u, m[cur], h[cur], m[1 - cur], h[1 - cur]);
+    if (st != SLDG_OK) return st;
+    cur = 1 - cur;
+  }
+  if (result_buffer) *result_buffer = cur;
   return ok();
 }
 

@@ -1,0 +1,124 @@
+"""GPU parity of the self-consistent field of (x, v) problems
+(sldg_poisson_shift, sldg_vlasov_poisson_steps) against the oracle's
+poisson_field and its Strang loop, on the same seeded inputs, and the
+linear Landau damping of the GPU run."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import sldg_oracle as O
+from paper_1603_07008_amd import inputs
+from gpu_helpers import download, download_nd, have_gpu, upload, upload_nd, weighted_rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sl():
+    if not have_gpu():
+        pytest.skip("no HIP device")
+    import paper_1603_07008_amd as sl
+    sl.lib()
+    return sl
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def _landau(nx, nv, k, kappa=0.5, eps=0.01, dt=0.1):
+    L = 2 * math.pi / kappa
+    ns, los, his = (nx, nv), (0.0, -6.0), (L, 6.0)
+    st = O.project_separable([(lambda x: 1 + eps * np.cos(kappa * x), inputs.maxwellian)],
+                             ns, los, his, k)
+    hx, hv = L / nx, 12.0 / nv
+    sx = (-6.0 + (np.arange(nv) + 0.5) * hv) * (0.5 * dt) / hx
+    return st, ns, hx, hv, sx
+
+
+CASES = [((48, 40), 2, 1), ((33, 17), 1, 1), ((64, 50), 3, 1), ((40, 24), 2, 2)]
+
+
+@pytest.mark.parametrize("ns,k,ndouble", CASES)
+@pytest.mark.parametrize("tier", ["fp64", "fp32", "bf16"])
+def test_field_matches_oracle(sl, ns, k, ndouble, tier):
+    import torch
+    st = inputs.random_coefficients(2, k, ns[0] * ns[1], seed=ns[0] + k)
+    st = O.to_tier(st, tier, ndouble, k, 2)
+    hx, hv, dt = 0.37, 0.21, 0.1
+    plan = sl.Plan(ns, k, tier, ndouble=ndouble)
+    m, h = upload_nd(st, plan)
+    field = torch.empty(ns[0], dtype=torch.float64, device="cuda")
+    shift = plan.poisson_shift(m, h, hx, hv, dt, field_out=field)
+    want = O.poisson_field(st, ns, k, hx, hv)
+    got = field.cpu().numpy()
+    scale = float(np.max(np.abs(want)))
+    assert np.max(np.abs(got - want)) <= 1e-12 * scale, np.max(np.abs(got - want)) / scale
+    assert np.allclose(shift.cpu().numpy(), got * dt / hv, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("tier,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+def test_self_consistent_steps_match_oracle(sl, tier, tol):
+    nsteps = 12
+    st0, ns, hx, hv, sx = _landau(32, 48, 2)
+    st0 = O.to_tier(st0, tier)
+    dt = 0.1
+    cur = st0
+    for _ in range(nsteps):
+        cur = O.sweep(cur, ns, 2, 0, sx, (1,), tier)
+        cur = O.sweep(cur, ns, 2, 1, O.poisson_shift(cur, ns, 2, hx, hv, dt), (0,), tier)
+        cur = O.sweep(cur, ns, 2, 0, sx, (1,), tier)
+    plan = sl.Plan(ns, 2, tier)
+    s0 = upload(st0, tier)
+    s1 = plan.empty_state()
+    res = plan.vlasov_poisson_steps(nsteps, _dev(sx), hx, hv, dt, s0, s1)
+    got = download(*(s0, s1)[res])
+    assert weighted_rel_l2(got, cur, 2, 2) <= tol
+    m0 = O.mass_sum(st0[0])
+    assert abs(O.mass_sum(got[0]) - m0) <= 1e-14 * abs(m0)
+
+
+def test_landau_damping_on_the_gpu(sl):
+    import torch
+    nx, nv, k, dt = 64, 128, 2, 0.1
+    st0, ns, hx, hv, sx = _landau(nx, nv, k)
+    plan = sl.Plan(ns, k, "fp32")
+    bufs = [upload(O.to_tier(st0, "fp32"), "fp32"), plan.empty_state()]
+    shift_x = _dev(sx)
+    shift_v = torch.empty(nx, dtype=torch.float64, device="cuda")
+    field = torch.empty(nx, dtype=torch.float64, device="cuda")
+    cur = 0
+    log_e = []
+    for _ in range(230):
+        plan.poisson_shift(*bufs[cur], hx, hv, dt, shift_v, field)
+        log_e.append(0.5 * math.log(float(torch.sum(field * field)) * hx))
+        res = plan.vlasov_poisson_steps(1, shift_x, hx, hv, dt, bufs[cur], bufs[1 - cur], shift_v)
+        cur = cur if res == 0 else 1 - cur
+    ts = np.arange(len(log_e)) * dt
+    le = np.array(log_e)
+    peaks = [i for i in range(1, len(ts) - 1)
+             if le[i] > le[i - 1] and le[i] > le[i + 1] and 1.0 < ts[i] < 22.0]
+    gamma = np.polyfit(ts[peaks], le[peaks], 1)[0]
+    omega = math.pi / float(np.mean(np.diff(ts[peaks])))
+    assert abs(gamma + 0.1533) < 0.03 * 0.1533, gamma
+    assert abs(omega - 1.4156) < 0.03 * 1.4156, omega
+
+
+def test_field_entry_points_reject_bad_arguments(sl):
+    import torch
+    p3 = sl.Plan((8, 6, 4), 1, "fp64")
+    m, h = p3.empty_state()
+    out = torch.empty(8, dtype=torch.float64, device="cuda")
+    with pytest.raises(sl.SldgError) as ei:
+        p3.poisson_shift(m, h, 0.1, 0.1, 0.1, out)
+    assert ei.value.status == sl.SLDG_ERR_ARG
+    p2 = sl.Plan((8, 6), 1, "fp64")
+    m, h = p2.empty_state()
+    with pytest.raises(sl.SldgError) as ei:
+        p2.poisson_shift(m, h, 0.1, 0.1, 0.1, m)          # output over the state
+    assert ei.value.status == sl.SLDG_ERR_ALIAS
+    with pytest.raises(sl.SldgError) as ei:
+        p2.poisson_shift(m, h, -1.0, 0.1, 0.1)
+    assert ei.value.status == sl.SLDG_ERR_ARG
