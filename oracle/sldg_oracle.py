@@ -453,6 +453,61 @@ def run_sequence_scaled(scaled, ns, k, seq, steps=1, ndouble=1, headroom=SCALE_H
 
 
 # ---------------------------------------------------------------------------
+# Transverse Gauss-node collocation
+#
+# With the displacement of a sweep along d depending on a transverse
+# coordinate y (dimension t), the cell-centre sweep gives every line of a
+# transverse cell the displacement at the cell centre (section II-A applied
+# line by line).  The collocated sweep instead takes the state at the o
+# Gauss-Legendre nodes y_q of the transverse cell (modal -> nodal in j_t),
+# sweeps each node line with its own displacement sigma(y_q) (the update rule
+# of section II-A, unchanged), and projects back onto the Legendre modes in
+# y with the Gauss weights (nodal -> modal, eq. (cj) with the o-point rule).
+# ---------------------------------------------------------------------------
+
+def sweep_collocated(state, ns, k, dim, tdim, node_sigma, tier="fp64", ndouble=1):
+    """One collocated sweep along `dim`, nodes in `tdim`.
+    node_sigma: displacement in cells [N_tdim, o] (transverse cell, node)."""
+    ns = [int(v) for v in ns]
+    ndim = len(ns)
+    o = k + 1
+    if dim == tdim:
+        raise ValueError("the transverse dimension must differ from the swept one")
+    sig = np.asarray(node_sigma, dtype=np.float64).reshape(ns[tdim], o)
+    st = np.asarray(state, dtype=np.float64)
+    shape = [o] * ndim + ns[::-1]
+    X = st.reshape(shape)
+    jax = lambda e: ndim - 1 - e              # mode axis of dimension e
+    iax = lambda e: 2 * ndim - 1 - e          # cell axis of dimension e
+    xi, w = gauss_legendre(o)
+    P = legendre_values(k, xi)                # [j, q]
+    out = np.zeros_like(X)
+    N = ns[dim]
+    for q in range(o):
+        nod = np.tensordot(P[:, q], X, axes=([0], [jax(tdim)]))        # j_t removed
+        # axes of nod: modes without t (in order), then the cells
+        jd = jax(dim) - (1 if jax(tdim) < jax(dim) else 0)
+        it, idd = iax(tdim) - 1, iax(dim) - 1
+        Y = np.moveaxis(nod, (jd, it, idd), (0, 1, -1))             # [j_d, N_t, ..., N_d]
+        Z = np.empty_like(Y)
+        s_tab, ab_tab = line_tables(sig[:, q], k)
+        for i_t in range(ns[tdim]):
+            s = int(s_tab[i_t])
+            A, B = ab_tab[i_t, 0], ab_tab[i_t, 1]
+            src = np.arange(N)
+            ya = Y[:, i_t][..., (src - s) % N]
+            yb = Y[:, i_t][..., (src - s - 1) % N]
+            Z[:, i_t] = np.tensordot(A, ya, axes=([1], [0])) + np.tensordot(B, yb, axes=([1], [0]))
+        back = np.moveaxis(Z, (0, 1, -1), (jd, it, idd))
+        for jt in range(o):
+            sl = [slice(None)] * (2 * ndim)
+            sl[jax(tdim)] = jt
+            out[tuple(sl)] += 0.5 * (2 * jt + 1) * w[q] * P[jt, q] * back
+    res = out.reshape(st.shape)
+    return to_tier(res, tier, ndouble, k, ndim) if tier != "fp64" else res
+
+
+# ---------------------------------------------------------------------------
 # Self-consistent field of a 1D-1V problem (x = dimension 0, v = dimension 1)
 #
 # The paper states the Vlasov equation with a given field E(x) (section II) and
