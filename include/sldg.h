@@ -284,6 +284,27 @@ sldg_status sldg_split_steps_scaled(sldg_plan_t plan, const sldg_sweep_desc* seq
                                     int* result_buffer);
 
 /*
+ * Sweep along `dim` with transverse Gauss-node collocation in `tdim`.  The
+ * displacement varies across the cells of tdim; instead of one value per
+ * transverse cell (sldg_advect_dim), the state is taken at the k+1
+ * Gauss-Legendre nodes y_q of each transverse cell (modal -> nodal in j_tdim),
+ * each node line is swept with its own displacement (section II-A update rule,
+ * unchanged), and the result is projected back onto the Legendre modes in
+ * tdim with the Gauss weights (eq. (cj) with the (k+1)-point rule).  Other
+ * mode indices are spectators.  The total mass is conserved (the rule
+ * integrates P_0 exactly).
+ *   node_shift  device double [N_tdim * (k+1)]: displacement in cells of
+ *               node q (ascending in y) of transverse cell i at [i*(k+1) + q]
+ *   buffers as in sldg_advect_dim
+ * All arithmetic is FP64; narrow modes are rounded to nearest even on store.
+ * Asynchronous on the plan's stream.  Errors: SLDG_ERR_ARG, SLDG_ERR_ALIAS,
+ * SLDG_ERR_UNSUPPORTED, SLDG_ERR_DEVICE.
+ */
+sldg_status sldg_advect_dim_collocated(sldg_plan_t plan, int dim, int tdim,
+                                       const double* node_shift, const double* in_mass,
+                                       const void* in_hi, double* out_mass, void* out_hi);
+
+/*
  * Self-consistent field of an (x, v) problem (ndim = 2; dimension 0 is x,
  * dimension 1 is v), for the v-sweep of the split step.  The paper states the
  * Vlasov equation with a field E(x) (section II) but no field equation; the

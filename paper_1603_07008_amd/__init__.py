@@ -27,7 +27,7 @@ EXPORTS = ("sldg_plan", "sldg_plan_destroy", "sldg_plan_set_stream", "sldg_line_
            "sldg_scaled_export", "sldg_advect_dim_scaled", "sldg_split_steps_scaled",
            "sldg_plan_set_shape", "sldg_plan_get_shape", "sldg_tune_candidate", "sldg_plan_tune",
            "sldg_device_plane_copy", "sldg_batch_get_class_tuning", "sldg_batch_set_class_tuning",
-           "sldg_poisson_shift", "sldg_vlasov_poisson_steps")
+           "sldg_poisson_shift", "sldg_vlasov_poisson_steps", "sldg_advect_dim_collocated")
 
 
 class SldgError(RuntimeError):
@@ -114,6 +114,8 @@ def lib():
                                  ctypes.POINTER(ctypes.c_double)]
     L.sldg_plan_tune.restype = i32
     dbl = ctypes.c_double
+    L.sldg_advect_dim_collocated.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
+    L.sldg_advect_dim_collocated.restype = i32
     L.sldg_poisson_shift.argtypes = [vp, vp, vp, dbl, dbl, dbl, vp, vp]
     L.sldg_poisson_shift.restype = i32
     L.sldg_vlasov_poisson_steps.argtypes = [vp, i32, vp, dbl, dbl, dbl, vp, vp, vp, vp, vp,
@@ -290,6 +292,23 @@ class Plan:
                                       _ptr(state0[0]), _ptr(state0[1]), _ptr(state1[0]),
                                       _ptr(state1[1]), ctypes.byref(res)), "sldg_split_steps")
         return res.value
+
+    def advect_dim_collocated(self, dim, tdim, node_shift, in_mass, in_hi, out_mass, out_hi):
+        """Sweep along `dim` with Gauss-node collocation in `tdim`
+        (sldg_advect_dim_collocated); node_shift: float64 device
+        [N_tdim * (k+1)], node fastest."""
+        import torch
+        need = self.ncells[tdim] * (self.k + 1)
+        if not isinstance(node_shift, torch.Tensor) or not node_shift.is_cuda or \
+                node_shift.dtype != torch.float64 or not node_shift.is_contiguous() or \
+                node_shift.numel() < need:
+            raise ValueError(f"advect_dim_collocated: node_shift must be a contiguous float64 "
+                             f"device tensor of >= {need} elements")
+        self._check_state(in_mass, in_hi, "advect_dim_collocated input")
+        self._check_state(out_mass, out_hi, "advect_dim_collocated output")
+        _check(lib().sldg_advect_dim_collocated(self.handle, int(dim), int(tdim), _ptr(node_shift),
+                                                _ptr(in_mass), _ptr(in_hi), _ptr(out_mass),
+                                                _ptr(out_hi)), "sldg_advect_dim_collocated")
 
     # --- self-consistent field of (x, v) problems ---------------------------
 

@@ -8,9 +8,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsldg.so")
 SOURCES = [os.path.join(CSRC, f) for f in ("sldg_host.hip", "sldg_batch.hip", "sldg_kernels.hip",
-                                          "sldg_ref.hip", "sldg_field.hip")]
+                                          "sldg_ref.hip", "sldg_field.hip", "sldg_colloc.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("sldg_internal.h", "ab_poly.h", "sldg_ref.h",
-                                          "sldg_field.h")] + \
+                                          "sldg_field.h", "sldg_colloc.h")] + \
     [os.path.join(ROOT, "include", "sldg.h")]
 ARCH = os.environ.get("SLDG_OFFLOAD_ARCH", "gfx950")
 

@@ -17,6 +17,7 @@
 #include "sldg_internal.h"
 #include "sldg_ref.h"
 #include "sldg_field.h"
+#include "sldg_colloc.h"
 
 using namespace sldg;
 
@@ -422,7 +423,11 @@ sldg_status sldg_plan_ex(sldg_plan_t* out, int ndim, const int64_t* ncells, int 
   }
   p->lo_bytes = p->n_lo * cells * 8;
   p->hi_bytes = p->n_hi * cells * elem_size(tier);
-  p->table_cap = cells / min_n;     // the most lines any sweep can have
+  // the most lines any sweep can have, and the (transverse cell, node) entries
+  // of a collocated sweep
+  int64_t max_n = 0;
+  for (int e = 0; e < ndim; ++e) max_n = std::max<int64_t>(max_n, ncells[e]);
+  p->table_cap = std::max<int64_t>(cells / min_n, (int64_t)(k + 1) * max_n);
   // default launch shape (measured on MI355X for the 4D k = 2 workload; the
   // tuner picks per dimension), overridable from the environment
   int rows = 4, tuples = 9, colwaves = 1;
@@ -813,6 +818,100 @@ sldg_status sldg_device_copy(const void* src, void* dst, int64_t bytes, void* st
   if (overlap(src, bytes, dst, bytes)) return fail(SLDG_ERR_ALIAS, "copy buffers overlap");
   hipError_t e = launch_copy16(src, dst, bytes / 16, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return device_error(e, "copy launch");
+  return ok();
+}
+
+namespace {
+
+// Gauss-Legendre nodes (ascending) and weights of the o-point rule, o = 2..4,
+// from their closed forms.
+void gauss_rule(int o, double* x, double* w) {
+  if (o == 2) {
+    const double a = 1.0 / std::sqrt(3.0);
+    x[0] = -a; x[1] = a;
+    w[0] = w[1] = 1.0;
+  } else if (o == 3) {
+    const double a = std::sqrt(0.6);
+    x[0] = -a; x[1] = 0.0; x[2] = a;
+    w[0] = w[2] = 5.0 / 9.0;
+    w[1] = 8.0 / 9.0;
+  } else {
+    const double r = 2.0 / 7.0 * std::sqrt(6.0 / 5.0);
+    const double outer = std::sqrt(3.0 / 7.0 + r), inner = std::sqrt(3.0 / 7.0 - r);
+    const double wo = (18.0 - std::sqrt(30.0)) / 36.0, wi = (18.0 + std::sqrt(30.0)) / 36.0;
+    x[0] = -outer; x[1] = -inner; x[2] = inner; x[3] = outer;
+    w[0] = w[3] = wo;
+    w[1] = w[2] = wi;
+  }
+}
+
+}  // namespace
+
+sldg_status sldg_advect_dim_collocated(sldg_plan_t p, int dim, int tdim, const double* node_shift,
+                                       const double* in_mass, const void* in_hi,
+                                       double* out_mass, void* out_hi) {
+  if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
+  if (tdim < 0 || tdim >= p->ndim || tdim == dim)
+    return fail(SLDG_ERR_ARG, "transverse dim %d invalid for the sweep along %d", tdim, dim);
+  sldg_status st = check_sweep(p, dim, node_shift, 1u << tdim, in_mass, in_hi, out_mass, out_hi);
+  if (st != SLDG_OK) return st;
+  const int o = p->o;
+  const int64_t nent = p->n[tdim] * o;
+  if ((p->lo_bytes > 0 && overlap(node_shift, 8 * nent, out_mass, p->lo_bytes)) ||
+      (p->hi_bytes > 0 && overlap(node_shift, 8 * nent, out_hi, p->hi_bytes)))
+    return fail(SLDG_ERR_ALIAS, "node_shift overlaps an output buffer");
+  if (nent > p->table_cap) return fail(SLDG_ERR_ARG, "too many node entries for the plan tables");
+  hipError_t e = launch_line_tables(p->k, nent, p->n[dim], node_shift, p->d_s, p->d_ab, true,
+                                    false, p->stream);
+  if (e != hipSuccess) return device_error(e, "line-table launch");
+  ColArgs a{};
+  a.in_lo = in_mass;
+  a.in_hi = in_hi;
+  a.out_lo = out_mass;
+  a.out_hi = out_hi;
+  a.pmap = p->d_pmap;
+  a.s_tab = p->d_s;
+  a.ab_tab = p->d_ab;
+  a.ab_cs = nent;
+  a.cells = p->cells;
+  a.ndim = p->ndim;
+  a.d = dim;
+  a.t = tdim;
+  int64_t Pd = 1, Pt = 1;
+  int32_t msd = 1, mst = 1;
+  for (int f = 0; f < dim; ++f) { Pd *= p->n[f]; msd *= o; }
+  for (int f = 0; f < tdim; ++f) { Pt *= p->n[f]; mst *= o; }
+  a.Pd = Pd;
+  a.Nd = p->n[dim];
+  a.Pt = Pt;
+  a.Nt = p->n[tdim];
+  a.msd = msd;
+  a.mst = mst;
+  int32_t groups = 1;
+  for (int f = 0; f < p->ndim - 2; ++f) groups *= o;
+  a.ngroups = groups;
+  double x[4], w[4];
+  gauss_rule(o, x, w);
+  for (int q = 0; q < o; ++q) {
+    double pm = 1.0, pc = x[q];          // P_0, P_1 (Bonnet's recurrence)
+    for (int j = 0; j < o; ++j) {
+      double pj;
+      if (j == 0) pj = 1.0;
+      else if (j == 1) pj = x[q];
+      else {
+        const double pn = ((2 * (j - 1) + 1) * x[q] * pc - (j - 1) * pm) / j;
+        pm = pc;
+        pc = pn;
+        pj = pn;
+      }
+      a.P[j][q] = pj;
+      a.back[j][q] = 0.5 * (2 * j + 1) * w[q] * pj;
+    }
+  }
+  e = launch_colloc(p->k, (int)p->tier, a, p->stream);
+  if (e == hipErrorInvalidConfiguration)
+    return fail(SLDG_ERR_UNSUPPORTED, "collocated sweep: grid too large for one launch");
+  if (e != hipSuccess) return device_error(e, "collocated sweep launch");
   return ok();
 }
 
