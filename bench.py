@@ -335,6 +335,60 @@ def scaled_fp16_extra(sl, torch, prob, init, steps, warmup, ref_final):
     return out
 
 
+def next4_extra(sl, torch, prob, init, reps=10):
+    """The steps around the path: the 4D x1-sweep with Gauss-node collocation
+    in v1 (FP32-mode), and a self-consistent (x, v) Vlasov-Poisson step."""
+    out = {}
+    p = sl.Plan(prob.ns, prob.k, "fp32")
+    mass0, hi0 = init
+    s0 = (mass0.clone(), hi0.to(torch.float32).contiguous())
+    s1 = p.empty_state()
+    sw = prob.seq[0]                                   # x1 sweep, displacement from v1
+    o = prob.k + 1
+    xi = [float(v) for v in __import__("numpy").polynomial.legendre.leggauss(o)[0]]
+    n1 = prob.ns[sw.dep[0]]
+    # displacement at the v1 Gauss nodes: linear in v1 across each cell
+    sig = torch.from_numpy(sw.sigma).cuda()
+    dsig = torch.empty_like(sig)
+    dsig[1:-1] = 0.5 * (sig[2:] - sig[:-2])
+    dsig[0], dsig[-1] = sig[1] - sig[0], sig[-1] - sig[-2]
+    node = (sig[:, None] + 0.5 * dsig[:, None] * torch.tensor(xi, dtype=torch.float64,
+                                                             device="cuda")[None, :]).contiguous()
+    for _ in range(3):
+        p.advect_dim_collocated(sw.dim, sw.dep[0], node, *s0, *s1)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    e0.record()
+    for _ in range(reps):
+        p.advect_dim_collocated(sw.dim, sw.dep[0], node, *s0, *s1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 2 * state_bytes(prob.cells, prob.modes, "fp32")
+    out["collocated_x1_sweep"] = {"ms": round(ms, 4),
+                                  "algorithmic_GBps": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                                  "frac_hbm_peak": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    p.close()
+    from paper_1603_07008_amd import inputs
+    pr = inputs.landau_2d(512, 512, 2, 0.1, 0.5)
+    q = sl.Plan(pr.ns, pr.k, "fp32")
+    m, h = inputs.random_coefficients_device(2, pr.k, pr.cells, seed=7)
+    a = (m, h.to(torch.float32).contiguous())
+    b = q.empty_state()
+    hx, hv = pr.h
+    sx = torch.from_numpy(pr.seq[0].sigma).cuda()
+    q.vlasov_poisson_steps(2, sx, hx, hv, pr.dt, a, b)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    e0.record()
+    q.vlasov_poisson_steps(20, sx, hx, hv, pr.dt, a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    out["vlasov_poisson_step_512x512_k2"] = {"ms_per_step": round(e0.elapsed_time(e1) / 20, 4)}
+    q.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -468,6 +522,8 @@ def main():
         extras["batched"] = batched_extra(sl, torch, 20, args.seed)
         log("bench: differentiation workload")
         extras["adjoint"] = adjoint_extra(sl, torch, args.seed)
+        log("bench: collocated sweep and self-consistent field")
+        extras["next4"] = next4_extra(sl, torch, prob, (mass0, hi0))
         out["extras"] = extras
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle baseline")

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sldg_internal.h"
+
 namespace sldg {
 
 struct ColArgs {
@@ -18,6 +20,9 @@ struct ColArgs {
   int64_t cells;
   int32_t ndim, d, t;      // swept and transverse dimensions
   int64_t Pd, Nd, Pt, Nt;  // strides (cells) and extents of d and t
+  FastDiv fPd, fNd, fPt, fNt;
+  int32_t n_lo;            // planes in lo
+  int32_t wide;            // 0: at most the cell mean in FP64 (plane index m - n_lo)
   int32_t msd, mst;        // mode-id strides of j_d and j_t
   int32_t ngroups;         // spectator groups (o^(ndim-2))
   double P[4][4];          // P_j(y_q) at the Gauss nodes (ascending)

@@ -885,6 +885,12 @@ sldg_status sldg_advect_dim_collocated(sldg_plan_t p, int dim, int tdim, const d
   a.Nd = p->n[dim];
   a.Pt = Pt;
   a.Nt = p->n[tdim];
+  a.fPd = FastDiv::make((uint32_t)Pd);
+  a.fNd = FastDiv::make((uint32_t)a.Nd);
+  a.fPt = FastDiv::make((uint32_t)Pt);
+  a.fNt = FastDiv::make((uint32_t)a.Nt);
+  a.n_lo = (int32_t)p->n_lo;
+  a.wide = p->ndouble > 1 ? 1 : 0;
   a.msd = msd;
   a.mst = mst;
   int32_t groups = 1;

@@ -41,6 +41,12 @@ CASES = [
     ((8, 6, 5), 2, 0, 2, 1),
     ((8, 6, 5), 1, 2, 1, 1),
     ((20, 12), 2, 0, 1, 2),
+    # transverse stride a multiple of 64 cells (one transverse cell per wave)
+    ((64, 12), 2, 0, 1, 1),
+    ((16, 8, 6), 1, 1, 2, 1),
+    ((64, 10), 3, 0, 1, 2),
+    ((8, 8, 3, 4), 2, 0, 2, 1),
+    ((4, 16, 4, 5), 2, 3, 2, 2),
 ]
 
 
