@@ -70,6 +70,8 @@ def _load():
         lib.oracle_round_array.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int]
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_num_threads.argtypes = []
+        lib.oracle_set_threads.restype = None
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -77,6 +79,11 @@ def _load():
 def num_threads():
     """OpenMP threads the oracle's C sweep runs on."""
     return _load().oracle_num_threads()
+
+
+def set_threads(n):
+    """Sets the OpenMP threads of later C sweeps (for timing the oracle)."""
+    _load().oracle_set_threads(int(n))
 
 
 # ---------------------------------------------------------------------------
@@ -568,6 +575,75 @@ def poisson_field(state, ns, k, hx, hv):
 def poisson_shift(state, ns, k, hx, hv, dt):
     """The v-sweep displacement (cells) per x line: E(x_i) dt / h_v."""
     return poisson_field(state, ns, k, hx, hv) * dt / hv
+
+
+# ---------------------------------------------------------------------------
+# Self-consistent field of (x1, x2, v1, v2) problems (section II: the Vlasov
+# equation with E(x)).  Gauss's law div E = rho - mean(rho) with a curl-free
+# periodic E = -grad phi, solved spectrally on the cell means of the density
+# (the c_0 of the x cells): the cell means are divided by the Fourier symbol of
+# cell averaging, sinc(kappa_1 h_1/2) sinc(kappa_2 h_2/2), so the solve is
+# exact for densities that are trigonometric polynomials resolved by the grid;
+# the Nyquist modes and the mean are dropped.  E at the x cell centres; the
+# v1 (v2) sweep of the line through x cell (i1, i2) moves by E_1 dt / h_v1
+# (E_2 dt / h_v2).
+# ---------------------------------------------------------------------------
+
+def density_means_2d(state, ns, hv1, hv2):
+    """Cell means of rho(x1, x2) = int int f dv1 dv2 over the x cells:
+    h_v1 h_v2 times the sum over the v cells of c_0 (the mean of f over a v
+    cell integrates to h_v1 h_v2 c_0).  Shape [N2, N1] (x1 fastest)."""
+    n1, n2, m1, m2 = ns
+    c0 = np.asarray(state[0], dtype=np.float64).reshape(m2, m1, n2, n1)
+    out = np.empty((n2, n1))
+    for i2 in range(n2):
+        for i1 in range(n1):
+            out[i2, i1] = hv1 * hv2 * math.fsum(c0[:, :, i2, i1].ravel().tolist())
+    return out
+
+
+def _wavenumbers(n, h):
+    """Angular wave numbers 2 pi m / (n h) of the DFT indices 0..n-1 (m taken
+    in (-n/2, n/2]), and whether each is the Nyquist index of an even n."""
+    m = np.array([j if j <= n // 2 else j - n for j in range(n)], dtype=np.float64)
+    nyq = np.array([n % 2 == 0 and j == n // 2 for j in range(n)])
+    return 2.0 * math.pi * m / (n * h), nyq
+
+
+def poisson_field_2d(state, ns, h):
+    """(E_1, E_2) at the x cell centres, each flattened with x1 fastest.
+    h = (h_x1, h_x2, h_v1, h_v2).  Steps: the cell means of rho; their 2D DFT
+    (library FFT); per wave vector kappa != 0 without a Nyquist index, the
+    point-value Fourier coefficient rho_hat / (sinc(kappa_1 h_1/2)
+    sinc(kappa_2 h_2/2)) and E_hat = -i kappa rho_hat / |kappa|^2 (from
+    -lap phi = rho - mean, E = -grad phi); the inverse DFT at the centres."""
+    n1, n2 = ns[0], ns[1]
+    rho = density_means_2d(state, ns, h[2], h[3])
+    R = np.fft.fft2(rho)                              # axis 0: x2, axis 1: x1
+    k1, nyq1 = _wavenumbers(n1, h[0])
+    k2, nyq2 = _wavenumbers(n2, h[1])
+    E1h = np.zeros((n2, n1), dtype=complex)
+    E2h = np.zeros((n2, n1), dtype=complex)
+    for a in range(n2):
+        for b in range(n1):
+            if nyq1[b] or nyq2[a] or (k1[b] == 0.0 and k2[a] == 0.0):
+                continue
+            s1 = math.sin(0.5 * k1[b] * h[0]) / (0.5 * k1[b] * h[0]) if k1[b] != 0.0 else 1.0
+            s2 = math.sin(0.5 * k2[a] * h[1]) / (0.5 * k2[a] * h[1]) if k2[a] != 0.0 else 1.0
+            rho_pt = R[a, b] / (s1 * s2)
+            kk = k1[b] ** 2 + k2[a] ** 2
+            E1h[a, b] = -1j * k1[b] * rho_pt / kk
+            E2h[a, b] = -1j * k2[a] * rho_pt / kk
+    E1 = np.real(np.fft.ifft2(E1h))
+    E2 = np.real(np.fft.ifft2(E2h))
+    return E1.ravel(), E2.ravel()
+
+
+def poisson_shift_2d(state, ns, h, dt):
+    """The v1- and v2-sweep displacements (cells) per x line (x1 fastest):
+    E_1 dt / h_v1 and E_2 dt / h_v2."""
+    E1, E2 = poisson_field_2d(state, ns, h)
+    return E1 * dt / h[2], E2 * dt / h[3]
 
 
 # ---------------------------------------------------------------------------

@@ -167,6 +167,17 @@ int oracle_num_threads(void)
     return nt;
 }
 
+/* Sets the OpenMP thread count of later sweeps (n > 0); timing only. */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /*
  * Transpose of oracle_sweep (no rounding): g_in = M^T g_out, M the sweep with
  * the same tables.  Output cell i reads input cells i-s (through A) and
