@@ -112,7 +112,7 @@ def measured_plane_copy(sl, torch, cells, nplanes, tiers=(1, 3, 9, 27), reps=10)
     return out
 
 
-def run_tier(sl, torch, prob, tier, init, steps, warmup, tune_cache=None):
+def run_tier(sl, torch, prob, tier, init, steps, warmup, tune_cache=None, single_reps=20):
     """Time `steps` split steps (after `warmup`) of `prob` in `tier`."""
     p = sl.Plan(prob.ns, prob.k, tier)
     mass0, hi0 = init
@@ -162,8 +162,28 @@ def run_tier(sl, torch, prob, tier, init, steps, warmup, tune_cache=None):
     m_end = p.mass(bufs[cur][0])
     drift = abs((m_end[0] + m_end[1]) - (m_start[0] + m_start[1])) / abs(m_start[0] + m_start[1])
     final = bufs[cur]
+    # each sweep direction alone (its table launch included): event pairs
+    # around single calls, after 3 warm-ups, outside the timed steps
+    single = {}
+    other = bufs[1 - cur]
+    for d, dep, sig in seq:
+        if d in single:
+            continue
+        for _ in range(3):
+            p.advect_dim(d, sig, dep, *final, *other)
+        ts = []
+        for _ in range(single_reps):
+            e0, e1 = _events(torch)
+            e0.record()
+            p.advect_dim(d, sig, dep, *final, *other)
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ts.sort()
+        single[d] = {"median_ms": round(ts[len(ts) // 2], 4), "min_ms": round(ts[0], 4),
+                     "reps": single_reps}
     return {"plan": p, "ms_per_step": ms, "kernels": kern, "per_dim": per_dim,
-            "mass_drift": drift, "final": final, "shapes": shapes}
+            "mass_drift": drift, "final": final, "shapes": shapes, "single": single}
 
 
 def cpu_baseline(prob, tier, seconds, seed):
@@ -198,12 +218,26 @@ def cpu_baseline(prob, tier, seconds, seed):
         O.sweep(state, prob.ns, prob.k, sw.dim, sw.sigma, sw.dep, tier, sel=sel)
     dt = time.perf_counter() - t0
     updates = nsel * prob.modes * len(prob.seq)
-    return {"value": updates / dt, "unit": "coeff-updates/s", "cores": O.num_threads(),
-            "kind": "oracle",
+    # the same sweeps on one thread: the marginal cost between two samples
+    # (about 1 s and 4 s of work), so the fixed cost of each call drops out
+    nt = O.num_threads()
+    nb = int(min(nsel, max(4096, 4.0 / (per * nt))))
+    na = max(1024, nb // 4)
+    O.set_threads(1)
+    try:
+        ta, tb = timed(na), timed(nb)
+    finally:
+        O.set_threads(nt)
+    dt1 = max(tb - ta, 1e-9)
+    n1 = nb - na
+    updates1 = n1 * prob.modes * len(prob.seq)
+    return {"value": updates / dt, "unit": "coeff-updates/s", "cores": nt,
+            "kind": "oracle", "value_1_thread": updates1 / dt1,
             "sample": f"one split step (6 sweeps) of the {prob.ns} k={prob.k} {tier}-mode "
                       f"workload on the full host state, evaluated for {nsel} randomly sampled "
                       f"output cells x {prob.modes} coefficients ({updates} coefficient updates, "
-                      f"{dt:.1f} s)"}
+                      f"{dt:.1f} s); value_1_thread: one thread, the marginal rate between samples "
+                      f"of {na} and {nb} cells ({ta:.1f} s, {tb:.1f} s)"}
 
 
 def _events(torch):
@@ -466,7 +500,8 @@ def main():
             per_sweep[names.get(d, str(d))] = {
                 "avg_ms": round(a, 4), "GB/s": round(launch_bytes / (a * 1e-3) / 1e9, 1),
                 "frac_hbm_peak": round(launch_bytes / (a * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                "launch_shape": main_r["shapes"][d]}
+                "launch_shape": main_r["shapes"][d],
+                "single_call": main_r["single"].get(d)}
 
     # mixed vs FP64: speedup and the error of the mixed run against the FP64 run
     tiers_out = {}

@@ -340,6 +340,53 @@ sldg_status sldg_vlasov_poisson_steps(sldg_plan_t plan, int nsteps, const double
                                       int* result_buffer);
 
 /*
+ * Self-consistent field of an (x1, x2, v1, v2) problem (ndim = 4, dimensions
+ * in that order), for the v-sweeps of the split step.  As for the (x, v)
+ * field, the paper gives the Vlasov equation with a field E(x) (section II)
+ * but no field equation.  The one taken is Gauss's law div E = rho -
+ * mean(rho), with E = -grad phi periodic, in the paper's sign convention
+ * (+E . grad_v f).  It is solved spectrally on the x-cell means of rho,
+ * which are h_v1 h_v2 times the sums over the v cells of the cell means c_0.
+ * The 2D DFT of the cell means is divided by the Fourier symbol of cell
+ * averaging, sinc(kappa_1 h_x1 / 2) sinc(kappa_2 h_x2 / 2), and
+ * E_hat = -i kappa rho_hat / |kappa|^2.  The mean and the Nyquist modes are
+ * dropped.  E is evaluated at the x cell centres.  The solve is exact for
+ * densities that are trigonometric polynomials resolved by the grid.
+ *   mass, hi    the state (device; the plan's layout and tier, unscaled)
+ *   h           host double[4]: cell widths h_x1, h_x2, h_v1, h_v2
+ *   dt          time step of the v-sweeps
+ *   shift_v1    device double [N1 N2], x1 fastest: E_1 dt / h_v1, the
+ *               displacement of the v1-sweep line through x cell (i1, i2)
+ *               (use dep_mask = 3)
+ *   shift_v2    device double [N1 N2]: E_2 dt / h_v2 (dep_mask = 3)
+ *   field_out   optional device double [2 N1 N2]: E_1, then E_2
+ * N1, N2 <= 2048 (direct DFTs with twiddles in LDS; SLDG_ERR_UNSUPPORTED
+ * beyond).  Asynchronous on the plan's stream.  Grows a plan-owned scratch
+ * buffer (hipMalloc) on the first call that needs more.  Errors: SLDG_ERR_ARG,
+ * SLDG_ERR_ALIAS, SLDG_ERR_UNSUPPORTED, SLDG_ERR_NOMEM, SLDG_ERR_DEVICE.
+ */
+sldg_status sldg_poisson_shift_2d(sldg_plan_t plan, const double* mass, const void* hi,
+                                  const double* h, double dt, double* shift_v1, double* shift_v2,
+                                  double* field_out);
+
+/*
+ * nsteps self-consistent Strang steps of an (x1, x2, v1, v2) plan:
+ *   - X1(dt/2) with shift_x1 (device [N_v1], per v1 line, dep_mask = 4);
+ *   - X2(dt/2) with shift_x2 (device [N_v2], dep_mask = 8);
+ *   - the field of the state into shift_v1, shift_v2 (device [N1 N2] each,
+ *     overwritten; sldg_poisson_shift_2d);
+ *   - V1(dt), V2(dt);
+ *   - X1(dt/2), X2(dt/2).
+ * Buffers as in sldg_split_steps.  *result_buffer receives the buffer holding
+ * the result.  Asynchronous on the plan's stream.
+ */
+sldg_status sldg_vlasov_poisson_steps_2d2v(sldg_plan_t plan, int nsteps, const double* shift_x1,
+                                           const double* shift_x2, const double* h, double dt,
+                                           double* shift_v1, double* shift_v2, double* mass0,
+                                           void* hi0, double* mass1, void* hi1,
+                                           int* result_buffer);
+
+/*
  * Kernel timing.  While enabled, every sweep kernel launch of the plan is
  * bracketed by a pair of HIP events recorded on the plan's stream (the line
  * table kernel is outside the pair), up to 4096 launches after enabling.

@@ -27,7 +27,8 @@ EXPORTS = ("sldg_plan", "sldg_plan_destroy", "sldg_plan_set_stream", "sldg_line_
            "sldg_scaled_export", "sldg_advect_dim_scaled", "sldg_split_steps_scaled",
            "sldg_plan_set_shape", "sldg_plan_get_shape", "sldg_tune_candidate", "sldg_plan_tune",
            "sldg_device_plane_copy", "sldg_batch_get_class_tuning", "sldg_batch_set_class_tuning",
-           "sldg_poisson_shift", "sldg_vlasov_poisson_steps", "sldg_advect_dim_collocated")
+           "sldg_poisson_shift", "sldg_vlasov_poisson_steps", "sldg_advect_dim_collocated",
+           "sldg_poisson_shift_2d", "sldg_vlasov_poisson_steps_2d2v")
 
 
 class SldgError(RuntimeError):
@@ -121,6 +122,11 @@ def lib():
     L.sldg_vlasov_poisson_steps.argtypes = [vp, i32, vp, dbl, dbl, dbl, vp, vp, vp, vp, vp,
                                             ctypes.POINTER(i32)]
     L.sldg_vlasov_poisson_steps.restype = i32
+    L.sldg_poisson_shift_2d.argtypes = [vp, vp, vp, ctypes.POINTER(dbl), dbl, vp, vp, vp]
+    L.sldg_poisson_shift_2d.restype = i32
+    L.sldg_vlasov_poisson_steps_2d2v.argtypes = [vp, i32, vp, vp, ctypes.POINTER(dbl), dbl, vp,
+                                                 vp, vp, vp, vp, vp, ctypes.POINTER(i32)]
+    L.sldg_vlasov_poisson_steps_2d2v.restype = i32
     L.sldg_status_string.argtypes = [i32]
     L.sldg_status_string.restype = ctypes.c_char_p
     L.sldg_last_error.argtypes = []
@@ -347,6 +353,65 @@ class Plan:
                                                _ptr(state0[0]), _ptr(state0[1]),
                                                _ptr(state1[0]), _ptr(state1[1]),
                                                ctypes.byref(res)), "sldg_vlasov_poisson_steps")
+        return res.value
+
+    # --- self-consistent field of (x1, x2, v1, v2) problems ----------------
+
+    def _check_xtable(self, t, n, what):
+        import torch
+        if t is not None and (not t.is_cuda or t.dtype != torch.float64 or
+                              not t.is_contiguous() or t.numel() < n):
+            raise ValueError(f"{what} must be a contiguous float64 device tensor of >= {n} "
+                             f"elements")
+
+    def poisson_shift_2d(self, mass, hi, h, dt, shift_v1=None, shift_v2=None, field_out=None):
+        """The v1- and v2-sweep displacements E_1 dt / h_v1, E_2 dt / h_v2 of
+        the state's field (sldg_poisson_shift_2d); h = (h_x1, h_x2, h_v1,
+        h_v2).  Returns (shift_v1, shift_v2), device float64 [N1 N2] each."""
+        import torch
+        self._check_state(mass, hi, "poisson_shift_2d")
+        if self.ndim != 4:
+            raise ValueError("poisson_shift_2d needs an (x1, x2, v1, v2) plan")
+        nxx = self.ncells[0] * self.ncells[1]
+        if shift_v1 is None:
+            shift_v1 = torch.empty(nxx, dtype=torch.float64, device=mass.device)
+        if shift_v2 is None:
+            shift_v2 = torch.empty(nxx, dtype=torch.float64, device=mass.device)
+        self._check_xtable(shift_v1, nxx, "poisson_shift_2d: shift_v1")
+        self._check_xtable(shift_v2, nxx, "poisson_shift_2d: shift_v2")
+        self._check_xtable(field_out, 2 * nxx, "poisson_shift_2d: field_out")
+        hh = (ctypes.c_double * 4)(*[float(x) for x in h])
+        _check(lib().sldg_poisson_shift_2d(self.handle, _ptr(mass), _ptr(hi), hh, float(dt),
+                                           _ptr(shift_v1), _ptr(shift_v2),
+                                           None if field_out is None else _ptr(field_out)),
+               "sldg_poisson_shift_2d")
+        return shift_v1, shift_v2
+
+    def vlasov_poisson_steps_2d2v(self, nsteps, shift_x1, shift_x2, h, dt, state0, state1,
+                                  shift_v1=None, shift_v2=None):
+        """nsteps self-consistent Strang steps of an (x1, x2, v1, v2) plan
+        (sldg_vlasov_poisson_steps_2d2v); returns the index (0 or 1) of the
+        state holding the result."""
+        import torch
+        if self.ndim != 4:
+            raise ValueError("vlasov_poisson_steps_2d2v needs an (x1, x2, v1, v2) plan")
+        self._check_shift(shift_x1, 4, "vlasov_poisson_steps_2d2v")
+        self._check_shift(shift_x2, 8, "vlasov_poisson_steps_2d2v")
+        self._check_state(*state0, "vlasov_poisson_steps_2d2v state0")
+        self._check_state(*state1, "vlasov_poisson_steps_2d2v state1")
+        nxx = self.ncells[0] * self.ncells[1]
+        if shift_v1 is None:
+            shift_v1 = torch.empty(nxx, dtype=torch.float64, device=state0[0].device)
+        if shift_v2 is None:
+            shift_v2 = torch.empty(nxx, dtype=torch.float64, device=state0[0].device)
+        self._check_shift(shift_v1, 3, "vlasov_poisson_steps_2d2v")
+        self._check_shift(shift_v2, 3, "vlasov_poisson_steps_2d2v")
+        hh = (ctypes.c_double * 4)(*[float(x) for x in h])
+        res = ctypes.c_int(-1)
+        _check(lib().sldg_vlasov_poisson_steps_2d2v(
+            self.handle, int(nsteps), _ptr(shift_x1), _ptr(shift_x2), hh, float(dt),
+            _ptr(shift_v1), _ptr(shift_v2), _ptr(state0[0]), _ptr(state0[1]), _ptr(state1[0]),
+            _ptr(state1[1]), ctypes.byref(res)), "sldg_vlasov_poisson_steps_2d2v")
         return res.value
 
     # --- launch shapes and the autotuner -----------------------------------

@@ -10,6 +10,7 @@
 // polynomial of degree k+1 per cell; the v-sweep displaces the line through
 // x cell i by E(x_i) dt / h_v (each line uses its transverse cell centre).
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 
 #include "sldg_field.h"
@@ -137,6 +138,250 @@ hipError_t launch_field(int tier, const FieldPlanes& fp, int o, int32_t nx, int3
     case 3: return launch_field_t<_Float16>(fp, o, nx, nv, hx, hv, dt, scratch, shift_out, field_out, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+// ---------------------------------------------------------------------------
+// 2D-2V problems (x1, x2, v1, v2).  Gauss's law div E = rho - mean(rho) with a
+// curl-free periodic E = -grad phi, solved spectrally on the x-cell means of
+// rho (h_v1 h_v2 times the sum over the v cells of the cell mean c_0): the
+// DFT of the cell means is divided by the Fourier symbol of cell averaging,
+// sinc(kappa_1 h_1/2) sinc(kappa_2 h_2/2), and E_hat = -i kappa rho_hat /
+// |kappa|^2 (mean and Nyquist modes dropped); E at the x cell centres.  The
+// transforms are direct DFTs (N1, N2 <= kMaxDft) with twiddles from a table
+// in LDS and exact integer phase reduction; all arithmetic in FP64.
+// ---------------------------------------------------------------------------
+
+// Partial sums over v cells [z rows, (z+1) rows) of the mode-0 plane for x
+// cells [256 blockIdx.x, +256).
+template <class T>
+__global__ __launch_bounds__(256) void density2_partial_kernel(const void* plane, int64_t nxx,
+                                                               int64_t nslab, int64_t rows,
+                                                               double* __restrict__ part) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t z = blockIdx.y;
+  if (i >= nxx) return;
+  const int64_t s0 = z * rows, s1 = s0 + rows < nslab ? s0 + rows : nslab;
+  const T* p = static_cast<const T*>(plane);
+  double acc = 0.0;
+  for (int64_t s = s0; s < s1; ++s) acc += as_double(p[s * nxx + i]);
+  part[z * nxx + i] = acc;
+}
+
+__global__ __launch_bounds__(256) void density2_final_kernel(const double* __restrict__ part,
+                                                             int32_t nz, int64_t nxx,
+                                                             double hvv, double* __restrict__ rho) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nxx) return;
+  double acc = 0.0;
+  for (int32_t z = 0; z < nz; ++z) acc += part[(int64_t)z * nxx + i];
+  rho[i] = hvv * acc;
+}
+
+// tw[r] = exp(2 pi i r / n), r < n, filled by the workgroup.
+__device__ __forceinline__ void fill_twiddles(double2* tw, int32_t n) {
+  for (int32_t r = threadIdx.x; r < n; r += blockDim.x) {
+    double sn, cs;
+    sincospi(2.0 * r / n, &sn, &cs);
+    tw[r] = make_double2(cs, sn);
+  }
+  __syncthreads();
+}
+
+// Forward DFT along x1 of the real cell means: thread t = k1 + N1 i2,
+// C[t] = sum_i1 rho[i1 + N1 i2] exp(-2 pi i k1 i1 / N1).
+__global__ __launch_bounds__(256) void dft_x1_kernel(const double* __restrict__ rho, int32_t n1,
+                                                     int32_t n2, double2* __restrict__ C) {
+  extern __shared__ double2 tw[];
+  fill_twiddles(tw, n1);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n1 * n2) return;
+  const int32_t k1 = (int32_t)(t % n1), i2 = (int32_t)(t / n1);
+  const double* row = rho + (int64_t)i2 * n1;
+  double re = 0.0, im = 0.0;
+  int32_t r = 0;
+  for (int32_t i1 = 0; i1 < n1; ++i1) {
+    const double v = row[i1];
+    re = fma(v, tw[r].x, re);
+    im = fma(-v, tw[r].y, im);
+    r += k1;
+    if (r >= n1) r -= n1;
+  }
+  C[t] = make_double2(re, im);
+}
+
+// Wave number 2 pi m / (n h), m the index taken in (-n/2, n/2]; nyq when m is
+// the Nyquist index of an even n.
+__device__ __forceinline__ double wave_number(int32_t j, int32_t n, double h, bool* nyq) {
+  const int32_t m = j <= n / 2 ? j : j - n;
+  *nyq = (n % 2 == 0) && (j == n / 2);
+  return 2.0 * M_PI * m / (n * h);
+}
+
+// sin(pi m / n) / (pi m / n), the cell-average symbol at index j.
+__device__ __forceinline__ double cell_sinc(int32_t j, int32_t n) {
+  const int32_t m = j <= n / 2 ? j : j - n;
+  if (m == 0) return 1.0;
+  const double z = (double)m / n;
+  return sinpi(z) / (M_PI * z);
+}
+
+// Forward DFT along x2 and the field symbol: thread t = k1 + N1 k2,
+// R = sum_i2 C[k1 + N1 i2] exp(-2 pi i k2 i2 / N2), then
+// E_hat_f = -i kappa_f (R / sincs) / |kappa|^2.
+__global__ __launch_bounds__(256) void dft_x2_solve_kernel(const double2* __restrict__ C,
+                                                           int32_t n1, int32_t n2, double h1,
+                                                           double h2, double2* __restrict__ E1h,
+                                                           double2* __restrict__ E2h) {
+  extern __shared__ double2 tw[];
+  fill_twiddles(tw, n2);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n1 * n2) return;
+  const int32_t k1 = (int32_t)(t % n1), k2 = (int32_t)(t / n1);
+  double re = 0.0, im = 0.0;
+  int32_t r = 0;
+  for (int32_t i2 = 0; i2 < n2; ++i2) {
+    const double2 c = C[k1 + (int64_t)n1 * i2];
+    const double2 w = tw[r];                       // exp(+...); the forward uses its conjugate
+    re = fma(c.x, w.x, fma(c.y, w.y, re));
+    im = fma(c.y, w.x, fma(-c.x, w.y, im));
+    r += k2;
+    if (r >= n2) r -= n2;
+  }
+  bool ny1, ny2;
+  const double q1 = wave_number(k1, n1, h1, &ny1), q2 = wave_number(k2, n2, h2, &ny2);
+  double2 e1 = make_double2(0.0, 0.0), e2 = e1;
+  if (!ny1 && !ny2 && (k1 != 0 || k2 != 0)) {
+    const double sc = cell_sinc(k1, n1) * cell_sinc(k2, n2);
+    const double pre = re / sc, pim = im / sc;
+    const double kk = q1 * q1 + q2 * q2;
+    // -i kappa (pre + i pim) = kappa pim - i kappa pre
+    e1 = make_double2(q1 * pim / kk, -q1 * pre / kk);
+    e2 = make_double2(q2 * pim / kk, -q2 * pre / kk);
+  }
+  E1h[t] = e1;
+  E2h[t] = e2;
+}
+
+// Inverse DFT along x2 of both fields: thread t = k1 + N1 i2,
+// D_f[t] = sum_k2 E_hat_f[k1 + N1 k2] exp(2 pi i k2 i2 / N2).
+__global__ __launch_bounds__(256) void idft_x2_kernel(const double2* __restrict__ E1h,
+                                                      const double2* __restrict__ E2h, int32_t n1,
+                                                      int32_t n2, double2* __restrict__ D1,
+                                                      double2* __restrict__ D2) {
+  extern __shared__ double2 tw[];
+  fill_twiddles(tw, n2);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n1 * n2) return;
+  const int32_t k1 = (int32_t)(t % n1), i2 = (int32_t)(t / n1);
+  double a_re = 0.0, a_im = 0.0, b_re = 0.0, b_im = 0.0;
+  int32_t r = 0;
+  for (int32_t k2 = 0; k2 < n2; ++k2) {
+    const double2 w = tw[r];
+    const double2 a = E1h[k1 + (int64_t)n1 * k2], b = E2h[k1 + (int64_t)n1 * k2];
+    a_re = fma(a.x, w.x, fma(-a.y, w.y, a_re));
+    a_im = fma(a.x, w.y, fma(a.y, w.x, a_im));
+    b_re = fma(b.x, w.x, fma(-b.y, w.y, b_re));
+    b_im = fma(b.x, w.y, fma(b.y, w.x, b_im));
+    r += i2;
+    if (r >= n2) r -= n2;
+  }
+  D1[t] = make_double2(a_re, a_im);
+  D2[t] = make_double2(b_re, b_im);
+}
+
+// Inverse DFT along x1, real part, 1 / (N1 N2): thread t = i1 + N1 i2.
+__global__ __launch_bounds__(256) void idft_x1_kernel(const double2* __restrict__ D1,
+                                                      const double2* __restrict__ D2, int32_t n1,
+                                                      int32_t n2, double dt, double hv1,
+                                                      double hv2, double* __restrict__ shift1,
+                                                      double* __restrict__ shift2,
+                                                      double* __restrict__ field) {
+  extern __shared__ double2 tw[];
+  fill_twiddles(tw, n1);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nxx = (int64_t)n1 * n2;
+  if (t >= nxx) return;
+  const int32_t i1 = (int32_t)(t % n1), i2 = (int32_t)(t / n1);
+  const double2* d1 = D1 + (int64_t)i2 * n1;
+  const double2* d2 = D2 + (int64_t)i2 * n1;
+  double e1 = 0.0, e2 = 0.0;
+  int32_t r = 0;
+  for (int32_t k1 = 0; k1 < n1; ++k1) {
+    const double2 w = tw[r];
+    e1 = fma(d1[k1].x, w.x, fma(-d1[k1].y, w.y, e1));
+    e2 = fma(d2[k1].x, w.x, fma(-d2[k1].y, w.y, e2));
+    r += i1;
+    if (r >= n1) r -= n1;
+  }
+  const double inv = 1.0 / (double)nxx;
+  e1 *= inv;
+  e2 *= inv;
+  shift1[t] = e1 * dt / hv1;
+  shift2[t] = e2 * dt / hv2;
+  if (field) {
+    field[t] = e1;
+    field[nxx + t] = e2;
+  }
+}
+
+int32_t field2_chunks(int64_t nxx, int64_t nslab) {
+  int64_t nz = nslab < 256 ? nslab : 256;
+  const int64_t cap = ((int64_t)1 << 22) / (nxx > 0 ? nxx : 1);
+  if (nz > cap) nz = cap;
+  return (int32_t)(nz > 0 ? nz : 1);
+}
+
+int64_t field2_scratch_doubles(int32_t n1, int32_t n2, int64_t nslab) {
+  const int64_t nxx = (int64_t)n1 * n2;
+  return (int64_t)field2_chunks(nxx, nslab) * nxx + 11 * nxx + 1;   // + 1: double2 alignment
+}
+
+template <class T>
+static hipError_t launch_density2(const Field2Args& a, int32_t nz, int64_t nxx, double* part,
+                                  hipStream_t st) {
+  const int64_t rows = (a.nslab + nz - 1) / nz;
+  dim3 grid((unsigned)((nxx + 255) / 256), (unsigned)nz);
+  density2_partial_kernel<T><<<grid, 256, 0, st>>>(a.plane0, nxx, a.nslab, rows, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_field2(int tier, const Field2Args& a, double* scratch, hipStream_t st) {
+  const int64_t nxx = (int64_t)a.n1 * a.n2;
+  if (a.n1 < 1 || a.n2 < 1 || a.n1 > kMaxDft || a.n2 > kMaxDft) return hipErrorInvalidValue;
+  const int32_t nz = field2_chunks(nxx, a.nslab);
+  double* part = scratch;                               // [nz][nxx]
+  double* rho = part + (int64_t)nz * nxx;                // [nxx]
+  const int64_t cofs = ((int64_t)nz * nxx + nxx + 1) & ~(int64_t)1;   // 16-byte aligned
+  double2* C = reinterpret_cast<double2*>(scratch + cofs);  // [nxx] complex
+  double2* E1h = C + nxx;
+  double2* E2h = E1h + nxx;
+  double2* D1 = E2h + nxx;
+  double2* D2 = D1 + nxx;
+  hipError_t e;
+  if (a.lo0) e = launch_density2<double>(a, nz, nxx, part, st);
+  else {
+    switch (tier) {
+      case 0: e = launch_density2<double>(a, nz, nxx, part, st); break;
+      case 1: e = launch_density2<float>(a, nz, nxx, part, st); break;
+      case 2: e = launch_density2<__bf16>(a, nz, nxx, part, st); break;
+      case 3: e = launch_density2<_Float16>(a, nz, nxx, part, st); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (e != hipSuccess) return e;
+  const unsigned g = (unsigned)((nxx + 255) / 256);
+  density2_final_kernel<<<g, 256, 0, st>>>(part, nz, nxx, a.hv1 * a.hv2, rho);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const size_t lds1 = sizeof(double2) * a.n1, lds2 = sizeof(double2) * a.n2;
+  dft_x1_kernel<<<g, 256, lds1, st>>>(rho, a.n1, a.n2, C);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  dft_x2_solve_kernel<<<g, 256, lds2, st>>>(C, a.n1, a.n2, a.h1, a.h2, E1h, E2h);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  idft_x2_kernel<<<g, 256, lds2, st>>>(E1h, E2h, a.n1, a.n2, D1, D2);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  idft_x1_kernel<<<g, 256, lds1, st>>>(D1, D2, a.n1, a.n2, a.dt, a.hv1, a.hv2, a.shift1,
+                                       a.shift2, a.field);
+  return hipGetLastError();
 }
 
 }  // namespace sldg

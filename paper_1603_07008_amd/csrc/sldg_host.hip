@@ -921,6 +921,22 @@ sldg_status sldg_advect_dim_collocated(sldg_plan_t p, int dim, int tdim, const d
   return ok();
 }
 
+// Grows the plan's field scratch to `need` doubles (hipFree waits for the
+// device, so earlier solves that used the old buffer have finished).
+static sldg_status ensure_field(sldg_plan_t p, int64_t need) {
+  if (need <= p->field_cap) return SLDG_OK;
+  if (p->d_field) (void)hipFree(p->d_field);
+  p->d_field = nullptr;
+  p->field_cap = 0;
+  hipError_t e = hipMalloc(&p->d_field, sizeof(double) * (size_t)need);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SLDG_ERR_NOMEM, "field scratch: %s", hipGetErrorString(e));
+  }
+  p->field_cap = need;
+  return SLDG_OK;
+}
+
 sldg_status sldg_poisson_shift(sldg_plan_t p, const double* mass, const void* hi, double hx,
                                double hv, double dt, double* shift_out, double* field_out) {
   if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
@@ -950,18 +966,8 @@ sldg_status sldg_poisson_shift(sldg_plan_t p, const double* mass, const void* hi
                         : static_cast<const void*>(static_cast<const char*>(hi) +
                                                    (int64_t)v * p->cells * elem_size(p->tier));
   }
-  const int64_t need = field_scratch_doubles(p->o, nx, nv);
-  if (need > p->field_cap) {
-    if (p->d_field) (void)hipFree(p->d_field);
-    p->d_field = nullptr;
-    p->field_cap = 0;
-    hipError_t e = hipMalloc(&p->d_field, sizeof(double) * (size_t)need);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(SLDG_ERR_NOMEM, "field scratch: %s", hipGetErrorString(e));
-    }
-    p->field_cap = need;
-  }
+  sldg_status st = ensure_field(p, field_scratch_doubles(p->o, nx, nv));
+  if (st != SLDG_OK) return st;
   hipError_t e = launch_field((int)p->tier, fp, p->o, nx, nv, hx, hv, dt, p->d_field, shift_out,
                               field_out, p->stream);
   if (e != hipSuccess) return device_error(e, "field launch");
@@ -1001,6 +1007,104 @@ sldg_status sldg_vlasov_poisson_steps(sldg_plan_t p, int nsteps, const double* s
     st = run_sweep(p, 0, shift_x, 2u, m[cur], h[cur], m[1 - cur], h[1 - cur]);
     if (st != SLDG_OK) return st;
     cur = 1 - cur;
+  }
+  if (result_buffer) *result_buffer = cur;
+  return ok();
+}
+
+sldg_status sldg_poisson_shift_2d(sldg_plan_t p, const double* mass, const void* hi,
+                                  const double* h, double dt, double* shift_v1, double* shift_v2,
+                                  double* field_out) {
+  if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
+  if (p->ndim != 4)
+    return fail(SLDG_ERR_ARG, "the 2D field solve needs an (x1, x2, v1, v2) plan (ndim = 4)");
+  if (!h) return fail(SLDG_ERR_ARG, "null cell widths");
+  for (int d = 0; d < 4; ++d)
+    if (!(h[d] > 0.0) || !std::isfinite(h[d]))
+      return fail(SLDG_ERR_ARG, "cell width h[%d] = %g must be finite and > 0", d, h[d]);
+  if (!std::isfinite(dt)) return fail(SLDG_ERR_ARG, "dt must be finite");
+  if (!shift_v1 || !shift_v2) return fail(SLDG_ERR_ARG, "null shift output");
+  if (p->n[0] > kMaxDft || p->n[1] > kMaxDft)
+    return fail(SLDG_ERR_UNSUPPORTED, "2D field solve: N1, N2 must be <= %d", (int)kMaxDft);
+  const int32_t v = p->h_pmap[0];
+  if (v < 0 ? !mass : !hi) return fail(SLDG_ERR_ARG, "null state pointer");
+  const int64_t nxx = p->n[0] * p->n[1];
+  const int64_t ob = 8 * nxx;
+  const void* outs[3] = {shift_v1, shift_v2, field_out};
+  const int64_t len[3] = {ob, ob, 2 * ob};
+  for (int i = 0; i < 3; ++i) {
+    if (!outs[i]) continue;
+    if ((p->lo_bytes > 0 && overlap(outs[i], len[i], mass, p->lo_bytes)) ||
+        (p->hi_bytes > 0 && overlap(outs[i], len[i], hi, p->hi_bytes)))
+      return fail(SLDG_ERR_ALIAS, "field output overlaps the state");
+    for (int j = 0; j < i; ++j)
+      if (outs[j] && overlap(outs[i], len[i], outs[j], len[j]))
+        return fail(SLDG_ERR_ALIAS, "field outputs overlap each other");
+  }
+  Field2Args a{};
+  a.lo0 = v < 0 ? 1 : 0;
+  a.plane0 = v < 0 ? static_cast<const void*>(mass + (int64_t)(-1 - v) * p->cells)
+                   : static_cast<const void*>(static_cast<const char*>(hi) +
+                                              (int64_t)v * p->cells * elem_size(p->tier));
+  a.n1 = (int32_t)p->n[0];
+  a.n2 = (int32_t)p->n[1];
+  a.nslab = p->n[2] * p->n[3];
+  a.h1 = h[0];
+  a.h2 = h[1];
+  a.hv1 = h[2];
+  a.hv2 = h[3];
+  a.dt = dt;
+  a.shift1 = shift_v1;
+  a.shift2 = shift_v2;
+  a.field = field_out;
+  sldg_status st = ensure_field(p, field2_scratch_doubles(a.n1, a.n2, a.nslab));
+  if (st != SLDG_OK) return st;
+  hipError_t e = launch_field2((int)p->tier, a, p->d_field, p->stream);
+  if (e != hipSuccess) return device_error(e, "2D field launch");
+  return ok();
+}
+
+sldg_status sldg_vlasov_poisson_steps_2d2v(sldg_plan_t p, int nsteps, const double* shift_x1,
+                                           const double* shift_x2, const double* h, double dt,
+                                           double* shift_v1, double* shift_v2, double* mass0,
+                                           void* hi0, double* mass1, void* hi1,
+                                           int* result_buffer) {
+  if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
+  if (p->ndim != 4) return fail(SLDG_ERR_ARG, "2D-2V Vlasov-Poisson steps need ndim = 4");
+  if (nsteps < 0) return fail(SLDG_ERR_ARG, "nsteps %d < 0", nsteps);
+  if (!shift_x1 || !shift_x2 || !shift_v1 || !shift_v2)
+    return fail(SLDG_ERR_ARG, "null shift pointer");
+  double* m[2] = {mass0, mass1};
+  void* hh[2] = {hi0, hi1};
+  // x1 moves with v1 (dep dim 2), x2 with v2 (dep dim 3); v1, v2 with E(x1, x2)
+  const unsigned dep[4] = {1u << 2, 1u << 3, 3u, 3u};
+  const double* sh[4] = {shift_x1, shift_x2, shift_v1, shift_v2};
+  for (int b = 0; b < 2; ++b)
+    for (int d = 0; d < 4; ++d) {
+      sldg_status st = check_sweep(p, d, sh[d], dep[d], m[b], hh[b], m[1 - b], hh[1 - b]);
+      if (st != SLDG_OK) return st;
+    }
+  const int64_t ob = 8 * p->n[0] * p->n[1];
+  for (int b = 0; b < 2; ++b)
+    for (double* s : {shift_v1, shift_v2})
+      if ((p->lo_bytes > 0 && overlap(s, ob, m[b], p->lo_bytes)) ||
+          (p->hi_bytes > 0 && overlap(s, ob, hh[b], p->hi_bytes)))
+        return fail(SLDG_ERR_ALIAS, "a v shift table overlaps a state buffer");
+  if (overlap(shift_v1, ob, shift_v2, ob)) return fail(SLDG_ERR_ALIAS, "shift_v1 overlaps shift_v2");
+  int cur = 0;
+  auto sweep = [&](int d) {
+    sldg_status st = run_sweep(p, d, sh[d], dep[d], m[cur], hh[cur], m[1 - cur], hh[1 - cur]);
+    if (st == SLDG_OK) cur = 1 - cur;
+    return st;
+  };
+  for (int n = 0; n < nsteps; ++n) {
+    // X1(dt/2) X2(dt/2), the field of the state, V1(dt) V2(dt), X1(dt/2) X2(dt/2)
+    sldg_status st;
+    if ((st = sweep(0)) != SLDG_OK || (st = sweep(1)) != SLDG_OK) return st;
+    st = sldg_poisson_shift_2d(p, m[cur], hh[cur], h, dt, shift_v1, shift_v2, nullptr);
+    if (st != SLDG_OK) return st;
+    if ((st = sweep(2)) != SLDG_OK || (st = sweep(3)) != SLDG_OK) return st;
+    if ((st = sweep(0)) != SLDG_OK || (st = sweep(1)) != SLDG_OK) return st;
   }
   if (result_buffer) *result_buffer = cur;
   return ok();

@@ -1,0 +1,202 @@
+"""GPU parity of the self-consistent field of (x1, x2, v1, v2) problems
+(sldg_poisson_shift_2d, sldg_vlasov_poisson_steps_2d2v) against the oracle's
+poisson_field_2d and its Strang loop, on the same seeded inputs; the exact
+field of resolved waves; and linear Landau damping of the GPU run, for a
+wave along x1 and for a diagonal wave vector (which needs E_2).
+
+Bound: both sides compute in FP64 (the oracle with a library FFT and exact
+sums, the GPU with direct DFTs and plain sums), so they agree to a small
+multiple of N eps relative to the largest field value."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import sldg_oracle as O
+from paper_1603_07008_amd import inputs
+from gpu_helpers import download, download_nd, have_gpu, upload, upload_nd, weighted_rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sl():
+    if not have_gpu():
+        pytest.skip("no HIP device")
+    import paper_1603_07008_amd as sl
+    sl.lib()
+    return sl
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+CASES = [
+    # ns, k, tier, ndouble
+    ((12, 10, 3, 2), 1, "fp64", 1),
+    ((16, 8, 4, 6), 2, "fp32", 1),
+    ((9, 7, 5, 3), 1, "bf16", 1),
+    ((11, 16, 2, 3), 2, "fp16", 1),
+    ((10, 6, 3, 4), 2, "fp32", 0),
+    ((8, 12, 4, 2), 1, "fp32", 2),
+    ((48, 48, 6, 5), 2, "fp32", 1),
+]
+
+
+@pytest.mark.parametrize("ns,k,tier,ndouble", CASES)
+def test_field_matches_oracle(sl, ns, k, tier, ndouble):
+    import torch
+    st = inputs.random_coefficients(4, k, int(np.prod(ns)), seed=sum(ns) + k)
+    st = O.to_tier(st, tier, ndouble, k, 4)
+    h = (0.37, 0.29, 0.21, 0.17)
+    plan = sl.Plan(ns, k, tier, ndouble=ndouble)
+    m, hi = upload_nd(st, plan)
+    nxx = ns[0] * ns[1]
+    field = torch.empty(2 * nxx, dtype=torch.float64, device="cuda")
+    s1, s2 = plan.poisson_shift_2d(m, hi, h, 0.1, field_out=field)
+    W1, W2 = O.poisson_field_2d(st, ns, h)
+    got = field.cpu().numpy()
+    scale = max(np.max(np.abs(W1)), np.max(np.abs(W2)))
+    assert np.max(np.abs(got[:nxx] - W1)) <= 1e-12 * scale
+    assert np.max(np.abs(got[nxx:] - W2)) <= 1e-12 * scale
+    assert np.allclose(s1.cpu().numpy(), got[:nxx] * 0.1 / h[2], rtol=1e-15, atol=0)
+    assert np.allclose(s2.cpu().numpy(), got[nxx:] * 0.1 / h[3], rtol=1e-15, atol=0)
+
+
+def test_field_of_resolved_waves_is_exact(sl):
+    import torch
+    ns = (12, 10, 3, 2)
+    L1, L2, LV = 4 * math.pi, 3 * math.pi, 12.0
+    h = (L1 / ns[0], L2 / ns[1], LV / ns[2], LV / ns[3])
+    flat = lambda v: np.full_like(v, 1.0 / LV)
+    waves = [(0.03, -2, 1, 1.1), (0.01, 3, 0, 0.2), (0.02, 1, -3, 2.5)]
+    terms = [(np.ones_like, np.ones_like, flat, flat)]
+    for a, p1, p2, phi in waves:
+        k1, k2 = 2 * math.pi * p1 / L1, 2 * math.pi * p2 / L2
+        terms += [(lambda x, k1=k1, a=a, phi=phi: a * np.cos(k1 * x + phi), lambda y, k2=k2: np.cos(k2 * y), flat, flat),
+                  (lambda x, k1=k1, a=a, phi=phi: -a * np.sin(k1 * x + phi), lambda y, k2=k2: np.sin(k2 * y), flat, flat)]
+    st = O.project_separable(terms, ns, (0, 0, -6, -6), (L1, L2, 6, 6), 2, nq=8)
+    plan = sl.Plan(ns, 2, "fp64")
+    m, hi = upload(st, "fp64")
+    field = torch.empty(2 * ns[0] * ns[1], dtype=torch.float64, device="cuda")
+    plan.poisson_shift_2d(m, hi, h, 0.1, field_out=field)
+    X1, X2 = np.meshgrid((np.arange(ns[0]) + 0.5) * h[0], (np.arange(ns[1]) + 0.5) * h[1])
+    W1, W2 = np.zeros_like(X1), np.zeros_like(X1)
+    for a, p1, p2, phi in waves:
+        k1, k2 = 2 * math.pi * p1 / L1, 2 * math.pi * p2 / L2
+        s = a * np.sin(k1 * X1 + k2 * X2 + phi) / (k1 * k1 + k2 * k2)
+        W1 += k1 * s
+        W2 += k2 * s
+    got = field.cpu().numpy()
+    scale = max(np.max(np.abs(W1)), np.max(np.abs(W2)))
+    n = ns[0] * ns[1]
+    assert np.max(np.abs(got[:n] - W1.ravel())) <= 1e-13 * scale
+    assert np.max(np.abs(got[n:] - W2.ravel())) <= 1e-13 * scale
+
+
+def _landau4d(ns, kappa, k, eps=0.01):
+    """f = (1 + eps cos(kappa . x)) M(v1) M(v2) on the periodic box with one
+    wavelength along each x direction that kappa has a component in."""
+    L = [2 * math.pi / kk if kk else 4 * math.pi for kk in kappa]
+    M = inputs.maxwellian
+    one = np.ones_like
+    k1, k2 = kappa
+    terms = [(one, one, M, M),
+             (lambda x: eps * np.cos(k1 * x), lambda y: np.cos(k2 * y), M, M),
+             (lambda x: -eps * np.sin(k1 * x), lambda y: np.sin(k2 * y), M, M)]
+    los, his = (0.0, 0.0, -6.0, -6.0), (L[0], L[1], 6.0, 6.0)
+    st = O.project_separable(terms, ns, los, his, k)
+    h = tuple((his[e] - los[e]) / ns[e] for e in range(4))
+    return st, h
+
+
+@pytest.mark.parametrize("tier,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+def test_self_consistent_steps_match_oracle(sl, tier, tol):
+    ns, k, dt, nsteps = (8, 6, 8, 6), 2, 0.1, 5
+    st0, h = _landau4d(ns, (0.5, 2 * math.pi / (4 * math.pi) * 2), k, eps=0.05)
+    st0 = O.to_tier(st0, tier)
+    v1 = -6.0 + (np.arange(ns[2]) + 0.5) * h[2]
+    v2 = -6.0 + (np.arange(ns[3]) + 0.5) * h[3]
+    sx1, sx2 = v1 * (0.5 * dt) / h[0], v2 * (0.5 * dt) / h[1]
+    cur = st0
+    for _ in range(nsteps):
+        cur = O.sweep(cur, ns, k, 0, sx1, (2,), tier)
+        cur = O.sweep(cur, ns, k, 1, sx2, (3,), tier)
+        e1, e2 = O.poisson_shift_2d(cur, ns, h, dt)
+        cur = O.sweep(cur, ns, k, 2, e1, (0, 1), tier)
+        cur = O.sweep(cur, ns, k, 3, e2, (0, 1), tier)
+        cur = O.sweep(cur, ns, k, 0, sx1, (2,), tier)
+        cur = O.sweep(cur, ns, k, 1, sx2, (3,), tier)
+    plan = sl.Plan(ns, k, tier)
+    s0 = upload(st0, tier)
+    s1 = plan.empty_state()
+    res = plan.vlasov_poisson_steps_2d2v(nsteps, _dev(sx1), _dev(sx2), h, dt, s0, s1)
+    got = download(*(s0, s1)[res])
+    assert weighted_rel_l2(got, cur, 4, k) <= tol
+    m0 = O.mass_sum(st0[0])
+    assert abs(O.mass_sum(got[0]) - m0) <= 1e-14 * abs(m0)
+
+
+def _damping(sl, ns, kappa, k=2, dt=0.1, nsteps=230):
+    import torch
+    st0, h = _landau4d(ns, kappa, k)
+    plan = sl.Plan(ns, k, "fp32")
+    bufs = [upload(O.to_tier(st0, "fp32"), "fp32"), plan.empty_state()]
+    v1 = -6.0 + (np.arange(ns[2]) + 0.5) * h[2]
+    v2 = -6.0 + (np.arange(ns[3]) + 0.5) * h[3]
+    sx1, sx2 = _dev(v1 * (0.5 * dt) / h[0]), _dev(v2 * (0.5 * dt) / h[1])
+    nxx = ns[0] * ns[1]
+    field = torch.empty(2 * nxx, dtype=torch.float64, device="cuda")
+    sv1 = torch.empty(nxx, dtype=torch.float64, device="cuda")
+    sv2 = torch.empty(nxx, dtype=torch.float64, device="cuda")
+    cur, log_e = 0, []
+    for _ in range(nsteps):
+        plan.poisson_shift_2d(*bufs[cur], h, dt, sv1, sv2, field)
+        log_e.append(0.5 * math.log(float(torch.sum(field * field)) * h[0] * h[1]))
+        res = plan.vlasov_poisson_steps_2d2v(1, sx1, sx2, h, dt, bufs[cur], bufs[1 - cur], sv1, sv2)
+        cur = cur if res == 0 else 1 - cur
+    ts = np.arange(len(log_e)) * dt
+    le = np.array(log_e)
+    peaks = [i for i in range(1, len(ts) - 1)
+             if le[i] > le[i - 1] and le[i] > le[i + 1] and 1.0 < ts[i] < 22.0]
+    gamma = np.polyfit(ts[peaks], le[peaks], 1)[0]
+    omega = math.pi / float(np.mean(np.diff(ts[peaks])))
+    return gamma, omega
+
+
+def test_landau_damping_along_x1(sl):
+    gamma, omega = _damping(sl, (32, 4, 96, 4), (0.5, 0.0))
+    assert abs(gamma + 0.1533) < 0.03 * 0.1533, gamma
+    assert abs(omega - 1.4156) < 0.03 * 1.4156, omega
+
+
+def test_landau_damping_along_a_diagonal(sl):
+    # |kappa| = 0.5 along (1, 1): the same rate and frequency as along x1
+    # (32 x cells per wavelength in each direction, as for the x1 case; at 16
+    # the fitted rate is 3% high from the x discretisation alone)
+    kd = 0.5 / math.sqrt(2.0)
+    gamma, omega = _damping(sl, (32, 32, 48, 48), (kd, kd))
+    assert abs(gamma + 0.1533) < 0.03 * 0.1533, gamma
+    assert abs(omega - 1.4156) < 0.03 * 1.4156, omega
+
+
+def test_field_2d_entry_points_reject_bad_arguments(sl):
+    import torch
+    p2 = sl.Plan((8, 6), 1, "fp64")
+    m, hi = p2.empty_state()
+    with pytest.raises(ValueError):
+        p2.poisson_shift_2d(m, hi, (0.1,) * 4, 0.1)
+    p4 = sl.Plan((6, 4, 3, 2), 1, "fp64")
+    m, hi = p4.empty_state()
+    with pytest.raises(sl.SldgError) as ei:
+        p4.poisson_shift_2d(m, hi, (0.1, -0.1, 0.1, 0.1), 0.1)
+    assert ei.value.status == sl.SLDG_ERR_ARG
+    with pytest.raises(sl.SldgError) as ei:
+        p4.poisson_shift_2d(m, hi, (0.1,) * 4, 0.1, shift_v1=m)     # output over the state
+    assert ei.value.status == sl.SLDG_ERR_ALIAS
+    s = torch.empty(24, dtype=torch.float64, device="cuda")
+    with pytest.raises(sl.SldgError) as ei:
+        p4.poisson_shift_2d(m, hi, (0.1,) * 4, 0.1, shift_v1=s, shift_v2=s)
+    assert ei.value.status == sl.SLDG_ERR_ALIAS
