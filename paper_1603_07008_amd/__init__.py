@@ -51,6 +51,9 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libsldg.so is not built ({LIB_PATH}); run paper_1603_07008_amd/build.py")
+    # torch's HIP runtime is loaded first, so that the library binds to the
+    # same runtime (same soname) as the tensors whose pointers it is given
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, i64, i32, u32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_uint32
     L.sldg_plan.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(i64), i32, i32, vp]
