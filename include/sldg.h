@@ -189,7 +189,12 @@ sldg_status sldg_mass_device(sldg_plan_t plan, const double* mass, double* out_d
  * Launch shape of the sweeps along one dimension.  It changes how the work is
  * split between threads, never the arithmetic of an output: results are
  * bitwise the same for every shape.
- *   rows      strided sweeps (dim > 0): consecutive rows per thread, 1/2/4/8
+ *   rows      strided sweeps (dim > 0): consecutive rows per thread, 1/2/4/8.
+ *             Dimension 0, where the window form does not apply (N_0 % 4 != 0
+ *             or buffers not 16-byte aligned): 1 for the lane form (one cell
+ *             per lane), 2/4/8 for the group form (4 cells per thread), 0
+ *             (the default) for the lane form with all tuples in one run
+ *             (tuples is then ignored where the window form does not apply)
  *   tuples    spectator mode tuples per thread (0: all)
  *   colwaves  strided sweeps: waves of a workgroup side by side along the
  *             columns (1, 2 or 4; the others stack along the rows)
@@ -462,11 +467,13 @@ sldg_status sldg_batch_run(sldg_batch_t batch, int nsteps, int use_graph, int* r
 /* Launch-shape tuner: for every sweep of the sequence and every class of its
  * work list (tile kind: 0 dimension-0 window form, 1 dimension-0 group form,
  * 2 strided; x degree 1..3; class = 3 * kind + k - 1), times rows-per-thread
- * {2, 4, 8} (strided sweeps) x tuples-per-thread {1, 3, 9, all} on the bound
- * data (reads buffer 0, overwrites buffer 1) and keeps the fastest per class. */
+ * {2, 4, 8} (strided sweeps) or {4, 1} (dimension 0: the group form, or with
+ * rows 1 the lane form, one cell per lane; the window form ignores rows) x
+ * tuples-per-thread {1, 3, 9, all} on the bound data (reads buffer 0,
+ * overwrites buffer 1) and keeps the fastest per class. */
 sldg_status sldg_batch_tune(sldg_batch_t batch, int reps);
-/* Set the launch shape of every class of sweep q (rows 2, 4 or 8; tuples
- * 0 = all).  get: the shape of the class with the most tiles, and the tuned
+/* Set the launch shape of every class of sweep q (rows 2, 4 or 8, or 1 for
+ * the lane form of a dimension-0 sweep; tuples 0 = all).  get: the shape of the class with the most tiles, and the tuned
  * time of the whole sweep (-1 if not tuned). */
 sldg_status sldg_batch_get_tuning(sldg_batch_t batch, int q, int* rows, int* tuples, double* ms);
 sldg_status sldg_batch_set_tuning(sldg_batch_t batch, int q, int rows, int tuples);

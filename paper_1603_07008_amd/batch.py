@@ -196,6 +196,12 @@ class Batch:
             out.append({"rows": r.value, "tuples": t.value, "ms": ms.value, "classes": classes})
         return out
 
+    def set_class_tuning(self, q, cls, rows, tuples):
+        """Launch shape of class `cls` of sweep q alone
+        (sldg_batch_set_class_tuning)."""
+        _check(_lib().sldg_batch_set_class_tuning(self.handle, int(q), int(cls), int(rows),
+                                                  int(tuples)), "sldg_batch_set_class_tuning")
+
     def set_tuning(self, shapes):
         """Apply shapes as `tuning()` returns them (per class when given)."""
         for q, sh in enumerate(shapes):

@@ -115,6 +115,9 @@ sldg_status build_sweep(sldg_batch_s* b, int q) {
       int64_t ntab = 0;
       describe_grid(b->ndim, ext(b, p), o, b->modes[p], dim, mask, b->rows[sc], b->tuples[sc], a,
                     ntab);
+      // rows 1: the lane form of the non-window classes (the launch picks the
+      // kernel from the same rows)
+      a.lane = (kind == 1 && b->rows[sc] == 1) ? 1 : 0;
       a.in_lo = b->mass[src][p];
       a.in_hi = b->hi[src][p];
       a.out_lo = b->mass[1 - src][p];
@@ -128,7 +131,9 @@ sldg_status build_sweep(sldg_batch_s* b, int q) {
     const SweepArgs& a = args[0][p];
     const int32_t nq = (a.nspec + a.tuples - 1) / a.tuples;
     if (dim == 0) {
-      const int64_t groups = kind == 0 ? a.cells / 4 : (int64_t)a.Q * ((a.N + 3) / 4);
+      const int64_t groups = kind == 0 ? a.cells / 4
+                             : a.lane ? a.cells
+                                      : (int64_t)a.Q * ((a.N + 3) / 4);
       const int64_t tiles = (groups + 255) / 256;
       auto& bk = bucket[class_of(kind, b->k[p])];
       for (int32_t qg = 0; qg < nq; ++qg)
@@ -403,8 +408,9 @@ sldg_status sldg_batch_run(sldg_batch_t b, int nsteps, int use_graph, int* resul
 sldg_status sldg_batch_set_tuning(sldg_batch_t b, int q, int rows, int tuples) {
   if (!b) return fail(SLDG_ERR_ARG, "batch is NULL");
   if (q < 0 || q >= b->nseq) return fail(SLDG_ERR_ARG, "sweep %d out of range", q);
-  if (!(rows == 2 || rows == 4 || rows == 8) || tuples < 0)
-    return fail(SLDG_ERR_ARG, "rows %d not in {2, 4, 8} or tuples %d < 0", rows, tuples);
+  if (!(rows == 2 || rows == 4 || rows == 8 || (rows == 1 && b->dims[q] == 0)) || tuples < 0)
+    return fail(SLDG_ERR_ARG, "rows %d not in {2, 4, 8} (or 1 along dimension 0) or tuples %d < 0",
+                rows, tuples);
   for (int c = 0; c < kClasses; ++c) {
     b->rows[(size_t)q * kClasses + c] = rows;
     b->tuples[(size_t)q * kClasses + c] = tuples;
@@ -422,8 +428,9 @@ sldg_status sldg_batch_set_class_tuning(sldg_batch_t b, int q, int cls, int rows
   if (!b) return fail(SLDG_ERR_ARG, "batch is NULL");
   if (q < 0 || q >= b->nseq) return fail(SLDG_ERR_ARG, "sweep %d out of range", q);
   if (cls < 0 || cls >= kClasses) return fail(SLDG_ERR_ARG, "class %d out of range", cls);
-  if (!(rows == 2 || rows == 4 || rows == 8) || tuples < 0)
-    return fail(SLDG_ERR_ARG, "rows %d not in {2, 4, 8} or tuples %d < 0", rows, tuples);
+  if (!(rows == 2 || rows == 4 || rows == 8 || (rows == 1 && cls / 3 != 2)) || tuples < 0)
+    return fail(SLDG_ERR_ARG, "rows %d not in {2, 4, 8} (or 1 for classes 0-5) or tuples %d < 0",
+                rows, tuples);
   const size_t i = (size_t)q * kClasses + cls;
   b->rows[i] = rows;
   b->tuples[i] = tuples;
@@ -495,6 +502,7 @@ sldg_status sldg_batch_tune(sldg_batch_t b, int reps) {
     return device_error(e, "hipEventCreate");
   }
   const int rows_c[3] = {2, 4, 8};
+  const int rows_c0[2] = {4, 1};              // dimension 0: group, lane form
   const int tup_c[4] = {1, 3, 9, 0};
   sldg_status st = SLDG_OK;
   for (int q = 0; q < b->nseq && st == SLDG_OK; ++q) {
@@ -505,12 +513,12 @@ sldg_status sldg_batch_tune(sldg_batch_t b, int reps) {
       best_t[c] = b->tuples[(size_t)q * kClasses + c];
       best[c] = 1e300;
     }
-    const int nr = b->dims[q] == 0 ? 1 : 3;
+    const int nr = b->dims[q] == 0 ? 2 : 3;
     for (int ir = 0; ir < nr && st == SLDG_OK; ++ir)
       for (int it = 0; it < 4 && st == SLDG_OK; ++it) {
         // every class of the sweep takes the candidate; each class is timed alone
         for (int c = 0; c < kClasses; ++c) {
-          b->rows[(size_t)q * kClasses + c] = b->dims[q] == 0 ? 4 : rows_c[ir];
+          b->rows[(size_t)q * kClasses + c] = b->dims[q] == 0 ? rows_c0[ir] : rows_c[ir];
           b->tuples[(size_t)q * kClasses + c] = tup_c[it];
         }
         st = build_sweep(b, q);

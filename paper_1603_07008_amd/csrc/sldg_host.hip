@@ -145,6 +145,19 @@ void describe_grid(int ndim, const int64_t* n, int o, int64_t modes, int dim, ui
   ntab = str;
   a.tuples = (tuples_per_thread > 0 && tuples_per_thread < a.nspec) ? tuples_per_thread : a.nspec;
   a.colwaves = 1;
+  // dimension 0 without the window form: rows 1 asks for the lane form, 0
+  // for the automatic choice (the lane form, with every tuple in one run:
+  // a lane's share of a tuple is small, and the run amortises the line's
+  // table), anything else for the group form
+  a.lane = 0;
+  if (dim == 0) {
+    if (rows_per_thread == 1) {
+      a.lane = 1;
+    } else if (rows_per_thread == 0) {
+      a.lane = 1;
+      a.tuples = a.nspec;
+    }
+  }
   // strided sweep: rows per thread (one-shot chunks along the swept dim)
   if (dim > 0) {
     int rows = rows_per_thread;
@@ -207,8 +220,10 @@ void describe(const sldg_plan_s* p, int dim, uint32_t dep_mask, SweepArgs& a, in
 }
 
 // Launch shapes the tuner tries: (rows, tuples, column waves).  Dimension-0
-// sweeps only use the tuple count.
-constexpr int kTuneContig[][3] = {{4, 1, 1}, {4, 3, 1}, {4, 9, 1}, {4, 27, 1}, {4, 0, 1}};
+// sweeps use the tuple count, and rows to pick the group (4) or lane (1)
+// form where the window form does not apply.
+constexpr int kTuneContig[][3] = {{4, 1, 1}, {4, 3, 1}, {4, 9, 1}, {4, 27, 1}, {4, 0, 1},
+                                  {1, 1, 1}, {1, 3, 1}, {1, 9, 1}, {1, 27, 1}, {1, 0, 1}};
 constexpr int kTuneStrided[][3] = {
     {2, 1, 1},  {2, 1, 2},  {2, 1, 4},  {2, 3, 1},  {2, 3, 2},  {2, 3, 4},  {2, 9, 1},
     {2, 9, 2},  {2, 9, 4},  {2, 27, 1}, {2, 27, 2}, {2, 27, 4}, {4, 1, 1},  {4, 1, 2},
@@ -453,6 +468,7 @@ sldg_status sldg_plan_ex(sldg_plan_t* out, int ndim, const int64_t* ncells, int 
     p->tuples_d[d] = tuples;
     p->colwaves_d[d] = colwaves;
   }
+  p->rows_d[0] = 0;         // dimension 0: automatic form
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) {
     free_plan(p);
@@ -604,8 +620,8 @@ sldg_status sldg_split_steps(sldg_plan_t p, const sldg_sweep_desc* seq, int nseq
 sldg_status sldg_plan_set_shape(sldg_plan_t p, int dim, int rows, int tuples, int colwaves) {
   if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
   if (dim < 0 || dim >= p->ndim) return fail(SLDG_ERR_ARG, "dim %d out of range", dim);
-  if (!(rows == 1 || rows == 2 || rows == 4 || rows == 8))
-    return fail(SLDG_ERR_ARG, "rows %d not in {1, 2, 4, 8}", rows);
+  if (!(rows == 1 || rows == 2 || rows == 4 || rows == 8 || (dim == 0 && rows == 0)))
+    return fail(SLDG_ERR_ARG, "rows %d not in {1, 2, 4, 8}%s", rows, dim == 0 ? " or 0" : "");
   if (tuples < 0) return fail(SLDG_ERR_ARG, "tuples %d < 0", tuples);
   if (!(colwaves == 1 || colwaves == 2 || colwaves == 4))
     return fail(SLDG_ERR_ARG, "colwaves %d not in {1, 2, 4}", colwaves);
@@ -665,11 +681,17 @@ sldg_status sldg_plan_tune(sldg_plan_t p, const sldg_sweep_desc* seq, int nseq,
     }
     const bool strided = dim > 0;
     const int n = strided ? kNumTuneStrided : kNumTuneContig;
+    // the window form ignores the dimension-0 form choice: its lane variants
+    // would time the same launch again
+    const bool window = p->n[0] % 4 == 0 &&
+                        (((uintptr_t)mass0 | (uintptr_t)hi0 | (uintptr_t)mass1 | (uintptr_t)hi1) &
+                         15) == 0;
     const int keep[3] = {p->rows_d[dim], p->tuples_d[dim], p->colwaves_d[dim]};
     double best = -1.0;
     int bi = -1;
     for (int i = 0; i < n && st == SLDG_OK; ++i) {
       const int* c = strided ? kTuneStrided[i] : kTuneContig[i];
+      if (!strided && window && c[0] == 1) continue;
       p->rows_d[dim] = c[0];
       p->tuples_d[dim] = c[1];
       p->colwaves_d[dim] = c[2];

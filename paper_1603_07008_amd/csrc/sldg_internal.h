@@ -68,6 +68,7 @@ struct SweepArgs {
   int32_t chunk;          // strided sweep: rows per thread (1, 2, 4 or 8)
   int32_t tuples;         // spectator tuples per thread (a run; blockIdx.y picks it)
   int32_t colwaves;       // strided sweep: waves of a workgroup side by side (1, 2 or 4)
+  int32_t lane;           // dimension-0 sweep without the window form: 1 lane form, 0 group form
   FastDiv fP;             // division by P
   FastDiv fN;             // division by N
   FastDiv fchunk;         // division by nchunk

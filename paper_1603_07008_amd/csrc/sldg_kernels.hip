@@ -1050,6 +1050,34 @@ __device__ __forceinline__ void strided_cell(const SweepArgs& a, int32_t col, in
     strided_body<K, TIER, L, NDMAX>(a, ilow, chunk, ihigh, t, q, qe, slot, active);
 }
 
+// Dimension-0 sweep, lane form (any N_0, any alignment): one output cell per
+// lane, consecutive lanes on consecutive cells, tuples [q, qe).  A line along
+// dimension 0 is a strided line with stride P = 1 whose rows are its cells, so
+// this is the strided body with L = 1 and the lane's cell as its row chunk:
+// the two sources i-s and i-s-1 of every lane are contiguous across the wave
+// (up to the periodic wrap), one access per plane and source.  Lanes past the
+// last cell act as in contig_group.
+template <int K, int TIER, int NDMAX>
+__device__ __forceinline__ void contig_lane(const SweepArgs& a, int64_t c, int32_t q, int32_t qe,
+                                            int32_t slot) {
+  bool active = true;
+  if (c >= a.cells) {
+    if constexpr (TIER != 3) {
+      return;
+    } else {
+      if (!a.amax_part) return;
+      c = a.cells - 1;
+      active = false;
+    }
+  }
+  const int32_t line = (int32_t)a.fN.div((uint32_t)c);
+  const int32_t i = (int32_t)c - line * a.N;
+  const int32_t t = table_index(a.map, 0, line);
+  const int32_t t0 = __builtin_amdgcn_readfirstlane(t);
+  if (__all(t == t0)) strided_body<K, TIER, 1, NDMAX>(a, 0, i, line, t0, q, qe, slot, active);
+  else strided_body<K, TIER, 1, NDMAX>(a, 0, i, line, t, q, qe, slot, active);
+}
+
 // Work decomposition: a wave takes 64 consecutive columns (column =
 // ihigh * P + ilow, i.e. a cell of the transverse dimensions, consecutive
 // columns contiguous in memory), the waves of a workgroup take consecutive
@@ -1088,6 +1116,20 @@ __global__ __launch_bounds__(256) void sweep_strided_kernel(SweepArgs a) {
                                   (int32_t)(bz * gx + bx) * waves + wave);
 }
 
+template <int K, int TIER, int NDMAX>
+__global__ __launch_bounds__(256) void sweep_contig_lane_kernel(SweepArgs a) {
+  uint32_t bx = blockIdx.x, by = blockIdx.y;
+  if (a.xcd) {                 // tile order: x fastest, then y
+    const uint32_t t = xcd_tile(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y, a.xcd);
+    by = t / gridDim.x;
+    bx = t - by * gridDim.x;
+  }
+  const int64_t c = (int64_t)bx * blockDim.x + threadIdx.x;
+  const int32_t q = by * a.tuples;
+  contig_lane<K, TIER, NDMAX>(a, c, q, min(a.nspec, q + a.tuples),
+                              (int32_t)(bx * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+}
+
 bool contig_window_ok(const SweepArgs& a) {
   const uintptr_t align = (uintptr_t)a.in_lo | (uintptr_t)a.in_hi | (uintptr_t)a.out_lo |
                           (uintptr_t)a.out_hi;
@@ -1102,10 +1144,14 @@ static bool sweep_grid(int dim, const SweepArgs& a, int& form, dim3& grid, dim3&
       form = 0;
       grid = dim3((unsigned)((groups + 255) / 256), (unsigned)((a.nspec + a.tuples - 1) / a.tuples));
       block = dim3(256);
-    } else {
+    } else if (!a.lane) {
       const int64_t groups = (int64_t)a.Q * ((a.N + 3) / 4);
       form = 1;
       grid = dim3((unsigned)((groups + 255) / 256), (unsigned)((a.nspec + a.tuples - 1) / a.tuples));
+      block = dim3(256);
+    } else {
+      form = 3;
+      grid = dim3((unsigned)((a.cells + 255) / 256), (unsigned)((a.nspec + a.tuples - 1) / a.tuples));
       block = dim3(256);
     }
     return true;
@@ -1125,7 +1171,7 @@ int64_t sweep_slots(int dim, const SweepArgs& a) {
   int form;
   dim3 grid, block;
   if (!sweep_grid(dim, a, form, grid, block)) return -1;
-  if (form == 0 || form == 1) return (int64_t)grid.x * (block.x / 64);
+  if (form != 2) return (int64_t)grid.x * (block.x / 64);
   return (int64_t)grid.x * grid.z * (block.x / 64);
 }
 
@@ -1138,6 +1184,8 @@ static hipError_t launch_sweep_ktn(int dim, const SweepArgs& a, hipStream_t st) 
     sweep_contig_window_kernel<K, TIER, NDMAX><<<grid, block, 0, st>>>(a);
   } else if (form == 1) {
     sweep_contig_group_kernel<K, TIER, NDMAX><<<grid, block, 0, st>>>(a);
+  } else if (form == 3) {
+    sweep_contig_lane_kernel<K, TIER, NDMAX><<<grid, block, 0, st>>>(a);
   } else {
     switch (a.chunk) {
       case 1: sweep_strided_kernel<K, TIER, 1, NDMAX><<<grid, block, 0, st>>>(a); break;
@@ -1200,6 +1248,8 @@ __global__ __launch_bounds__(256) void batch_class_kernel(const SweepArgs* __res
     contig_group<K, TIER, 1>(a, (int64_t)w.x * blockDim.x + threadIdx.x, q, qe, 0);
   } else if constexpr (KIND == 1) {
     contig_group_any<K, TIER, 1>(a, (int64_t)w.x * blockDim.x + threadIdx.x, q, qe, 0);
+  } else if constexpr (KIND == 3) {          // kind 1 in the lane form (rows 1)
+    contig_lane<K, TIER, 1>(a, (int64_t)w.x * blockDim.x + threadIdx.x, q, qe, 0);
   } else {
     const int32_t col = w.x * 64 + (int32_t)(threadIdx.x & 63);
     const int32_t chunk = w.z * (int32_t)(blockDim.x >> 6) +
@@ -1211,7 +1261,10 @@ __global__ __launch_bounds__(256) void batch_class_kernel(const SweepArgs* __res
 template <int K, int TIER, int KIND>
 static hipError_t launch_class_ktk(int rows, const SweepArgs* args, const BatchItem* items,
                                    int32_t nitems, int32_t xcd, hipStream_t st) {
-  if constexpr (KIND != 2) {
+  if constexpr (KIND == 1) {
+    if (rows == 1) batch_class_kernel<K, TIER, 3, 1><<<nitems, 256, 0, st>>>(args, items, xcd);
+    else batch_class_kernel<K, TIER, 1, 1><<<nitems, 256, 0, st>>>(args, items, xcd);
+  } else if constexpr (KIND != 2) {
     batch_class_kernel<K, TIER, KIND, 1><<<nitems, 256, 0, st>>>(args, items, xcd);
   } else {
     switch (rows) {

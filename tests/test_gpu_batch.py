@@ -115,6 +115,36 @@ def test_graph_replays_match_eager_and_tuning_keeps_results(sl):
             assert np.array_equal(download(*(s0, s1)[res][i]), ref[0][i])
 
 
+@pytest.mark.parametrize("tier", ["fp32", "bf16"])
+def test_batch_dimension0_forms_agree_bitwise(sl, tier):
+    """Rows 1 (lane form) and 4 (group form) of the non-window dimension-0
+    classes, with one tuple or all per thread, give the same bits."""
+    import torch
+    probs = _problems()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b, c0s, s0, s1, shifts = _setup(sl, probs, tier, stream.cuda_stream)
+        init = [(m.clone(), h.clone()) for m, h in s0]
+        ref = None
+        for rows in (4, 1):
+            for tuples in (1, 0):
+                for q in (0, 2):                       # the two x-sweeps of the step
+                    for cls in (3, 4, 5):              # dimension-0 group classes, k = 1..3
+                        b.set_class_tuning(q, cls, rows, tuples)
+                for i in range(len(probs)):
+                    s0[i][0].copy_(init[i][0])
+                    s0[i][1].copy_(init[i][1])
+                res = b.run(2)
+                stream.synchronize()
+                got = [download(*(s0, s1)[res][i]) for i in range(len(probs))]
+                if ref is None:
+                    ref = got
+                else:
+                    for i in range(len(probs)):
+                        assert np.array_equal(got[i], ref[i]), (rows, tuples, i)
+        assert any(p.ns[0] % 4 for p in probs)
+
+
 def test_full_batched_workload_matches_single_plans_and_oracle(sl):
     """The batched workload at its full size (512 problems, N_x, N_v in
     32..512, k in 1..3, FP32-mode) in the launch shapes the batch tuner

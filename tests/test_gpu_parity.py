@@ -379,3 +379,79 @@ def test_leading_fp64_modes_sweeps(sl, case, tier):
         torch.cuda.synchronize()
         assert np.array_equal(download_nd(m_out, h_out, p),
                               O.sweep(state, ns, k, dim, sig_i, dep, tier, ndouble=nd))
+
+
+# ---------------------------------------------------------------------------
+# a2: the two dimension-0 forms where the window form does not apply
+# ---------------------------------------------------------------------------
+
+FORM_CASES = [
+    # (ns, k, dep of the dimension-0 sweep, ndouble)
+    ((37, 19), 3, (1,), 1),
+    ((45, 8, 6), 2, (2,), 1),
+    ((5, 7, 6), 2, (1, 2), 1),
+    ((13, 9, 4, 3), 1, (2,), 1),
+    ((21, 6, 5), 2, (2,), 2),
+    ((301, 4), 1, (1,), 1),
+]
+
+
+@pytest.mark.parametrize("tier", TIERS)
+@pytest.mark.parametrize("case", FORM_CASES, ids=[_case_id(c) for c in FORM_CASES])
+def test_dimension0_lane_and_group_forms_agree_bitwise(sl, case, tier):
+    """Rows 1 (one cell per lane), 4 (four cells per thread) and 0 (automatic)
+    give the same bits for every tuple count; one of them is checked against
+    the oracle."""
+    import torch
+    from gpu_helpers import download_nd, upload_nd
+    ns, k, dep, nd = case
+    ndim = len(ns)
+    cells = int(np.prod(ns))
+    rng = np.random.default_rng(zlib.crc32(repr(("forms", ns, k, tier, nd)).encode()))
+    state = O.to_tier(inputs.random_coefficients(ndim, k, cells, seed=int(rng.integers(1 << 30))),
+                      tier, nd, k=k, ndim=ndim)
+    p = sl.Plan(ns, k, tier, ndouble=nd)
+    m_in, h_in = upload_nd(state, p)
+    nsig = int(np.prod([ns[e] for e in dep]))
+    sig = rng.uniform(-2.5 * ns[0], 2.5 * ns[0], nsig)
+    mask = sum(1 << e for e in dep)
+    ref = None
+    for rows in (1, 4, 0):
+        for tuples in (1, 3, 0):
+            p.set_shape(0, rows, tuples)
+            m_out, h_out = p.empty_state()
+            p.advect_dim(0, _dev(sig), mask, m_in, h_in, m_out, h_out)
+            torch.cuda.synchronize()
+            got = download_nd(m_out, h_out, p)
+            if ref is None:
+                ref = got
+                keep = O.fp64_modes(ndim, k, nd).astype(bool)
+                want = O.sweep(state, ns, k, 0, sig, dep, tier, ndouble=nd)
+                mag = O.sweep(state, ns, k, 0, sig, dep, absolute=True)
+                assert_sweep_close(got, want, mag, tier, k, keep=keep,
+                                   what=f"{ns} k={k} {tier} lane form")
+            else:
+                assert np.array_equal(got, ref), (rows, tuples)
+
+
+def test_dimension0_forms_agree_bitwise_on_scaled_fp16(sl):
+    import torch
+    ns, k = (45, 8, 6), 2
+    cells = int(np.prod(ns))
+    state = inputs.random_coefficients(3, k, cells, seed=77)
+    sig = _dev(np.random.default_rng(8).uniform(-60, 60, ns[2]))
+    p = sl.Plan(ns, k, "fp16")
+    mass = _dev(state[0])
+    hi64 = _dev(state[1:])
+    hi, sc = p.empty_state()[1], p.empty_scale()
+    p.scaled_import(hi64, hi, sc)
+    outs = []
+    for rows in (1, 4):
+        p.set_shape(0, rows, 0)
+        m_out, h_out = p.empty_state()
+        s_out = p.empty_scale()
+        p.advect_dim_scaled(0, sig, 4, mass, hi, sc, m_out, h_out, s_out)
+        torch.cuda.synchronize()
+        outs.append((m_out.cpu(), h_out.view(torch.int16).cpu(), s_out.cpu()))
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
