@@ -112,6 +112,29 @@ def measured_plane_copy(sl, torch, cells, nplanes, tiers=(1, 3, 9, 27), reps=10)
     return out
 
 
+def sweep_kernel_name(ns, k, tier, d, shape):
+    """The template instance the library launches for the sweep along d (as
+    the profiler names it): the window or lane form along dimension 0; the
+    strided kernel with its rows per thread and whether its one-value-per-lane
+    stores carry the non-temporal hint (a wave's stores cover whole 128-byte
+    lines: the column stride P is a multiple of 64, or P times the value size
+    a multiple of 128 bytes; the narrow value size for FP32, else 8 bytes)."""
+    tid = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}[tier]
+    if d == 0:
+        if ns[0] % 4 == 0:
+            return f"sldg::sweep_contig_window_kernel<{k}, {tid}, 1>"
+        return f"sldg::sweep_contig_lane_kernel<{k}, {tid}, 1, true>"
+    P = 1
+    for e in range(d):
+        P *= ns[e]
+    size = 4 if tier == "fp32" else 8
+    nt = P % 64 == 0 or (P * size) % 128 == 0
+    rows = shape["rows"]
+    while rows > 1 and rows > ns[d]:
+        rows //= 2
+    return f"sldg::sweep_strided_kernel<{k}, {tid}, {rows}, 1, {'true' if nt else 'false'}>"
+
+
 def run_tier(sl, torch, prob, tier, init, steps, warmup, tune_cache=None, single_reps=20):
     """Time `steps` split steps (after `warmup`) of `prob` in `tier`."""
     p = sl.Plan(prob.ns, prob.k, tier)
@@ -151,12 +174,10 @@ def run_tier(sl, torch, prob, tier, init, steps, warmup, tune_cache=None, single
     ms = ev0.elapsed_time(ev1) / steps
     p.timing_enable(False)
     tid = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}[tier]
-    contig = "sweep_contig_window_kernel" if prob.ns[0] % 4 == 0 else "sweep_contig_kernel"
     per_dim = {d: p.timing_read(d) for d in range(prob.ndim)}
     kern = {}                       # kernel (template instance) -> (launches, total ms)
     for d, (n, tot) in per_dim.items():
-        name = (f"sldg::{contig}<{prob.k}, {tid}, 1>" if d == 0 else
-                f"sldg::sweep_strided_kernel<{prob.k}, {tid}, {shapes[d]['rows']}, 1>")
+        name = sweep_kernel_name(prob.ns, prob.k, tier, d, shapes[d])
         n0, t0 = kern.get(name, (0, 0.0))
         kern[name] = (n0 + n, t0 + tot)
     m_end = p.mass(bufs[cur][0])

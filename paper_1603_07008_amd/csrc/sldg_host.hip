@@ -168,6 +168,15 @@ void describe_grid(int ndim, const int64_t* n, int o, int64_t modes, int dim, ui
     a.chunk = a.N;
     a.nchunk = 1;
   }
+  // non-temporal stores where every store of a wave writes whole 128-byte
+  // lines: dimension 0 (consecutive lanes on consecutive cells; the group
+  // form stores without the hint), and strided sweeps whose 64 columns of a
+  // wave are one run (P % 64 == 0) or runs of whole lines (P * size % 128 == 0)
+  a.ntmask = 0;
+  for (int b = 0; b < 2; ++b) {
+    const int64_t size = b ? 8 : 4;
+    if (dim == 0 || P % 64 == 0 || (P * size) % 128 == 0) a.ntmask |= 1 << b;
+  }
   a.fP = FastDiv::make((uint32_t)a.P);
   a.fN = FastDiv::make((uint32_t)a.N);
   a.fchunk = FastDiv::make((uint32_t)a.nchunk);

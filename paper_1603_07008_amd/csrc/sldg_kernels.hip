@@ -23,6 +23,33 @@
 
 namespace sldg {
 
+// Stores of the sweeps' outputs.  Every output coefficient is written once
+// per sweep and not read again by it, so stores whose wave writes whole
+// 128-byte lines carry the non-temporal hint, which raises the HBM rate of
+// this pattern: the window form's 16 bytes per lane, and 4- or 8-byte values
+// one per lane (kernels instantiated with NT) where the host found the wave's
+// cells to cover whole lines (SweepArgs::ntmask).  Stores that leave partial
+// lines (2-byte values, the group form's 4 cells per lane, strided rows of 48
+// FP32 cells) stay plain: there the hint measured slower.  The choice is made
+// at compile time: a run-time branch between the two stores is merged by the
+// compiler into one plain store.  Loads stay plain (the hint evicts the
+// neighbouring cells that the next lanes and rows read again).
+template <class T>
+__device__ __forceinline__ void st_stream(T* p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+
+template <bool NT, class T>
+__device__ __forceinline__ void st_lane(T* p, T v) {
+  if constexpr (NT && sizeof(T) >= 4) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef uint32_t nt_u2 __attribute__((ext_vector_type(2)));
+
+
 // ---------------------------------------------------------------------------
 // Storage tiers (section II-A: c_0 in FP64, the higher modes narrower)
 // ---------------------------------------------------------------------------
@@ -411,6 +438,7 @@ struct Planes {
       return narrow<T>(acc);
     }
   }
+  template <bool NT>
   __device__ __forceinline__ void store(int64_t c, const Mat<K, TIER>& M, const Rows64<K, ND>& R,
                                         const Raw<K, TIER, ND>& x, const Raw<K, TIER, ND>& y,
                                         float (&am)[O], bool active) const {
@@ -418,10 +446,10 @@ struct Planes {
     for (int j = 0; j < O; ++j) {
       if (j < ND) {
         const double v = Mat<K, TIER>::out64(R, j, x, y);
-        if (active) outd[j][c] = v;
+        if (active) st_lane<NT>(outd[j] + c, v);
       } else {
         const T v = put(j, M.out_acc(j, x, y), am);
-        if (active) outh[j][c] = v;
+        if (active) st_lane<NT>(outh[j] + c, v);
       }
     }
   }
@@ -490,8 +518,8 @@ struct Blk4 { T v[4]; };
 template <class T>
 struct Raw4 {
   using V = typename std::conditional<
-      sizeof(T) == 8, double2,
-      typename std::conditional<sizeof(T) == 4, float4, uint2>::type>::type;
+      sizeof(T) == 8, nt_d2,
+      typename std::conditional<sizeof(T) == 4, nt_f4, nt_u2>::type>::type;
   static constexpr int W = sizeof(T) == 8 ? 2 : 1;
   V v[W];
 };
@@ -513,7 +541,7 @@ __device__ __forceinline__ Blk4<T> unpack4(const Raw4<T>& w) {
   } else if constexpr (sizeof(T) == 4) {
     r.v[0] = w.v[0].x; r.v[1] = w.v[0].y; r.v[2] = w.v[0].z; r.v[3] = w.v[0].w;
   } else {
-    const uint2 a = w.v[0];
+    const nt_u2 a = w.v[0];
     r.v[0] = __builtin_bit_cast(T, (uint16_t)(a.x & 0xffff));
     r.v[1] = __builtin_bit_cast(T, (uint16_t)(a.x >> 16));
     r.v[2] = __builtin_bit_cast(T, (uint16_t)(a.y & 0xffff));
@@ -525,17 +553,17 @@ __device__ __forceinline__ Blk4<T> unpack4(const Raw4<T>& w) {
 template <class T>
 __device__ __forceinline__ void store4(T* dst, const T (&v)[4]) {
   if constexpr (sizeof(T) == 8) {
-    double2* d = reinterpret_cast<double2*>(dst);
-    d[0] = make_double2(v[0], v[1]);
-    d[1] = make_double2(v[2], v[3]);
+    nt_d2* d = reinterpret_cast<nt_d2*>(dst);
+    st_stream(d, nt_d2{v[0], v[1]});
+    st_stream(d + 1, nt_d2{v[2], v[3]});
   } else if constexpr (sizeof(T) == 4) {
-    *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+    st_stream(reinterpret_cast<nt_f4*>(dst), nt_f4{v[0], v[1], v[2], v[3]});
   } else {
     uint16_t b[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) b[u] = __builtin_bit_cast(uint16_t, v[u]);
-    *reinterpret_cast<uint2*>(dst) = make_uint2((uint32_t)b[0] | ((uint32_t)b[1] << 16),
-                                                (uint32_t)b[2] | ((uint32_t)b[3] << 16));
+    st_stream(reinterpret_cast<nt_u2*>(dst), nt_u2{(uint32_t)b[0] | ((uint32_t)b[1] << 16),
+                                                   (uint32_t)b[2] | ((uint32_t)b[3] << 16)});
   }
 }
 
@@ -914,7 +942,7 @@ __device__ __forceinline__ void strided_load(const Planes<K, TIER, ND>& pl, int6
   for (int u = 0; u <= L; ++u) pl.load(base + roff[u], R.v[u]);
 }
 
-template <int K, int TIER, int ND, int L>
+template <int K, int TIER, int ND, int L, bool NT>
 __device__ __forceinline__ void strided_store(const SweepArgs& a, const Planes<K, TIER, ND>& pl,
                                               int64_t base, int32_t r0, int32_t n,
                                               const Mat<K, TIER>& M, const Rows64<K, ND>& R64,
@@ -926,16 +954,17 @@ __device__ __forceinline__ void strided_store(const SweepArgs& a, const Planes<K
   if (n == L) {            // full chunk: no per-row predicate
 #pragma unroll
     for (int u = 0; u < L; ++u)
-      pl.store(base + (int64_t)(r0 + u) * P, M, R64, R.v[u + 1], R.v[u], am, active);
+      pl.template store<NT>(base + (int64_t)(r0 + u) * P, M, R64, R.v[u + 1], R.v[u], am, active);
   } else {                 // the last chunk of a line whose length L does not divide
 #pragma unroll
     for (int u = 0; u < L; ++u)
-      if (u < n) pl.store(base + (int64_t)(r0 + u) * P, M, R64, R.v[u + 1], R.v[u], am, active);
+      if (u < n)
+        pl.template store<NT>(base + (int64_t)(r0 + u) * P, M, R64, R.v[u + 1], R.v[u], am, active);
   }
   flush_amax<K, TIER, ND>(a, pl, am, slot);
 }
 
-template <int K, int TIER, int ND, int L>
+template <int K, int TIER, int ND, int L, bool NT>
 __device__ __forceinline__ void strided_single(const SweepArgs& a, const TupleMap& tm,
                                                const Mat<K, TIER>& M, int64_t base,
                                                const int32_t (&roff)[L + 1], int32_t r0,
@@ -946,10 +975,10 @@ __device__ __forceinline__ void strided_single(const SweepArgs& a, const TupleMa
   R64.load(M.ab, M.cs);
   Rows<K, TIER, ND, L> R;
   strided_load<K, TIER, ND, L>(pl, base, roff, R);
-  strided_store<K, TIER, ND, L>(a, pl, base, r0, n, M, R64, R, slot, active);
+  strided_store<K, TIER, ND, L, NT>(a, pl, base, r0, n, M, R64, R, slot, active);
 }
 
-template <int K, int TIER, int L, int NDMAX>
+template <int K, int TIER, int L, int NDMAX, bool NT>
 __device__ __forceinline__ void strided_body(const SweepArgs& a, int32_t ilow, int32_t chunk,
                                              int32_t ihigh, int32_t t, int32_t q, int32_t qe,
                                              int32_t slot, bool active) {
@@ -985,7 +1014,7 @@ __device__ __forceinline__ void strided_body(const SweepArgs& a, int32_t ilow, i
     const TupleMap tm = tuple_map<NDMAX>(a, m0, ms, O);
     if (tm.nd != 0) {
       dispatch_nd<NDMAX>(tm.nd, [&](auto ndc) {
-        strided_single<K, TIER, decltype(ndc)::value, L>(a, tm, M, base, roff, r0, n, slot,
+        strided_single<K, TIER, decltype(ndc)::value, L, NT>(a, tm, M, base, roff, r0, n, slot,
                                                          active);
       });
       advance(q, low, m0);
@@ -1011,10 +1040,10 @@ __device__ __forceinline__ void strided_body(const SweepArgs& a, int32_t ilow, i
     };
     for (;;) {
       const bool mb = next(pb, rb);
-      strided_store<K, TIER, 0, L>(a, pa, base, r0, n, M, R64, ra, slot, active);
+      strided_store<K, TIER, 0, L, NT>(a, pa, base, r0, n, M, R64, ra, slot, active);
       if (!mb) break;
       const bool ma = next(pa, ra);
-      strided_store<K, TIER, 0, L>(a, pb, base, r0, n, M, R64, rb, slot, active);
+      strided_store<K, TIER, 0, L, NT>(a, pb, base, r0, n, M, R64, rb, slot, active);
       if (!ma) break;
     }
   }
@@ -1024,7 +1053,7 @@ __device__ __forceinline__ void strided_body(const SweepArgs& a, int32_t ilow, i
 // chunk is uniform across a wave; in a scaled FP16 sweep, lanes past the
 // last column redo the last column without storing it, so that whole waves
 // reach the absmax reductions.
-template <int K, int TIER, int L, int NDMAX>
+template <int K, int TIER, int L, int NDMAX, bool NT>
 __device__ __forceinline__ void strided_cell(const SweepArgs& a, int32_t col, int32_t chunk,
                                              int32_t q, int32_t qe, int32_t slot) {
   if (chunk >= a.nchunk) return;
@@ -1045,9 +1074,9 @@ __device__ __forceinline__ void strided_cell(const SweepArgs& a, int32_t col, in
   const int32_t t = table_index(a.map, ilow, ihigh);
   const int32_t t0 = __builtin_amdgcn_readfirstlane(t);
   if (__all(t == t0))
-    strided_body<K, TIER, L, NDMAX>(a, ilow, chunk, ihigh, t0, q, qe, slot, active);
+    strided_body<K, TIER, L, NDMAX, NT>(a, ilow, chunk, ihigh, t0, q, qe, slot, active);
   else
-    strided_body<K, TIER, L, NDMAX>(a, ilow, chunk, ihigh, t, q, qe, slot, active);
+    strided_body<K, TIER, L, NDMAX, NT>(a, ilow, chunk, ihigh, t, q, qe, slot, active);
 }
 
 // Dimension-0 sweep, lane form (any N_0, any alignment): one output cell per
@@ -1057,7 +1086,7 @@ __device__ __forceinline__ void strided_cell(const SweepArgs& a, int32_t col, in
 // the two sources i-s and i-s-1 of every lane are contiguous across the wave
 // (up to the periodic wrap), one access per plane and source.  Lanes past the
 // last cell act as in contig_group.
-template <int K, int TIER, int NDMAX>
+template <int K, int TIER, int NDMAX, bool NT>
 __device__ __forceinline__ void contig_lane(const SweepArgs& a, int64_t c, int32_t q, int32_t qe,
                                             int32_t slot) {
   bool active = true;
@@ -1074,8 +1103,8 @@ __device__ __forceinline__ void contig_lane(const SweepArgs& a, int64_t c, int32
   const int32_t i = (int32_t)c - line * a.N;
   const int32_t t = table_index(a.map, 0, line);
   const int32_t t0 = __builtin_amdgcn_readfirstlane(t);
-  if (__all(t == t0)) strided_body<K, TIER, 1, NDMAX>(a, 0, i, line, t0, q, qe, slot, active);
-  else strided_body<K, TIER, 1, NDMAX>(a, 0, i, line, t, q, qe, slot, active);
+  if (__all(t == t0)) strided_body<K, TIER, 1, NDMAX, NT>(a, 0, i, line, t0, q, qe, slot, active);
+  else strided_body<K, TIER, 1, NDMAX, NT>(a, 0, i, line, t, q, qe, slot, active);
 }
 
 // Work decomposition: a wave takes 64 consecutive columns (column =
@@ -1088,7 +1117,7 @@ __device__ __forceinline__ void contig_lane(const SweepArgs& a, int64_t c, int32
 // over the XCDs so that tiles sharing lines (the halo row between row chunk
 // groups, the cache lines split between column blocks when the rows are
 // short) run on one XCD, one after the other.
-template <int K, int TIER, int L, int NDMAX>
+template <int K, int TIER, int L, int NDMAX, bool NT>
 __global__ __launch_bounds__(256) void sweep_strided_kernel(SweepArgs a) {
   uint32_t bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
   const uint32_t gx = gridDim.x, gz = gridDim.z;
@@ -1112,11 +1141,11 @@ __global__ __launch_bounds__(256) void sweep_strided_kernel(SweepArgs a) {
   const int32_t col = ((int32_t)bx * cw + wc) * 64 + (int32_t)(threadIdx.x & 63);
   const int32_t chunk = (int32_t)bz * zw + wz;
   const int32_t q = by * a.tuples;
-  strided_cell<K, TIER, L, NDMAX>(a, col, chunk, q, min(a.nspec, q + a.tuples),
+  strided_cell<K, TIER, L, NDMAX, NT>(a, col, chunk, q, min(a.nspec, q + a.tuples),
                                   (int32_t)(bz * gx + bx) * waves + wave);
 }
 
-template <int K, int TIER, int NDMAX>
+template <int K, int TIER, int NDMAX, bool NT>
 __global__ __launch_bounds__(256) void sweep_contig_lane_kernel(SweepArgs a) {
   uint32_t bx = blockIdx.x, by = blockIdx.y;
   if (a.xcd) {                 // tile order: x fastest, then y
@@ -1126,7 +1155,7 @@ __global__ __launch_bounds__(256) void sweep_contig_lane_kernel(SweepArgs a) {
   }
   const int64_t c = (int64_t)bx * blockDim.x + threadIdx.x;
   const int32_t q = by * a.tuples;
-  contig_lane<K, TIER, NDMAX>(a, c, q, min(a.nspec, q + a.tuples),
+  contig_lane<K, TIER, NDMAX, NT>(a, c, q, min(a.nspec, q + a.tuples),
                               (int32_t)(bx * (blockDim.x >> 6) + (threadIdx.x >> 6)));
 }
 
@@ -1175,6 +1204,12 @@ int64_t sweep_slots(int dim, const SweepArgs& a) {
   return (int64_t)grid.x * grid.z * (block.x / 64);
 }
 
+template <int K, int TIER, int L, int NDMAX>
+static void launch_strided(bool nt, dim3 grid, dim3 block, hipStream_t st, const SweepArgs& a) {
+  if (nt) sweep_strided_kernel<K, TIER, L, NDMAX, true><<<grid, block, 0, st>>>(a);
+  else sweep_strided_kernel<K, TIER, L, NDMAX, false><<<grid, block, 0, st>>>(a);
+}
+
 template <int K, int TIER, int NDMAX>
 static hipError_t launch_sweep_ktn(int dim, const SweepArgs& a, hipStream_t st) {
   int form;
@@ -1185,13 +1220,18 @@ static hipError_t launch_sweep_ktn(int dim, const SweepArgs& a, hipStream_t st) 
   } else if (form == 1) {
     sweep_contig_group_kernel<K, TIER, NDMAX><<<grid, block, 0, st>>>(a);
   } else if (form == 3) {
-    sweep_contig_lane_kernel<K, TIER, NDMAX><<<grid, block, 0, st>>>(a);
+    // dimension 0: the lanes' cells are consecutive, whole lines per wave
+    sweep_contig_lane_kernel<K, TIER, NDMAX, true><<<grid, block, 0, st>>>(a);
   } else {
+    // the narrow planes' value size decides (the FP64 mean is stored with
+    // the hint under the same test whenever 2-byte planes go without it)
+    const int bit = TIER == 1 ? 1 : 2;
+    const bool nt = (a.ntmask & bit) != 0;
     switch (a.chunk) {
-      case 1: sweep_strided_kernel<K, TIER, 1, NDMAX><<<grid, block, 0, st>>>(a); break;
-      case 2: sweep_strided_kernel<K, TIER, 2, NDMAX><<<grid, block, 0, st>>>(a); break;
-      case 4: sweep_strided_kernel<K, TIER, 4, NDMAX><<<grid, block, 0, st>>>(a); break;
-      case 8: sweep_strided_kernel<K, TIER, 8, NDMAX><<<grid, block, 0, st>>>(a); break;
+      case 1: launch_strided<K, TIER, 1, NDMAX>(nt, grid, block, st, a); break;
+      case 2: launch_strided<K, TIER, 2, NDMAX>(nt, grid, block, st, a); break;
+      case 4: launch_strided<K, TIER, 4, NDMAX>(nt, grid, block, st, a); break;
+      case 8: launch_strided<K, TIER, 8, NDMAX>(nt, grid, block, st, a); break;
       default: return hipErrorInvalidValue;
     }
   }
@@ -1249,12 +1289,12 @@ __global__ __launch_bounds__(256) void batch_class_kernel(const SweepArgs* __res
   } else if constexpr (KIND == 1) {
     contig_group_any<K, TIER, 1>(a, (int64_t)w.x * blockDim.x + threadIdx.x, q, qe, 0);
   } else if constexpr (KIND == 3) {          // kind 1 in the lane form (rows 1)
-    contig_lane<K, TIER, 1>(a, (int64_t)w.x * blockDim.x + threadIdx.x, q, qe, 0);
+    contig_lane<K, TIER, 1, false>(a, (int64_t)w.x * blockDim.x + threadIdx.x, q, qe, 0);
   } else {
     const int32_t col = w.x * 64 + (int32_t)(threadIdx.x & 63);
     const int32_t chunk = w.z * (int32_t)(blockDim.x >> 6) +
                           __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
-    strided_cell<K, TIER, L, 1>(a, col, chunk, q, qe, 0);
+    strided_cell<K, TIER, L, 1, false>(a, col, chunk, q, qe, 0);
   }
 }
 
