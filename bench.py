@@ -123,7 +123,9 @@ def sweep_kernel_name(ns, k, tier, d, shape):
     if d == 0:
         if ns[0] % 4 == 0:
             return f"sldg::sweep_contig_window_kernel<{k}, {tid}, 1>"
-        return f"sldg::sweep_contig_lane_kernel<{k}, {tid}, 1, true>"
+        return f"sldg::sweep_lane_kernel<{k}, {tid}, 1, true>"
+    if shape["rows"] == 0:
+        return f"sldg::sweep_lane_kernel<{k}, {tid}, 1, true>"
     P = 1
     for e in range(d):
         P *= ns[e]

@@ -189,11 +189,12 @@ sldg_status sldg_mass_device(sldg_plan_t plan, const double* mass, double* out_d
  * Launch shape of the sweeps along one dimension.  It changes how the work is
  * split between threads, never the arithmetic of an output: results are
  * bitwise the same for every shape.
- *   rows      strided sweeps (dim > 0): consecutive rows per thread, 1/2/4/8.
- *             Dimension 0, where the window form does not apply (N_0 % 4 != 0
- *             or buffers not 16-byte aligned): 1 for the lane form (one cell
- *             per lane), 2/4/8 for the group form (4 cells per thread), 0
- *             (the default) for the lane form with all tuples in one run
+ *   rows      strided sweeps (dim > 0): consecutive rows per thread, 1/2/4/8,
+ *             or 0 for the lane form (one cell per lane, consecutive lanes on
+ *             consecutive cells).  Dimension 0, where the window form does
+ *             not apply (N_0 % 4 != 0 or buffers not 16-byte aligned): 1 for
+ *             the lane form, 2/4/8 for the group form (4 cells per thread),
+ *             0 (the default) for the lane form with all tuples in one run
  *             (tuples is then ignored where the window form does not apply)
  *   tuples    spectator mode tuples per thread (0: all)
  *   colwaves  strided sweeps: waves of a workgroup side by side along the

@@ -157,10 +157,12 @@ void describe_grid(int ndim, const int64_t* n, int o, int64_t modes, int dim, ui
       a.lane = 1;
       a.tuples = a.nspec;
     }
+  } else if (rows_per_thread == 0) {
+    a.lane = 1;               // strided sweep in the lane form (one cell per lane)
   }
   // strided sweep: rows per thread (one-shot chunks along the swept dim)
   if (dim > 0) {
-    int rows = rows_per_thread;
+    int rows = a.lane ? 1 : rows_per_thread;
     while (rows > 1 && rows > a.N) rows >>= 1;
     a.chunk = rows;
     a.nchunk = (int32_t)((a.N + rows - 1) / rows);
@@ -175,7 +177,7 @@ void describe_grid(int ndim, const int64_t* n, int o, int64_t modes, int dim, ui
   a.ntmask = 0;
   for (int b = 0; b < 2; ++b) {
     const int64_t size = b ? 8 : 4;
-    if (dim == 0 || P % 64 == 0 || (P * size) % 128 == 0) a.ntmask |= 1 << b;
+    if (dim == 0 || a.lane || P % 64 == 0 || (P * size) % 128 == 0) a.ntmask |= 1 << b;
   }
   a.fP = FastDiv::make((uint32_t)a.P);
   a.fN = FastDiv::make((uint32_t)a.N);
@@ -230,7 +232,8 @@ void describe(const sldg_plan_s* p, int dim, uint32_t dep_mask, SweepArgs& a, in
 
 // Launch shapes the tuner tries: (rows, tuples, column waves).  Dimension-0
 // sweeps use the tuple count, and rows to pick the group (4) or lane (1)
-// form where the window form does not apply.
+// form where the window form does not apply; strided sweeps with rows 0 run
+// in the lane form.
 constexpr int kTuneContig[][3] = {{4, 1, 1}, {4, 3, 1}, {4, 9, 1}, {4, 27, 1}, {4, 0, 1},
                                   {1, 1, 1}, {1, 3, 1}, {1, 9, 1}, {1, 27, 1}, {1, 0, 1}};
 constexpr int kTuneStrided[][3] = {
@@ -239,7 +242,7 @@ constexpr int kTuneStrided[][3] = {
     {4, 1, 4},  {4, 3, 1},  {4, 3, 2},  {4, 3, 4},  {4, 9, 1},  {4, 9, 2},  {4, 9, 4},
     {4, 27, 1}, {4, 27, 2}, {4, 27, 4}, {8, 1, 1},  {8, 1, 2},  {8, 1, 4},  {8, 3, 1},
     {8, 3, 2},  {8, 3, 4},  {8, 9, 1},  {8, 9, 2},  {8, 9, 4},  {8, 27, 1}, {8, 27, 2},
-    {8, 27, 4}};
+    {8, 27, 4}, {0, 1, 1},  {0, 3, 1},  {0, 9, 1},  {0, 27, 1}, {0, 0, 1}};
 constexpr int kNumTuneContig = sizeof(kTuneContig) / sizeof(kTuneContig[0]);
 constexpr int kNumTuneStrided = sizeof(kTuneStrided) / sizeof(kTuneStrided[0]);
 
@@ -629,8 +632,8 @@ sldg_status sldg_split_steps(sldg_plan_t p, const sldg_sweep_desc* seq, int nseq
 sldg_status sldg_plan_set_shape(sldg_plan_t p, int dim, int rows, int tuples, int colwaves) {
   if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
   if (dim < 0 || dim >= p->ndim) return fail(SLDG_ERR_ARG, "dim %d out of range", dim);
-  if (!(rows == 1 || rows == 2 || rows == 4 || rows == 8 || (dim == 0 && rows == 0)))
-    return fail(SLDG_ERR_ARG, "rows %d not in {1, 2, 4, 8}%s", rows, dim == 0 ? " or 0" : "");
+  if (!(rows == 0 || rows == 1 || rows == 2 || rows == 4 || rows == 8))
+    return fail(SLDG_ERR_ARG, "rows %d not in {0, 1, 2, 4, 8}", rows);
   if (tuples < 0) return fail(SLDG_ERR_ARG, "tuples %d < 0", tuples);
   if (!(colwaves == 1 || colwaves == 2 || colwaves == 4))
     return fail(SLDG_ERR_ARG, "colwaves %d not in {1, 2, 4}", colwaves);

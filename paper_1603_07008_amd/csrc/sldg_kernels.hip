@@ -1079,16 +1079,18 @@ __device__ __forceinline__ void strided_cell(const SweepArgs& a, int32_t col, in
     strided_body<K, TIER, L, NDMAX, NT>(a, ilow, chunk, ihigh, t, q, qe, slot, active);
 }
 
-// Dimension-0 sweep, lane form (any N_0, any alignment): one output cell per
-// lane, consecutive lanes on consecutive cells, tuples [q, qe).  A line along
-// dimension 0 is a strided line with stride P = 1 whose rows are its cells, so
-// this is the strided body with L = 1 and the lane's cell as its row chunk:
-// the two sources i-s and i-s-1 of every lane are contiguous across the wave
-// (up to the periodic wrap), one access per plane and source.  Lanes past the
-// last cell act as in contig_group.
+// Lane form of a sweep along any dimension: one output cell per lane,
+// consecutive lanes on consecutive cells, tuples [q, qe).  Cell c is
+// (ilow, row, ihigh) with c = (ihigh * N + row) * P + ilow, and the sweep of
+// its column is the strided body with L = 1 and the cell's row as its row
+// chunk: the sources c - s P and c - (s+1) P of a wave's lanes are contiguous
+// (up to the periodic wrap), one access per plane and source, and every
+// store of a wave writes 64 consecutive cells.  Along dimension 0 (P = 1) the
+// column is the line itself.  Lanes past the last cell act as in
+// contig_group.
 template <int K, int TIER, int NDMAX, bool NT>
-__device__ __forceinline__ void contig_lane(const SweepArgs& a, int64_t c, int32_t q, int32_t qe,
-                                            int32_t slot) {
+__device__ __forceinline__ void lane_cell(const SweepArgs& a, int64_t c, int32_t q, int32_t qe,
+                                          int32_t slot) {
   bool active = true;
   if (c >= a.cells) {
     if constexpr (TIER != 3) {
@@ -1099,12 +1101,17 @@ __device__ __forceinline__ void contig_lane(const SweepArgs& a, int64_t c, int32
       active = false;
     }
   }
-  const int32_t line = (int32_t)a.fN.div((uint32_t)c);
-  const int32_t i = (int32_t)c - line * a.N;
-  const int32_t t = table_index(a.map, 0, line);
+  const uint32_t rest = a.fP.div((uint32_t)c);
+  const int32_t ilow = (int32_t)c - (int32_t)rest * a.P;
+  const uint32_t ih = a.fN.div(rest);
+  const int32_t row = (int32_t)rest - (int32_t)ih * a.N;
+  const int32_t ihigh = (int32_t)ih;
+  const int32_t t = table_index(a.map, ilow, ihigh);
   const int32_t t0 = __builtin_amdgcn_readfirstlane(t);
-  if (__all(t == t0)) strided_body<K, TIER, 1, NDMAX, NT>(a, 0, i, line, t0, q, qe, slot, active);
-  else strided_body<K, TIER, 1, NDMAX, NT>(a, 0, i, line, t, q, qe, slot, active);
+  if (__all(t == t0))
+    strided_body<K, TIER, 1, NDMAX, NT>(a, ilow, row, ihigh, t0, q, qe, slot, active);
+  else
+    strided_body<K, TIER, 1, NDMAX, NT>(a, ilow, row, ihigh, t, q, qe, slot, active);
 }
 
 // Work decomposition: a wave takes 64 consecutive columns (column =
@@ -1146,7 +1153,7 @@ __global__ __launch_bounds__(256) void sweep_strided_kernel(SweepArgs a) {
 }
 
 template <int K, int TIER, int NDMAX, bool NT>
-__global__ __launch_bounds__(256) void sweep_contig_lane_kernel(SweepArgs a) {
+__global__ __launch_bounds__(256) void sweep_lane_kernel(SweepArgs a) {
   uint32_t bx = blockIdx.x, by = blockIdx.y;
   if (a.xcd) {                 // tile order: x fastest, then y
     const uint32_t t = xcd_tile(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y, a.xcd);
@@ -1155,7 +1162,7 @@ __global__ __launch_bounds__(256) void sweep_contig_lane_kernel(SweepArgs a) {
   }
   const int64_t c = (int64_t)bx * blockDim.x + threadIdx.x;
   const int32_t q = by * a.tuples;
-  contig_lane<K, TIER, NDMAX, NT>(a, c, q, min(a.nspec, q + a.tuples),
+  lane_cell<K, TIER, NDMAX, NT>(a, c, q, min(a.nspec, q + a.tuples),
                               (int32_t)(bx * (blockDim.x >> 6) + (threadIdx.x >> 6)));
 }
 
@@ -1167,6 +1174,12 @@ bool contig_window_ok(const SweepArgs& a) {
 
 // Launch shape of a sweep: form 0 window, 1 generic dimension-0, 2 strided.
 static bool sweep_grid(int dim, const SweepArgs& a, int& form, dim3& grid, dim3& block) {
+  if (dim > 0 && a.lane) {
+    form = 3;
+    grid = dim3((unsigned)((a.cells + 255) / 256), (unsigned)((a.nspec + a.tuples - 1) / a.tuples));
+    block = dim3(256);
+    return true;
+  }
   if (dim == 0) {
     if (contig_window_ok(a)) {
       const int64_t groups = a.cells >> 2;
@@ -1220,8 +1233,8 @@ static hipError_t launch_sweep_ktn(int dim, const SweepArgs& a, hipStream_t st) 
   } else if (form == 1) {
     sweep_contig_group_kernel<K, TIER, NDMAX><<<grid, block, 0, st>>>(a);
   } else if (form == 3) {
-    // dimension 0: the lanes' cells are consecutive, whole lines per wave
-    sweep_contig_lane_kernel<K, TIER, NDMAX, true><<<grid, block, 0, st>>>(a);
+    // the lanes' cells are consecutive: whole lines per wave
+    sweep_lane_kernel<K, TIER, NDMAX, true><<<grid, block, 0, st>>>(a);
   } else {
     // the narrow planes' value size decides (the FP64 mean is stored with
     // the hint under the same test whenever 2-byte planes go without it)
@@ -1289,7 +1302,7 @@ __global__ __launch_bounds__(256) void batch_class_kernel(const SweepArgs* __res
   } else if constexpr (KIND == 1) {
     contig_group_any<K, TIER, 1>(a, (int64_t)w.x * blockDim.x + threadIdx.x, q, qe, 0);
   } else if constexpr (KIND == 3) {          // kind 1 in the lane form (rows 1)
-    contig_lane<K, TIER, 1, false>(a, (int64_t)w.x * blockDim.x + threadIdx.x, q, qe, 0);
+    lane_cell<K, TIER, 1, false>(a, (int64_t)w.x * blockDim.x + threadIdx.x, q, qe, 0);
   } else {
     const int32_t col = w.x * 64 + (int32_t)(threadIdx.x & 63);
     const int32_t chunk = w.z * (int32_t)(blockDim.x >> 6) +

@@ -455,3 +455,52 @@ def test_dimension0_forms_agree_bitwise_on_scaled_fp16(sl):
         outs.append((m_out.cpu(), h_out.view(torch.int16).cpu(), s_out.cpu()))
     for a, b in zip(*outs):
         assert torch.equal(a, b)
+
+
+STRIDED_FORM_CASES = [
+    # (ns, k, swept dim, dep, ndouble)
+    ((37, 19), 3, 1, (0,), 1),
+    ((5, 7, 6), 2, 1, (0, 2), 1),
+    ((5, 7, 6), 2, 2, (0,), 1),
+    ((13, 9, 4, 3), 1, 3, (1,), 1),
+    ((16, 6, 5), 2, 2, (0, 1), 2),
+    ((64, 3, 7), 1, 1, (2,), 1),
+]
+
+
+@pytest.mark.parametrize("tier", TIERS)
+@pytest.mark.parametrize("case", STRIDED_FORM_CASES,
+                         ids=[_case_id(c) + f"-d{c[2]}" for c in STRIDED_FORM_CASES])
+def test_strided_lane_form_agrees_bitwise(sl, case, tier):
+    """Rows 0 (one cell per lane) and 1, 2, 8 rows per thread of a strided
+    sweep give the same bits; one of them is checked against the oracle."""
+    import torch
+    from gpu_helpers import download_nd, upload_nd
+    ns, k, dim, dep, nd = case
+    ndim = len(ns)
+    cells = int(np.prod(ns))
+    rng = np.random.default_rng(zlib.crc32(repr(("sforms", ns, k, dim, tier, nd)).encode()))
+    state = O.to_tier(inputs.random_coefficients(ndim, k, cells, seed=int(rng.integers(1 << 30))),
+                      tier, nd, k=k, ndim=ndim)
+    p = sl.Plan(ns, k, tier, ndouble=nd)
+    m_in, h_in = upload_nd(state, p)
+    nsig = int(np.prod([ns[e] for e in dep]))
+    sig = rng.uniform(-2.5 * ns[dim], 2.5 * ns[dim], nsig)
+    mask = sum(1 << e for e in dep)
+    ref = None
+    for rows in (0, 1, 2, 8):
+        for tuples in (1, 0):
+            p.set_shape(dim, rows, tuples)
+            m_out, h_out = p.empty_state()
+            p.advect_dim(dim, _dev(sig), mask, m_in, h_in, m_out, h_out)
+            torch.cuda.synchronize()
+            got = download_nd(m_out, h_out, p)
+            if ref is None:
+                ref = got
+                keep = O.fp64_modes(ndim, k, nd).astype(bool)
+                want = O.sweep(state, ns, k, dim, sig, dep, tier, ndouble=nd)
+                mag = O.sweep(state, ns, k, dim, sig, dep, absolute=True)
+                assert_sweep_close(got, want, mag, tier, k, keep=keep,
+                                   what=f"{ns} k={k} {tier} dim={dim} lane form")
+            else:
+                assert np.array_equal(got, ref), (rows, tuples)
