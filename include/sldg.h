@@ -468,13 +468,14 @@ sldg_status sldg_batch_run(sldg_batch_t batch, int nsteps, int use_graph, int* r
 /* Launch-shape tuner: for every sweep of the sequence and every class of its
  * work list (tile kind: 0 dimension-0 window form, 1 dimension-0 group form,
  * 2 strided; x degree 1..3; class = 3 * kind + k - 1), times rows-per-thread
- * {2, 4, 8} (strided sweeps) or {4, 1} (dimension 0: the group form, or with
- * rows 1 the lane form, one cell per lane; the window form ignores rows) x
+ * {2, 4, 8, 0} (strided sweeps; 0 the lane form, one cell per lane) or {4, 1}
+ * (dimension 0: the group form, or with rows 1 the lane form; the window form
+ * ignores rows) x
  * tuples-per-thread {1, 3, 9, all} on the bound data (reads buffer 0,
  * overwrites buffer 1) and keeps the fastest per class. */
 sldg_status sldg_batch_tune(sldg_batch_t batch, int reps);
-/* Set the launch shape of every class of sweep q (rows 2, 4 or 8, or 1 for
- * the lane form of a dimension-0 sweep; tuples 0 = all).  get: the shape of the class with the most tiles, and the tuned
+/* Set the launch shape of every class of sweep q (rows 2, 4 or 8; the lane
+ * form: 1 along dimension 0, 0 along others; tuples 0 = all).  get: the shape of the class with the most tiles, and the tuned
  * time of the whole sweep (-1 if not tuned). */
 sldg_status sldg_batch_get_tuning(sldg_batch_t batch, int q, int* rows, int* tuples, double* ms);
 sldg_status sldg_batch_set_tuning(sldg_batch_t batch, int q, int rows, int tuples);

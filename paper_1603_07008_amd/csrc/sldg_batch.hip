@@ -115,9 +115,10 @@ sldg_status build_sweep(sldg_batch_s* b, int q) {
       int64_t ntab = 0;
       describe_grid(b->ndim, ext(b, p), o, b->modes[p], dim, mask, b->rows[sc], b->tuples[sc], a,
                     ntab);
-      // rows 1: the lane form of the non-window classes (the launch picks the
+      // the lane form (one cell per lane): rows 1 for the non-window
+      // dimension-0 classes, rows 0 for strided classes (the launch picks the
       // kernel from the same rows)
-      a.lane = (kind == 1 && b->rows[sc] == 1) ? 1 : 0;
+      a.lane = ((kind == 1 && b->rows[sc] == 1) || (kind == 2 && b->rows[sc] == 0)) ? 1 : 0;
       a.in_lo = b->mass[src][p];
       a.in_hi = b->hi[src][p];
       a.out_lo = b->mass[1 - src][p];
@@ -138,6 +139,11 @@ sldg_status build_sweep(sldg_batch_s* b, int q) {
       auto& bk = bucket[class_of(kind, b->k[p])];
       for (int32_t qg = 0; qg < nq; ++qg)
         for (int64_t x = 0; x < tiles; ++x) bk.push_back({p, kind, (int32_t)x, qg, 0});
+    } else if (a.lane) {
+      const int64_t tiles = (a.cells + 255) / 256;
+      auto& bk = bucket[class_of(2, b->k[p])];
+      for (int32_t qg = 0; qg < nq; ++qg)
+        for (int64_t x = 0; x < tiles; ++x) bk.push_back({p, 2, (int32_t)x, qg, 0});
     } else {
       const int64_t xt = ((int64_t)a.P * a.Q + 63) / 64;
       const int64_t zt = ((int64_t)a.nchunk + 3) / 4;
@@ -408,8 +414,11 @@ sldg_status sldg_batch_run(sldg_batch_t b, int nsteps, int use_graph, int* resul
 sldg_status sldg_batch_set_tuning(sldg_batch_t b, int q, int rows, int tuples) {
   if (!b) return fail(SLDG_ERR_ARG, "batch is NULL");
   if (q < 0 || q >= b->nseq) return fail(SLDG_ERR_ARG, "sweep %d out of range", q);
-  if (!(rows == 2 || rows == 4 || rows == 8 || (rows == 1 && b->dims[q] == 0)) || tuples < 0)
-    return fail(SLDG_ERR_ARG, "rows %d not in {2, 4, 8} (or 1 along dimension 0) or tuples %d < 0",
+  if (!(rows == 2 || rows == 4 || rows == 8 || (rows == 1 && b->dims[q] == 0) ||
+        (rows == 0 && b->dims[q] > 0)) ||
+      tuples < 0)
+    return fail(SLDG_ERR_ARG,
+                "rows %d not in {2, 4, 8} (or 1 along dimension 0, 0 along others) or tuples %d < 0",
                 rows, tuples);
   for (int c = 0; c < kClasses; ++c) {
     b->rows[(size_t)q * kClasses + c] = rows;
@@ -428,9 +437,12 @@ sldg_status sldg_batch_set_class_tuning(sldg_batch_t b, int q, int cls, int rows
   if (!b) return fail(SLDG_ERR_ARG, "batch is NULL");
   if (q < 0 || q >= b->nseq) return fail(SLDG_ERR_ARG, "sweep %d out of range", q);
   if (cls < 0 || cls >= kClasses) return fail(SLDG_ERR_ARG, "class %d out of range", cls);
-  if (!(rows == 2 || rows == 4 || rows == 8 || (rows == 1 && cls / 3 != 2)) || tuples < 0)
-    return fail(SLDG_ERR_ARG, "rows %d not in {2, 4, 8} (or 1 for classes 0-5) or tuples %d < 0",
-                rows, tuples);
+  if (!(rows == 2 || rows == 4 || rows == 8 || (rows == 1 && cls / 3 != 2) ||
+        (rows == 0 && cls / 3 == 2)) ||
+      tuples < 0)
+    return fail(SLDG_ERR_ARG,
+                "rows %d not in {2, 4, 8} (or 1 for classes 0-5, 0 for 6-8) or tuples %d < 0", rows,
+                tuples);
   const size_t i = (size_t)q * kClasses + cls;
   b->rows[i] = rows;
   b->tuples[i] = tuples;
@@ -501,7 +513,7 @@ sldg_status sldg_batch_tune(sldg_batch_t b, int reps) {
     for (int i = 0; i < nev - 1; ++i) (void)hipEventDestroy(ev[i]);
     return device_error(e, "hipEventCreate");
   }
-  const int rows_c[3] = {2, 4, 8};
+  const int rows_c[4] = {2, 4, 8, 0};          // strided: rows per thread, or the lane form
   const int rows_c0[2] = {4, 1};              // dimension 0: group, lane form
   const int tup_c[4] = {1, 3, 9, 0};
   sldg_status st = SLDG_OK;
@@ -513,7 +525,7 @@ sldg_status sldg_batch_tune(sldg_batch_t b, int reps) {
       best_t[c] = b->tuples[(size_t)q * kClasses + c];
       best[c] = 1e300;
     }
-    const int nr = b->dims[q] == 0 ? 2 : 3;
+    const int nr = b->dims[q] == 0 ? 2 : 4;
     for (int ir = 0; ir < nr && st == SLDG_OK; ++ir)
       for (int it = 0; it < 4 && st == SLDG_OK; ++it) {
         // every class of the sweep takes the candidate; each class is timed alone

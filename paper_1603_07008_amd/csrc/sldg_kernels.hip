@@ -1301,7 +1301,7 @@ __global__ __launch_bounds__(256) void batch_class_kernel(const SweepArgs* __res
     contig_group<K, TIER, 1>(a, (int64_t)w.x * blockDim.x + threadIdx.x, q, qe, 0);
   } else if constexpr (KIND == 1) {
     contig_group_any<K, TIER, 1>(a, (int64_t)w.x * blockDim.x + threadIdx.x, q, qe, 0);
-  } else if constexpr (KIND == 3) {          // kind 1 in the lane form (rows 1)
+  } else if constexpr (KIND == 3) {          // kinds 1 (rows 1) and 2 (rows 0) in the lane form
     lane_cell<K, TIER, 1, false>(a, (int64_t)w.x * blockDim.x + threadIdx.x, q, qe, 0);
   } else {
     const int32_t col = w.x * 64 + (int32_t)(threadIdx.x & 63);
@@ -1321,6 +1321,7 @@ static hipError_t launch_class_ktk(int rows, const SweepArgs* args, const BatchI
     batch_class_kernel<K, TIER, KIND, 1><<<nitems, 256, 0, st>>>(args, items, xcd);
   } else {
     switch (rows) {
+      case 0: batch_class_kernel<K, TIER, 3, 1><<<nitems, 256, 0, st>>>(args, items, xcd); break;
       case 2: batch_class_kernel<K, TIER, 2, 2><<<nitems, 256, 0, st>>>(args, items, xcd); break;
       case 4: batch_class_kernel<K, TIER, 2, 4><<<nitems, 256, 0, st>>>(args, items, xcd); break;
       case 8: batch_class_kernel<K, TIER, 2, 8><<<nitems, 256, 0, st>>>(args, items, xcd); break;

@@ -116,9 +116,10 @@ def test_graph_replays_match_eager_and_tuning_keeps_results(sl):
 
 
 @pytest.mark.parametrize("tier", ["fp32", "bf16"])
-def test_batch_dimension0_forms_agree_bitwise(sl, tier):
-    """Rows 1 (lane form) and 4 (group form) of the non-window dimension-0
-    classes, with one tuple or all per thread, give the same bits."""
+def test_batch_lane_and_tiled_forms_agree_bitwise(sl, tier):
+    """The lane form (rows 1 for the non-window dimension-0 classes, rows 0
+    for the strided classes) and the tiled forms (4-cell groups, 8 rows per
+    thread), with one tuple or all per thread, give the same bits."""
     import torch
     probs = _problems()
     stream = torch.cuda.Stream()
@@ -126,11 +127,13 @@ def test_batch_dimension0_forms_agree_bitwise(sl, tier):
         b, c0s, s0, s1, shifts = _setup(sl, probs, tier, stream.cuda_stream)
         init = [(m.clone(), h.clone()) for m, h in s0]
         ref = None
-        for rows in (4, 1):
+        for rows, vrows in ((4, 8), (1, 0), (4, 0)):
             for tuples in (1, 0):
                 for q in (0, 2):                       # the two x-sweeps of the step
                     for cls in (3, 4, 5):              # dimension-0 group classes, k = 1..3
                         b.set_class_tuning(q, cls, rows, tuples)
+                for cls in (6, 7, 8):                  # strided classes of the v-sweep
+                    b.set_class_tuning(1, cls, vrows, tuples)
                 for i in range(len(probs)):
                     s0[i][0].copy_(init[i][0])
                     s0[i][1].copy_(init[i][1])
