@@ -123,6 +123,8 @@ def sweep_kernel_name(ns, k, tier, d, shape):
     if d == 0:
         if ns[0] % 4 == 0:
             return f"sldg::sweep_contig_window_kernel<{k}, {tid}, 1>"
+        if shape["rows"] in (2, 4, 8):
+            return f"sldg::sweep_contig_group_kernel<{k}, {tid}, 1>"
         return f"sldg::sweep_lane_kernel<{k}, {tid}, 1, true>"
     if shape["rows"] == 0:
         return f"sldg::sweep_lane_kernel<{k}, {tid}, 1, true>"

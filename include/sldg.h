@@ -193,8 +193,10 @@ sldg_status sldg_mass_device(sldg_plan_t plan, const double* mass, double* out_d
  *             or 0 for the lane form (one cell per lane, consecutive lanes on
  *             consecutive cells).  Dimension 0, where the window form does
  *             not apply (N_0 % 4 != 0 or buffers not 16-byte aligned): 1 for
- *             the lane form, 2/4/8 for the group form (4 cells per thread),
- *             0 (the default) for the lane form with all tuples in one run
+ *             the lane form, 2/4/8 for the group form (4 cells of a line
+ *             per thread, interleaved with the line's other threads), 0 (the
+ *             default) for all tuples in one run, in the group form when the
+ *             displacement depends on dimension 1, else in the lane form
  *             (tuples is then ignored where the window form does not apply)
  *   tuples    spectator mode tuples per thread (0: all)
  *   colwaves  strided sweeps: waves of a workgroup side by side along the

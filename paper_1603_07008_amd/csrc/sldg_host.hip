@@ -146,15 +146,17 @@ void describe_grid(int ndim, const int64_t* n, int o, int64_t modes, int dim, ui
   a.tuples = (tuples_per_thread > 0 && tuples_per_thread < a.nspec) ? tuples_per_thread : a.nspec;
   a.colwaves = 1;
   // dimension 0 without the window form: rows 1 asks for the lane form, 0
-  // for the automatic choice (the lane form, with every tuple in one run:
-  // a lane's share of a tuple is small, and the run amortises the line's
-  // table), anything else for the group form
+  // for the automatic choice, anything else for the group form.  The
+  // automatic choice runs every tuple in one run (a thread's share of a
+  // tuple is small, the run amortises the line's table), in the group form
+  // when the displacement depends on dimension 1 (every line its own table,
+  // shared by a group's 4 cells), else in the lane form
   a.lane = 0;
   if (dim == 0) {
     if (rows_per_thread == 1) {
       a.lane = 1;
     } else if (rows_per_thread == 0) {
-      a.lane = 1;
+      a.lane = (dep_mask & 2u) ? 0 : 1;
       a.tuples = a.nspec;
     }
   } else if (rows_per_thread == 0) {

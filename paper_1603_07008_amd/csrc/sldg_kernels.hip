@@ -588,25 +588,28 @@ __device__ __forceinline__ void window5(const Blk4<T>& b0, const Blk4<T>& b1, in
 }
 
 template <int K, int TIER, int ND>
-struct Win {               // the 5-cell source window of one tuple
-  Raw<K, TIER, ND> w[5];
+struct Win {               // the source cells of one tuple: the 5-cell window of the
+  Raw<K, TIER, ND> w[8];   // window form, or (x_u, y_u) at (2u, 2u+1) in the group form
 };
 
-// Where the 5 source cells of a thread's output cells lie.  Window form: two
-// aligned 4-cell blocks of the line and the offset in the first.  Group form:
-// the line offsets of the 5 cells and the number n of output cells (the last
-// group of a line holds N_0 % 4 cells when that is not 0).
+// Where the source cells of a thread's output cells lie.  Window form: two
+// aligned 4-cell blocks of the line and the offset in the first.  Group
+// form: the thread's outputs are cells i0 + u step (u < n, step =
+// ceil(N_0 / 4)) of its line, interleaved with the other threads of the line
+// so that a wave's lanes touch consecutive cells; x[u], y[u] are the line
+// offsets of output u's sources i - s and i - s - 1.
 template <bool GROUP> struct Geo;
 template <> struct Geo<false> { int32_t blk0, blk1, d; };
-template <> struct Geo<true> { int32_t src[5]; int32_t n; };
+template <> struct Geo<true> { int32_t x[4], y[4]; int32_t n, step; };
 
 // The source cells of one tuple as loaded: two raw 4-cell blocks per plane
-// (window form) or 5 values per plane (group form).
+// (window form) or the two sources of each of 4 outputs per plane (group
+// form, x_u at 2u and y_u at 2u+1).
 template <int K, int TIER, int ND, bool GROUP>
 struct Fetched {
   using T = typename Tier<TIER>::T;
   static constexpr int O = K + 1;
-  static constexpr int NV = GROUP ? 5 : 2;
+  static constexpr int NV = GROUP ? 8 : 2;
   typename std::conditional<GROUP, double, Raw4<double>>::type d[O][NV];   // l < ND
   typename std::conditional<GROUP, T, Raw4<T>>::type h[O][NV];             // l >= ND
 };
@@ -617,11 +620,16 @@ __device__ __forceinline__ void contig_fetch(const Planes<K, TIER, ND>& pl, int6
   constexpr int O = K + 1;
 #pragma unroll
   for (int l = 0; l < O; ++l) {
-    if constexpr (GROUP) {           // one load per source cell
+    if constexpr (GROUP) {           // one load per source of each output
 #pragma unroll
-      for (int u = 0; u < 5; ++u) {
-        if (l < ND) F.d[l][u] = pl.ind[l][lb + g.src[u]];
-        else F.h[l][u] = pl.inh[l][lb + g.src[u]];
+      for (int u = 0; u < 4; ++u) {
+        if (l < ND) {
+          F.d[l][2 * u] = pl.ind[l][lb + g.x[u]];
+          F.d[l][2 * u + 1] = pl.ind[l][lb + g.y[u]];
+        } else {
+          F.h[l][2 * u] = pl.inh[l][lb + g.x[u]];
+          F.h[l][2 * u + 1] = pl.inh[l][lb + g.y[u]];
+        }
       }
     } else if (l < ND) {
       F.d[l][0] = fetch4(pl.ind[l] + lb + 4 * g.blk0);
@@ -656,7 +664,7 @@ __device__ __forceinline__ void contig_select(const Planes<K, TIER, ND>& pl, con
   for (int l = 0; l < O; ++l) {
     if constexpr (GROUP) {
 #pragma unroll
-      for (int u = 0; u < 5; ++u) {
+      for (int u = 0; u < 8; ++u) {
         if (l < ND) W.w[u].d[l] = F.d[l][u];
         else W.w[u].h[l] = to_reg<TIER>(F.h[l][u], pl.fin[l]);
       }
@@ -686,16 +694,17 @@ __device__ __forceinline__ void contig_store(const SweepArgs& a, const Planes<K,
   zero_amax(am);
 #pragma unroll
   for (int j = 0; j < O; ++j) {
-    if constexpr (GROUP) {           // one store per output cell, the last group partial
+    if constexpr (GROUP) {           // one store per output cell; the line's last ones partial
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         if (u < g.n) {
+          const int64_t cu = c + (int64_t)u * g.step;
           if (j < ND) {
-            const double v = Mat<K, TIER>::out64(R, j, W.w[u + 1], W.w[u]);
-            if (active) pl.outd[j][c + u] = v;
+            const double v = Mat<K, TIER>::out64(R, j, W.w[2 * u], W.w[2 * u + 1]);
+            if (active) pl.outd[j][cu] = v;
           } else {
-            const T v = pl.put(j, M.out_acc(j, W.w[u + 1], W.w[u]), am);
-            if (active) pl.outh[j][c + u] = v;
+            const T v = pl.put(j, M.out_acc(j, W.w[2 * u], W.w[2 * u + 1]), am);
+            if (active) pl.outh[j][cu] = v;
           }
         }
       }
@@ -748,13 +757,22 @@ __device__ __forceinline__ void contig_body(const SweepArgs& a, int32_t c, int32
   if (w0 < 0) w0 += N;
   Geo<GROUP> geo;
   if constexpr (GROUP) {
+    // outputs i0 + u step; sources (i - s) and (i - s - 1) mod N, s in [0, N)
+    const int32_t step = (N + 3) >> 2;
+    geo.step = step;
+    geo.n = 0;
 #pragma unroll
-    for (int u = 0; u < 5; ++u) {
-      int32_t v = w0 + u;
-      while (v >= N) v -= N;           // at most once for N >= 4
-      geo.src[u] = v;
+    for (int u = 0; u < 4; ++u) {
+      int32_t i = i0 + u * step;
+      if (i < N) ++geo.n;
+      else i = i0;                     // past the line: a valid duplicate, not stored
+      int32_t x = i - s;
+      if (x < 0) x += N;
+      int32_t y = x - 1;
+      if (y < 0) y += N;
+      geo.x[u] = x;
+      geo.y[u] = y;
     }
-    geo.n = min(4, N - i0);
   } else {
     const int32_t nb = N >> 2;
     geo.blk0 = w0 >> 2;
@@ -837,9 +855,10 @@ __device__ __forceinline__ void contig_group(const SweepArgs& a, int64_t g, int3
 }
 
 // Group gi of the dimension-0 sweep in the group form (any N_0, any
-// alignment): cells 4g .. min(4g+4, N_0)-1 of line gi / ng, g = gi % ng,
-// ng = ceil(N_0 / 4); tuples [q, qe).  Lanes past the last group act as in
-// contig_group.
+// alignment): cells g, g + ng, g + 2 ng, g + 3 ng (those below N_0) of line
+// gi / ng, g = gi % ng, ng = ceil(N_0 / 4), so consecutive lanes of a line
+// touch consecutive cells and the four cells share the line's table; tuples
+// [q, qe).  Lanes past the last group act as in contig_group.
 template <int K, int TIER, int NDMAX>
 __device__ __forceinline__ void contig_group_any(const SweepArgs& a, int64_t gi, int32_t q,
                                                  int32_t qe, int32_t slot) {
@@ -856,7 +875,7 @@ __device__ __forceinline__ void contig_group_any(const SweepArgs& a, int64_t gi,
     }
   }
   const int32_t line = (int32_t)a.fG.div((uint32_t)gi);
-  const int32_t i0 = ((int32_t)gi - line * ng) << 2;
+  const int32_t i0 = (int32_t)gi - line * ng;
   const int32_t c = line * a.N + i0;
   const int32_t t = table_index(a.map, 0, line);
   const int32_t t0 = __builtin_amdgcn_readfirstlane(t);

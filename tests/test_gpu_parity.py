@@ -80,7 +80,7 @@ CASES = [
     ((5, 7, 6), 2, {0: (1, 2), 1: (0, 2), 2: (0,)}),
     ((12, 10, 8, 9), 2, {0: (2,), 1: (3,), 2: (0, 1), 3: (0, 1)}),
     ((6, 4, 5, 3), 1, {0: (2, 3), 1: (), 2: (0, 1, 3), 3: (1,)}),
-    # dimension-0 lengths that take the LDS-tiled kernel (N_0 % 8 == 0)
+    # dimension-0 lengths that are multiples of 8 (the window form, several tiles)
     ((16, 6, 5), 2, {0: (1, 2), 1: (0,), 2: (0, 1)}),
     ((24, 7), 3, {0: (1,), 1: (0,)}),
     ((8, 6, 4, 5), 2, {0: (2,), 1: (3,), 2: (0, 1), 3: (0, 1)}),
