@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256) void density_partial_kernel(FieldPlanes fp, in
   part[((int64_t)z * gridDim.y + j) * nx + i] = acc;
 }
 
-constexpr int kFieldThreads = 256;
+constexpr int kFieldThreads = 1024;
 
 __device__ double block_sum(double v, double* sh) {
   sh[threadIdx.x] = v;
@@ -59,9 +59,9 @@ __device__ double block_sum(double v, double* sh) {
 }
 
 // One workgroup: the density moments, the mean density, the face values of
-// the antiderivative (a serial scan along x), its cell means, the zero-mean
-// constant, and E and the displacement at the cell centres.  `half[j]` is
-// int_{-1}^{0} P_j.
+// the antiderivative (a block-wide scan along x), its cell means, the
+// zero-mean constant, and E and the displacement at the cell centres.
+// `half[j]` is int_{-1}^{0} P_j.
 __global__ __launch_bounds__(kFieldThreads) void field_solve_kernel(
     const double* __restrict__ part, int32_t nz, int32_t o, int32_t nx, double hx, double hv,
     double dt, double h0, double h1, double h2, double h3, double* __restrict__ r,
@@ -79,14 +79,28 @@ __global__ __launch_bounds__(kFieldThreads) void field_solve_kernel(
   double loc = 0.0;
   for (int32_t i = threadIdx.x; i < nx; i += kFieldThreads) loc += r[i];
   const double rbar = block_sum(loc, sh) / nx;
-  // face values of the antiderivative of rho - rbar, from 0 at the left end
-  if (threadIdx.x == 0) {
-    double f = 0.0;
-    faces[0] = 0.0;
-    for (int32_t i = 0; i < nx; ++i) {
-      f += hx * (r[i] - rbar);
-      faces[i + 1] = f;
-    }
+  // face values of the antiderivative of rho - rbar, from 0 at the left end:
+  // each thread sums a contiguous chunk of cells, an inclusive scan of the
+  // chunk sums (fixed order) gives each chunk's starting face, and the thread
+  // writes its chunk's faces
+  const int32_t per = (nx + kFieldThreads - 1) / kFieldThreads;
+  const int32_t i0 = min(nx, (int32_t)threadIdx.x * per), i1 = min(nx, i0 + per);
+  double chunk = 0.0;
+  for (int32_t i = i0; i < i1; ++i) chunk += hx * (r[i] - rbar);
+  sh[threadIdx.x] = chunk;
+  __syncthreads();
+  for (int off = 1; off < kFieldThreads; off <<= 1) {
+    const double v = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0.0;
+    __syncthreads();
+    sh[threadIdx.x] += v;
+    __syncthreads();
+  }
+  double f = threadIdx.x > 0 ? sh[threadIdx.x - 1] : 0.0;   // sum of the chunks before
+  __syncthreads();
+  if (threadIdx.x == 0) faces[0] = 0.0;
+  for (int32_t i = i0; i < i1; ++i) {
+    f += hx * (r[i] - rbar);
+    faces[i + 1] = f;
   }
   __syncthreads();
   // cell means: F_i + h/2 (r0 - rbar) - h/6 r1; the constant making the mean 0
@@ -122,7 +136,7 @@ static hipError_t launch_field_t(const FieldPlanes& fp, int o, int32_t nx, int32
   return hipGetLastError();
 }
 
-int32_t field_chunks(int32_t nv) { return nv < 32 ? (nv > 0 ? nv : 1) : 32; }
+int32_t field_chunks(int32_t nv) { return nv < 8 ? (nv > 0 ? nv : 1) : 8; }
 
 int64_t field_scratch_doubles(int o, int32_t nx, int32_t nv) {
   return (int64_t)field_chunks(nv) * o * nx + (int64_t)o * nx + nx + 1;
