@@ -57,13 +57,19 @@ __device__ __forceinline__ double c_load(const ColArgs& a, const T* hin, int32_t
   return c_widen(hin[(int64_t)v * a.cells + x]);
 }
 
+// Stores: consecutive lanes write consecutive cells, so a wave writes whole
+// lines and 4- and 8-byte values carry the non-temporal hint (outputs are not
+// read again by the sweep); 2-byte values stay plain.
 template <int LO, class T>
 __device__ __forceinline__ void c_store(const ColArgs& a, T* hout, int32_t v, bool first,
                                         int64_t x, double r) {
-  if ((LO == 1 && first) || (LO == 2 && v < 0))
-    a.out_lo[(LO == 1 ? 0 : (int64_t)(-1 - v)) * a.cells + x] = r;
-  else
-    hout[(int64_t)v * a.cells + x] = c_narrow<T>(r);
+  if ((LO == 1 && first) || (LO == 2 && v < 0)) {
+    __builtin_nontemporal_store(r, a.out_lo + (LO == 1 ? 0 : (int64_t)(-1 - v)) * a.cells + x);
+  } else {
+    T* p = hout + (int64_t)v * a.cells + x;
+    if constexpr (sizeof(T) >= 4) __builtin_nontemporal_store(c_narrow<T>(r), p);
+    else *p = c_narrow<T>(r);
+  }
 }
 
 // The sweep of one output cell c of one spectator group, whose modes are
