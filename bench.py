@@ -115,28 +115,34 @@ def measured_plane_copy(sl, torch, cells, nplanes, tiers=(1, 3, 9, 27), reps=10)
 def sweep_kernel_name(ns, k, tier, d, shape):
     """The template instance the library launches for the sweep along d (as
     the profiler names it): the window or lane form along dimension 0; the
-    strided kernel with its rows per thread and whether its one-value-per-lane
-    stores carry the non-temporal hint (a wave's stores cover whole 128-byte
-    lines: the column stride P is a multiple of 64, or P times the value size
-    a multiple of 128 bytes; the narrow value size for FP32, else 8 bytes)."""
+    strided kernel with its rows per thread and which of its one-value-per-
+    lane stores carry the non-temporal hint (where a wave's stores cover
+    whole 128-byte lines: the column stride P is a multiple of 64, or P times
+    the value size a multiple of 128 bytes): 0 none, 1 the 4- and 8-byte
+    values, 2 the 2-byte values too."""
     tid = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}[tier]
     if d == 0:
         if ns[0] % 4 == 0:
             return f"sldg::sweep_contig_window_kernel<{k}, {tid}, 1>"
         if shape["rows"] in (2, 4, 8):
             return f"sldg::sweep_contig_group_kernel<{k}, {tid}, 1>"
-        return f"sldg::sweep_lane_kernel<{k}, {tid}, 1, true>"
+        return f"sldg::sweep_lane_kernel<{k}, {tid}, 1, 2>"
     if shape["rows"] == 0:
-        return f"sldg::sweep_lane_kernel<{k}, {tid}, 1, true>"
+        return f"sldg::sweep_lane_kernel<{k}, {tid}, 1, 2>"
     P = 1
     for e in range(d):
         P *= ns[e]
-    size = 4 if tier == "fp32" else 8
-    nt = P % 64 == 0 or (P * size) % 128 == 0
+    ok = lambda size: P % 64 == 0 or (P * size) % 128 == 0
+    if tier == "fp64":
+        nt = 1 if ok(8) else 0
+    elif tier == "fp32":
+        nt = 1 if ok(4) else 0
+    else:
+        nt = 2 if ok(2) else (1 if ok(8) else 0)
     rows = shape["rows"]
     while rows > 1 and rows > ns[d]:
         rows //= 2
-    return f"sldg::sweep_strided_kernel<{k}, {tid}, {rows}, 1, {'true' if nt else 'false'}>"
+    return f"sldg::sweep_strided_kernel<{k}, {tid}, {rows}, 1, {nt}>"
 
 
 def run_tier(sl, torch, prob, tier, init, steps, warmup, tune_cache=None, single_reps=20):

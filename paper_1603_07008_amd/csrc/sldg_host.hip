@@ -177,8 +177,8 @@ void describe_grid(int ndim, const int64_t* n, int o, int64_t modes, int dim, ui
   // form stores without the hint), and strided sweeps whose 64 columns of a
   // wave are one run (P % 64 == 0) or runs of whole lines (P * size % 128 == 0)
   a.ntmask = 0;
-  for (int b = 0; b < 2; ++b) {
-    const int64_t size = b ? 8 : 4;
+  for (int b = 0; b < 3; ++b) {
+    const int64_t size = 2LL << b;           // 2, 4, 8 bytes
     if (dim == 0 || a.lane || P % 64 == 0 || (P * size) % 128 == 0) a.ntmask |= 1 << b;
   }
   a.fP = FastDiv::make((uint32_t)a.P);

@@ -69,8 +69,8 @@ struct SweepArgs {
   int32_t tuples;         // spectator tuples per thread (a run; blockIdx.y picks it)
   int32_t colwaves;       // strided sweep: waves of a workgroup side by side (1, 2 or 4)
   int32_t lane;           // dimension-0 sweep without the window form: 1 lane form, 0 group form
-  int32_t ntmask;         // one-value-per-lane stores with the non-temporal hint: bit 0 for
-                          // 4-byte, bit 1 for 8-byte values (set where a wave writes whole lines)
+  int32_t ntmask;         // one-value-per-lane stores with the non-temporal hint: bits 0, 1, 2
+                          // for 2-, 4-, 8-byte values (set where a wave writes whole lines)
   FastDiv fP;             // division by P
   FastDiv fN;             // division by N
   FastDiv fchunk;         // division by nchunk

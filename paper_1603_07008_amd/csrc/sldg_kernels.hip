@@ -26,11 +26,11 @@ namespace sldg {
 // Stores of the sweeps' outputs.  Every output coefficient is written once
 // per sweep and not read again by it, so stores whose wave writes whole
 // 128-byte lines carry the non-temporal hint, which raises the HBM rate of
-// this pattern: the window form's 16 bytes per lane, and 4- or 8-byte values
-// one per lane (kernels instantiated with NT) where the host found the wave's
+// this pattern: the window form's 8 or 16 bytes per lane, and one value per
+// lane (kernels instantiated with NT > 0) where the host found the wave's
 // cells to cover whole lines (SweepArgs::ntmask).  Stores that leave partial
-// lines (2-byte values, the group form's 4 cells per lane, strided rows of 48
-// FP32 cells) stay plain: there the hint measured slower.  The choice is made
+// lines (the group form's interleaved cells, strided rows of 48 FP32 or BF16
+// cells) stay plain: there the hint measured slower.  The choice is made
 // at compile time: a run-time branch between the two stores is merged by the
 // compiler into one plain store.  Loads stay plain (the hint evicts the
 // neighbouring cells that the next lanes and rows read again).
@@ -39,10 +39,17 @@ __device__ __forceinline__ void st_stream(T* p, T v) {
   __builtin_nontemporal_store(v, p);
 }
 
-template <bool NT, class T>
+// NT: 0 plain; 1 the hint on 4- and 8-byte values; 2 on 2-byte values too
+// (the 16-bit tiers where a wave's 64 values fill a whole line).
+template <int NT, class T>
 __device__ __forceinline__ void st_lane(T* p, T v) {
-  if constexpr (NT && sizeof(T) >= 4) __builtin_nontemporal_store(v, p);
-  else *p = v;
+  if constexpr (NT >= 1 && sizeof(T) >= 4) {
+    __builtin_nontemporal_store(v, p);
+  } else if constexpr (NT >= 2 && sizeof(T) == 2) {
+    __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, v), reinterpret_cast<uint16_t*>(p));
+  } else {
+    *p = v;
+  }
 }
 
 typedef double nt_d2 __attribute__((ext_vector_type(2)));
@@ -438,7 +445,7 @@ struct Planes {
       return narrow<T>(acc);
     }
   }
-  template <bool NT>
+  template <int NT>
   __device__ __forceinline__ void store(int64_t c, const Mat<K, TIER>& M, const Rows64<K, ND>& R,
                                         const Raw<K, TIER, ND>& x, const Raw<K, TIER, ND>& y,
                                         float (&am)[O], bool active) const {
@@ -961,7 +968,7 @@ __device__ __forceinline__ void strided_load(const Planes<K, TIER, ND>& pl, int6
   for (int u = 0; u <= L; ++u) pl.load(base + roff[u], R.v[u]);
 }
 
-template <int K, int TIER, int ND, int L, bool NT>
+template <int K, int TIER, int ND, int L, int NT>
 __device__ __forceinline__ void strided_store(const SweepArgs& a, const Planes<K, TIER, ND>& pl,
                                               int64_t base, int32_t r0, int32_t n,
                                               const Mat<K, TIER>& M, const Rows64<K, ND>& R64,
@@ -983,7 +990,7 @@ __device__ __forceinline__ void strided_store(const SweepArgs& a, const Planes<K
   flush_amax<K, TIER, ND>(a, pl, am, slot);
 }
 
-template <int K, int TIER, int ND, int L, bool NT>
+template <int K, int TIER, int ND, int L, int NT>
 __device__ __forceinline__ void strided_single(const SweepArgs& a, const TupleMap& tm,
                                                const Mat<K, TIER>& M, int64_t base,
                                                const int32_t (&roff)[L + 1], int32_t r0,
@@ -997,7 +1004,7 @@ __device__ __forceinline__ void strided_single(const SweepArgs& a, const TupleMa
   strided_store<K, TIER, ND, L, NT>(a, pl, base, r0, n, M, R64, R, slot, active);
 }
 
-template <int K, int TIER, int L, int NDMAX, bool NT>
+template <int K, int TIER, int L, int NDMAX, int NT>
 __device__ __forceinline__ void strided_body(const SweepArgs& a, int32_t ilow, int32_t chunk,
                                              int32_t ihigh, int32_t t, int32_t q, int32_t qe,
                                              int32_t slot, bool active) {
@@ -1072,7 +1079,7 @@ __device__ __forceinline__ void strided_body(const SweepArgs& a, int32_t ilow, i
 // chunk is uniform across a wave; in a scaled FP16 sweep, lanes past the
 // last column redo the last column without storing it, so that whole waves
 // reach the absmax reductions.
-template <int K, int TIER, int L, int NDMAX, bool NT>
+template <int K, int TIER, int L, int NDMAX, int NT>
 __device__ __forceinline__ void strided_cell(const SweepArgs& a, int32_t col, int32_t chunk,
                                              int32_t q, int32_t qe, int32_t slot) {
   if (chunk >= a.nchunk) return;
@@ -1107,7 +1114,7 @@ __device__ __forceinline__ void strided_cell(const SweepArgs& a, int32_t col, in
 // store of a wave writes 64 consecutive cells.  Along dimension 0 (P = 1) the
 // column is the line itself.  Lanes past the last cell act as in
 // contig_group.
-template <int K, int TIER, int NDMAX, bool NT>
+template <int K, int TIER, int NDMAX, int NT>
 __device__ __forceinline__ void lane_cell(const SweepArgs& a, int64_t c, int32_t q, int32_t qe,
                                           int32_t slot) {
   bool active = true;
@@ -1143,7 +1150,7 @@ __device__ __forceinline__ void lane_cell(const SweepArgs& a, int64_t c, int32_t
 // over the XCDs so that tiles sharing lines (the halo row between row chunk
 // groups, the cache lines split between column blocks when the rows are
 // short) run on one XCD, one after the other.
-template <int K, int TIER, int L, int NDMAX, bool NT>
+template <int K, int TIER, int L, int NDMAX, int NT>
 __global__ __launch_bounds__(256) void sweep_strided_kernel(SweepArgs a) {
   uint32_t bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
   const uint32_t gx = gridDim.x, gz = gridDim.z;
@@ -1171,7 +1178,7 @@ __global__ __launch_bounds__(256) void sweep_strided_kernel(SweepArgs a) {
                                   (int32_t)(bz * gx + bx) * waves + wave);
 }
 
-template <int K, int TIER, int NDMAX, bool NT>
+template <int K, int TIER, int NDMAX, int NT>
 __global__ __launch_bounds__(256) void sweep_lane_kernel(SweepArgs a) {
   uint32_t bx = blockIdx.x, by = blockIdx.y;
   if (a.xcd) {                 // tile order: x fastest, then y
@@ -1237,9 +1244,15 @@ int64_t sweep_slots(int dim, const SweepArgs& a) {
 }
 
 template <int K, int TIER, int L, int NDMAX>
-static void launch_strided(bool nt, dim3 grid, dim3 block, hipStream_t st, const SweepArgs& a) {
-  if (nt) sweep_strided_kernel<K, TIER, L, NDMAX, true><<<grid, block, 0, st>>>(a);
-  else sweep_strided_kernel<K, TIER, L, NDMAX, false><<<grid, block, 0, st>>>(a);
+static void launch_strided(int nt, dim3 grid, dim3 block, hipStream_t st, const SweepArgs& a) {
+  if constexpr (TIER >= 2) {
+    if (nt == 2) {
+      sweep_strided_kernel<K, TIER, L, NDMAX, 2><<<grid, block, 0, st>>>(a);
+      return;
+    }
+  }
+  if (nt) sweep_strided_kernel<K, TIER, L, NDMAX, 1><<<grid, block, 0, st>>>(a);
+  else sweep_strided_kernel<K, TIER, L, NDMAX, 0><<<grid, block, 0, st>>>(a);
 }
 
 template <int K, int TIER, int NDMAX>
@@ -1253,12 +1266,15 @@ static hipError_t launch_sweep_ktn(int dim, const SweepArgs& a, hipStream_t st) 
     sweep_contig_group_kernel<K, TIER, NDMAX><<<grid, block, 0, st>>>(a);
   } else if (form == 3) {
     // the lanes' cells are consecutive: whole lines per wave
-    sweep_lane_kernel<K, TIER, NDMAX, true><<<grid, block, 0, st>>>(a);
+    sweep_lane_kernel<K, TIER, NDMAX, 2><<<grid, block, 0, st>>>(a);
   } else {
-    // the narrow planes' value size decides (the FP64 mean is stored with
-    // the hint under the same test whenever 2-byte planes go without it)
-    const int bit = TIER == 1 ? 1 : 2;
-    const bool nt = (a.ntmask & bit) != 0;
+    // ntmask: bit 0, 1, 2 for 2-, 4-, 8-byte values.  The narrow planes'
+    // value size decides; on the 16-bit tiers, the FP64 mean may take the
+    // hint (mode 1) where the 2-byte planes may not (mode 2)
+    int nt;
+    if (TIER == 0) nt = (a.ntmask & 4) ? 1 : 0;
+    else if (TIER == 1) nt = (a.ntmask & 2) ? 1 : 0;
+    else nt = (a.ntmask & 1) ? 2 : (a.ntmask & 4) ? 1 : 0;
     switch (a.chunk) {
       case 1: launch_strided<K, TIER, 1, NDMAX>(nt, grid, block, st, a); break;
       case 2: launch_strided<K, TIER, 2, NDMAX>(nt, grid, block, st, a); break;
@@ -1321,12 +1337,12 @@ __global__ __launch_bounds__(256) void batch_class_kernel(const SweepArgs* __res
   } else if constexpr (KIND == 1) {
     contig_group_any<K, TIER, 1>(a, (int64_t)w.x * blockDim.x + threadIdx.x, q, qe, 0);
   } else if constexpr (KIND == 3) {          // kinds 1 (rows 1) and 2 (rows 0) in the lane form
-    lane_cell<K, TIER, 1, false>(a, (int64_t)w.x * blockDim.x + threadIdx.x, q, qe, 0);
+    lane_cell<K, TIER, 1, 0>(a, (int64_t)w.x * blockDim.x + threadIdx.x, q, qe, 0);
   } else {
     const int32_t col = w.x * 64 + (int32_t)(threadIdx.x & 63);
     const int32_t chunk = w.z * (int32_t)(blockDim.x >> 6) +
                           __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
-    strided_cell<K, TIER, L, 1, false>(a, col, chunk, q, qe, 0);
+    strided_cell<K, TIER, L, 1, 0>(a, col, chunk, q, qe, 0);
   }
 }
 
