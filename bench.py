@@ -473,8 +473,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(the multi-GPU decomposition is a design note, not an implementation)",
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU decomposition is described, not implemented)",
               file=sys.stderr)
         sys.exit(2)
 
