@@ -217,15 +217,19 @@ def run_tier(sl, torch, prob, tier, init, steps, warmup, tune_cache=None, single
             "mass_drift": drift, "final": final, "shapes": shapes, "single": single}
 
 
-def cpu_baseline(prob, tier, seconds, seed):
+def cpu_baseline(prob, tier, seconds, seed, state=None, gpu_sweep=None):
     """The CPU oracle timed on a sampled subset of one split step: the full
-    4D state in host memory, every sweep of the step computed for a random
-    sample of output cells (all 81 coefficients of each)."""
+    4D state in host memory (the benchmark's initial state when given),
+    every sweep of the step computed for a random sample of output cells (all
+    81 coefficients of each).  With gpu_sweep (sampled cells -> the GPU's
+    outputs of the step's first sweep from the same state), the GPU result is
+    also compared with the FP64 oracle on a sample of cells."""
     import numpy as np
     from oracle import sldg_oracle as O
     from paper_1603_07008_amd import inputs
     t0 = time.time()
-    state = O.to_tier(inputs.random_coefficients(prob.ndim, prob.k, prob.cells, seed=seed), tier)
+    if state is None:
+        state = O.to_tier(inputs.random_coefficients(prob.ndim, prob.k, prob.cells, seed=seed), tier)
     log(f"cpu_baseline: host state ready in {time.time() - t0:.1f}s")
     rng = np.random.default_rng(seed + 1)
     # warm the A/B cache of the oracle, then calibrate the sample size
@@ -262,7 +266,21 @@ def cpu_baseline(prob, tier, seconds, seed):
     dt1 = max(tb - ta, 1e-9)
     n1 = nb - na
     updates1 = n1 * prob.modes * len(prob.seq)
+    check = None
+    if gpu_sweep is not None:
+        # the GPU's first sweep of the step against the FP64 oracle, element
+        # by element on sampled cells, in the mode-weighted L2 norm
+        sw = prob.seq[0]
+        probe = np.sort(rng.choice(prob.cells, min(prob.cells, 65536), replace=False))
+        want = O.sweep(state, prob.ns, prob.k, sw.dim, sw.sigma, sw.dep, "fp64", sel=probe)
+        got = gpu_sweep(probe)
+        w = O.mode_weights(prob.ndim, prob.k)[:, None]
+        rel = math.sqrt(float(np.sum(w * (got - want) ** 2)) / float(np.sum(w * want ** 2)))
+        mass_rel = float(np.max(np.abs(got[0] - want[0]) / np.abs(want[0])))
+        check = {"sweep": f"dimension {sw.dim}", "cells": int(probe.size),
+                 "rel_l2_vs_oracle_fp64": rel, "mass_mode_max_rel_err": mass_rel}
     return {"value": updates / dt, "unit": "coeff-updates/s", "cores": nt,
+            "oracle_check": check,
             "kind": "oracle", "value_1_thread": updates1 / dt1,
             "sample": f"one split step (6 sweeps) of the {prob.ns} k={prob.k} {tier}-mode "
                       f"workload on the full host state, evaluated for {nsel} randomly sampled "
@@ -593,7 +611,30 @@ def main():
         out["extras"] = extras
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(prob, args.tier, args.cpu_seconds, args.seed)
+        import numpy as np
+        # the benchmark's initial state, rounded to the tier, on the host
+        hi_t = hi0.to(sl.hi_dtype(args.tier))
+        host = np.empty((modes, cells))
+        host[0] = mass0.cpu().numpy()
+        host[1:] = hi_t.to(torch.float64).cpu().numpy().reshape(modes - 1, cells)
+
+        def gpu_sweep(probe):
+            sw = prob.seq[0]
+            p = sl.Plan(prob.ns, prob.k, args.tier)
+            a = (mass0, hi_t.contiguous())
+            b = p.empty_state()
+            p.advect_dim(sw.dim, torch.from_numpy(sw.sigma).cuda(), sw.dep_mask, *a, *b)
+            idx = torch.from_numpy(probe).cuda()
+            got = np.empty((modes, probe.size))
+            got[0] = b[0][idx].cpu().numpy()
+            got[1:] = b[1].reshape(modes - 1, cells)[:, idx].to(torch.float64).cpu().numpy()
+            p.close()
+            del b
+            return got
+
+        out["cpu_baseline"] = cpu_baseline(prob, args.tier, args.cpu_seconds, args.seed,
+                                           state=host, gpu_sweep=gpu_sweep)
+        del host
     print(json.dumps(out), flush=True)
 
 
