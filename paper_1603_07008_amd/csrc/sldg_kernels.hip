@@ -1454,16 +1454,28 @@ __device__ __forceinline__ float block_max(float v, float* sh) {
   return r;
 }
 
-// One workgroup per plane.
-__global__ __launch_bounds__(256) void scale_decide_kernel(const float* __restrict__ part,
-                                                           int32_t nslot,
-                                                           int32_t* __restrict__ out_exp,
-                                                           float* __restrict__ out_amax,
-                                                           int32_t* __restrict__ redo) {
-  __shared__ float sh[4];
+// One workgroup of 1024 threads per plane; four independent maxima per
+// thread keep several loads in flight (fmaxf ignores NaN operands, and the
+// maximum does not depend on the order).
+constexpr int kDecideThreads = 1024;
+
+__global__ __launch_bounds__(kDecideThreads) void scale_decide_kernel(
+    const float* __restrict__ part, int32_t nslot, int32_t* __restrict__ out_exp,
+    float* __restrict__ out_amax, int32_t* __restrict__ redo) {
+  __shared__ float sh[kDecideThreads / 64];
   const int64_t p = blockIdx.x;
-  float m = 0.0f;
-  for (int32_t i = threadIdx.x; i < nslot; i += blockDim.x) m = fmaxf(m, part[p * nslot + i]);
+  const float* q = part + p * nslot;
+  const int32_t step = (int32_t)blockDim.x;
+  float m0 = 0.0f, m1 = 0.0f, m2 = 0.0f, m3 = 0.0f;
+  int32_t i = threadIdx.x;
+  for (; i + 3 * step < nslot; i += 4 * step) {
+    m0 = fmaxf(m0, q[i]);
+    m1 = fmaxf(m1, q[i + step]);
+    m2 = fmaxf(m2, q[i + 2 * step]);
+    m3 = fmaxf(m3, q[i + 3 * step]);
+  }
+  for (; i < nslot; i += step) m0 = fmaxf(m0, q[i]);
+  float m = fmaxf(fmaxf(m0, m1), fmaxf(m2, m3));
   m = block_max(m, sh);
   if (threadIdx.x == 0) {
     const int32_t e = out_exp[p];
@@ -1480,7 +1492,8 @@ __global__ __launch_bounds__(256) void scale_decide_kernel(const float* __restri
 hipError_t launch_scale_decide(int64_t n_hi, const float* part, int32_t nslot, int32_t* out_exp,
                                float* out_amax, int32_t* redo, hipStream_t st) {
   if (n_hi <= 0) return hipSuccess;
-  scale_decide_kernel<<<(unsigned)n_hi, 256, 0, st>>>(part, nslot, out_exp, out_amax, redo);
+  scale_decide_kernel<<<(unsigned)n_hi, kDecideThreads, 0, st>>>(part, nslot, out_exp, out_amax,
+                                                                 redo);
   return hipGetLastError();
 }
 
