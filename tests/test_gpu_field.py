@@ -38,7 +38,9 @@ def _landau(nx, nv, k, kappa=0.5, eps=0.01, dt=0.1):
     return st, ns, hx, hv, sx
 
 
-CASES = [((48, 40), 2, 1), ((33, 17), 1, 1), ((64, 50), 3, 1), ((40, 24), 2, 2)]
+CASES = [((48, 40), 2, 1), ((33, 17), 1, 1), ((64, 50), 3, 1), ((40, 24), 2, 2),
+         # more x cells than the solve's threads: several cells per scan chunk
+         ((2500, 6), 2, 1)]
 
 
 @pytest.mark.parametrize("ns,k,ndouble", CASES)

@@ -42,6 +42,8 @@ CASES = [
     ((10, 6, 3, 4), 2, "fp32", 0),
     ((8, 12, 4, 2), 1, "fp32", 2),
     ((48, 48, 6, 5), 2, "fp32", 1),
+    # long x1 lines: the twiddle tables span several workgroup strides
+    ((300, 7, 3, 2), 1, "fp32", 1),
 ]
 
 
