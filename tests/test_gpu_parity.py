@@ -393,6 +393,10 @@ FORM_CASES = [
     ((13, 9, 4, 3), 1, (2,), 1),
     ((21, 6, 5), 2, (2,), 2),
     ((301, 4), 1, (1,), 1),
+    # lines shorter than 4 cells: one thread per line in the group form
+    ((3, 5), 2, (1,), 1),
+    ((1, 7), 1, (1,), 1),
+    ((2, 9, 3), 2, (2,), 1),
 ]
 
 
