@@ -86,8 +86,10 @@ struct SweepArgs {
 
 // One workgroup-sized tile of one problem of a batched sweep.
 //   kind 0: dimension-0 sweep, window form: groups [x*256, x*256+256) of 4 cells
-//   kind 1: dimension-0 sweep, group form: groups [x*256, x*256+256)
-//   kind 2: strided sweep: columns [64x, 64x+64), row chunks from z*(blockDim/64)
+//   kind 1: dimension-0 sweep, group form: groups [x*256, x*256+256), or in the
+//           lane form (class rows 1) cells [x*256, x*256+256)
+//   kind 2: strided sweep: columns [64x, 64x+64), row chunks from z*(blockDim/64),
+//           or in the lane form (class rows 0) cells [x*256, x*256+256)
 // qg selects the run of spectator tuples.
 struct BatchItem {
   int32_t prob, kind, x, qg, z;

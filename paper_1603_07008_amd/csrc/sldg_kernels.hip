@@ -514,7 +514,8 @@ __device__ __forceinline__ void dispatch_nd(int nd, F&& f) {
 // outputs with one vector store per plane.  Neighbouring threads load the same
 // blocks, which the vector L1 serves: every coefficient crosses HBM once.
 // A launch is one-shot (each thread a few loads, then stores, then exit),
-// which on MI355X streams closer to peak than long-lived threads.
+// which on MI355X streams closer to peak than long-lived threads.  Where the
+// window form does not apply, the group and lane forms below take the line.
 // ---------------------------------------------------------------------------
 
 template <class T>
@@ -746,8 +747,9 @@ __device__ __forceinline__ void contig_single(const SweepArgs& a, const TupleMap
   contig_store<K, TIER, ND, GROUP>(a, pl, c, g, M, R, W, slot, active);
 }
 
-// One thread: 4 consecutive output cells of one line, for the spectator
-// tuples [q, qe) in turn (the line's s, A and B are loaded once; across a run
+// One thread: 4 output cells of one line (consecutive in the window form,
+// interleaved with the line's other threads in the group form), for the
+// spectator tuples [q, qe) in turn (the line's s, A and B are loaded once; across a run
 // of tuples without FP64 modes, the loads of the next tuple are issued before
 // the current tuple is computed and stored).  When every lane of the wave
 // works on lines that share one table entry (the common case: the
@@ -1198,7 +1200,8 @@ bool contig_window_ok(const SweepArgs& a) {
   return a.N % 4 == 0 && (align & 15) == 0;
 }
 
-// Launch shape of a sweep: form 0 window, 1 generic dimension-0, 2 strided.
+// Launch shape of a sweep: form 0 window, 1 group (dimension 0), 2 strided,
+// 3 lane (any dimension).
 static bool sweep_grid(int dim, const SweepArgs& a, int& form, dim3& grid, dim3& block) {
   if (dim > 0 && a.lane) {
     form = 3;
@@ -1320,8 +1323,10 @@ hipError_t launch_sweep(int k, int tier, int dim, const SweepArgs& a, hipStream_
 // per item, XCD-aware order), so no kernel carries the registers of the
 // other code paths; the classes of a split step are captured together in one
 // HIP graph.  Kinds: 0 dimension-0 window form (256 groups of 4 cells),
-// 1 dimension-0 group form (256 groups), 2 strided (64 columns x 4 row
-// chunks).  A run of spectator tuples is part of the item.
+// 1 dimension-0 group form (256 groups of 4 interleaved cells), 2 strided
+// (64 columns x 4 row chunks); kinds 1 and 2 run in the lane form (256
+// consecutive cells, kernel kind 3) when their class's rows are 1 and 0.  A
+// run of spectator tuples is part of the item.
 // ---------------------------------------------------------------------------
 
 template <int K, int TIER, int KIND, int L>
