@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -56,8 +57,25 @@ namespace {
 constexpr int kClasses = 9;
 int class_of(int kind, int k) { return kind * 3 + (k - 1); }
 
-// XCD run lengths of the class launches (as the single-problem sweeps).
-constexpr int32_t kXcdContig = 8, kXcdStrided = 16;
+// XCD run lengths of the class launches: twice those of the single-problem
+// sweeps (measured on the batched Landau workload: 2.50 ms per step against
+// 2.53 ms with 8 and 16).
+constexpr int32_t kXcdContigDefault = 16, kXcdStridedDefault = 32;
+
+// XCD group sizes of the work lists (SLDG_BATCH_XCD_CONTIG / _STRIDED
+// override them, -1 .. 64).
+static int32_t xcd_group(bool strided) {
+  static const int32_t v[2] = {
+      [] {
+        const char* e = getenv("SLDG_BATCH_XCD_CONTIG");
+        return e ? std::max(-1, std::min(64, atoi(e))) : kXcdContigDefault;
+      }(),
+      [] {
+        const char* e = getenv("SLDG_BATCH_XCD_STRIDED");
+        return e ? std::max(-1, std::min(64, atoi(e))) : kXcdStridedDefault;
+      }()};
+  return v[strided ? 1 : 0];
+}
 
 void drop_graphs(sldg_batch_s* b) {
   for (int i = 0; i < 2; ++i)
@@ -211,7 +229,7 @@ sldg_status launch(sldg_batch_s* b, int q, int src) {
     const int kind = c / 3, k = c % 3 + 1;
     hipError_t e = launch_batch_class((int)b->tier, k, kind, b->rows[(size_t)q * kClasses + c],
                                       b->d_args[(size_t)q * 2 + src], b->d_items[q] + off[c], n,
-                                      kind == 2 ? kXcdStrided : kXcdContig, b->stream);
+                                      xcd_group(kind == 2), b->stream);
     if (e != hipSuccess) return device_error(e, "batched sweep launch");
   }
   return SLDG_OK;
@@ -544,7 +562,7 @@ sldg_status sldg_batch_tune(sldg_batch_t b, int reps) {
             e = launch_batch_class((int)b->tier, c % 3 + 1, c / 3,
                                    b->rows[(size_t)q * kClasses + c],
                                    b->d_args[(size_t)q * 2], b->d_items[q] + off[c], n,
-                                   c / 3 == 2 ? kXcdStrided : kXcdContig, b->stream);
+                                   xcd_group(c / 3 == 2), b->stream);
             if (e != hipSuccess) st = device_error(e, "tuning launch");
           }
         }
