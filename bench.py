@@ -575,7 +575,7 @@ def main():
         tiers_out[t] = ent
 
     out = {
-        "metric": "coefficient updates/s (and % of HBM peak per sweep); mixed vs FP64",
+        "metric": "Coefficient updates/s and % HBM peak per sweep; mixed vs FP64 at stated error",
         "value": value,
         "unit": "coeff-updates/s",
         "n_gpus": 1,
