@@ -102,3 +102,26 @@ def test_batch_rejects_bad_arguments_before_the_device(L):
     assert BL.sldg_batch_run(None, 1, 0, None) == sl.SLDG_ERR_ARG
     assert BL.sldg_batch_tune(None, 1) == sl.SLDG_ERR_ARG
     BL.sldg_batch_destroy(None)
+
+
+def test_tuner_candidates_are_valid_shapes(L):
+    """The autotuner's candidate lists (host data, no device): every shape is
+    one sldg_plan_set_shape accepts, the dimension-0 list offers the group
+    (rows 4) and lane (rows 1) forms with the same tuple counts, and the
+    strided list offers the lane form (rows 0) beside 2, 4 and 8 rows."""
+    def cands(strided):
+        out, i = [], 0
+        while True:
+            r, t, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+            st = L.sldg_tune_candidate(strided, i, ctypes.byref(r), ctypes.byref(t), ctypes.byref(c))
+            if st != 0:
+                assert st == sl.SLDG_ERR_ARG
+                return out
+            out.append((r.value, t.value, c.value))
+            i += 1
+    contig, strided = cands(0), cands(1)
+    assert {r for r, _, _ in contig} == {1, 4}
+    assert {t for r, t, _ in contig if r == 1} == {t for r, t, _ in contig if r == 4}
+    assert {r for r, _, _ in strided} == {0, 2, 4, 8}
+    assert all(c in (1, 2, 4) and t >= 0 for _, t, c in contig + strided)
+    assert len(set(strided)) == len(strided) and len(set(contig)) == len(contig)
