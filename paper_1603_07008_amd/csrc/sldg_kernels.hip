@@ -362,10 +362,27 @@ struct Mat {
 
 __device__ __forceinline__ float pow2f(int32_t e) { return __builtin_amdgcn_ldexpf(1.0f, e); }
 
+// Maximum over the 64 lanes of a wave (every lane active), in registers:
+// quad permutes (lane ^ 1, lane ^ 2) and row rotations (by 4, 8) give every
+// lane the maximum of its row of 16; the four rows meet through readlane.
+// The result is wave-uniform.  fmaxf ignores NaN operands, as in any order.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
+                                                               0xF, 0xF, true));
+}
+
 __device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-  return v;
+  v = fmaxf(v, dpp_f<0xB1>(v));     // quad_perm [1, 0, 3, 2]
+  v = fmaxf(v, dpp_f<0x4E>(v));     // quad_perm [2, 3, 0, 1]
+  v = fmaxf(v, dpp_f<0x124>(v));    // row_ror 4
+  v = fmaxf(v, dpp_f<0x128>(v));    // row_ror 8
+  const int b = __builtin_bit_cast(int, v);
+  const float r0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 0));
+  const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 16));
+  const float r2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 32));
+  const float r3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 48));
+  return fmaxf(fmaxf(r0, r1), fmaxf(r2, r3));
 }
 
 // Stored value -> register value (the FP16 tier widens and unscales).
