@@ -32,7 +32,8 @@ HBM_PEAK_GBS = 8000.0
 TIER_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}
 ARITH = {"fp64": "f64", "fp32": "f64", "bf16": "f32", "fp16": "f32"}
 KERNEL_SOURCES = ["paper_1603_07008_amd/csrc/sldg_kernels.hip", "paper_1603_07008_amd/csrc/ab_poly.h",
-                  "paper_1603_07008_amd/csrc/sldg_internal.h"]
+                  "paper_1603_07008_amd/csrc/sldg_internal.h", "paper_1603_07008_amd/csrc/sldg_sweep.h",
+                  "paper_1603_07008_amd/csrc/sldg_sweep_inst.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_vlasov4d_48_k2_fp32.json")
 
 

@@ -109,6 +109,15 @@ hipError_t launch_batch_class(int tier, int k, int kind, int rows, const SweepAr
                               const BatchItem* items, int32_t nitems, int32_t xcd,
                               hipStream_t st);
 bool contig_window_ok(const SweepArgs& a);
+
+// The launchers of one (degree K, storage tier) pair, explicitly
+// instantiated in sldg_sweep_inst.hip (compiled once per pair); launch_sweep
+// and launch_batch_class dispatch to them.
+template <int K, int TIER>
+hipError_t launch_sweep_inst(int dim, const SweepArgs& a, hipStream_t st);
+template <int K, int TIER>
+hipError_t launch_class_inst(int kind, int rows, const SweepArgs* args, const BatchItem* items,
+                             int32_t nitems, int32_t xcd, hipStream_t st);
 // Waves of one sweep launch that compute a given output plane (the absmax
 // partial slots per plane of a scaled FP16 sweep).
 int64_t sweep_slots(int dim, const SweepArgs& a);
