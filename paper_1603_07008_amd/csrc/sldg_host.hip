@@ -266,11 +266,11 @@ void free_plan(sldg_plan_s* p) {
 }
 
 // The absmax partial buffer holds at least n floats (grown with hipMalloc;
-// hipFree of the old one waits for the device).
+// hipFree of the old one waits for the device).  It owns d_part alone: the
+// field scratch is grown and freed only by ensure_field and free_plan.
 sldg_status ensure_part(sldg_plan_s* p, int64_t n) {
   if (n <= p->part_cap) return SLDG_OK;
   if (p->d_part) (void)hipFree(p->d_part);
-  if (p->d_field) (void)hipFree(p->d_field);
   p->d_part = nullptr;
   p->part_cap = 0;
   hipError_t e = hipMalloc(&p->d_part, sizeof(float) * (size_t)n);
