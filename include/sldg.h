@@ -336,6 +336,26 @@ sldg_status sldg_poisson_shift(sldg_plan_t plan, const double* mass, const void*
                                double hv, double dt, double* shift_out, double* field_out);
 
 /*
+ * sldg_poisson_shift for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, results and errors as sldg_poisson_shift, but
+ * the solve's scratch is a static device array of the library (4 MiB, one
+ * copy per device, held until the process ends) instead of a plan-owned
+ * buffer, and no call allocates or frees memory.
+ *   Limit: (9 (k+1) + 1) N_x + 1 <= 2^19 doubles of scratch when N_v >= 8
+ *          (N_x <= 14,169 at k = 3, 27,593 at k = 1); larger grids return
+ *          SLDG_ERR_UNSUPPORTED.
+ * Every call on one device shares that device's array, which keeps the last
+ * call's contents; nothing in it needs to start at zero.  Calls that overlap
+ * in time on one device (other streams, other threads, other plans) race on
+ * it: order them on one stream.  Errors: as sldg_poisson_shift, with
+ * SLDG_ERR_UNSUPPORTED for grids beyond the limit and never SLDG_ERR_NOMEM.
+ */
+sldg_status sldg_poisson_shift_noalloc(sldg_plan_t plan, const double* mass, const void* hi,
+                                       double hx, double hv, double dt, double* shift_out,
+                                       double* field_out);
+
+/*
  * nsteps self-consistent Strang steps of an (x, v) plan: X(dt/2) with the
  * displacements shift_x (device [N_v], per v line, dep_mask = 2), the field of
  * the state into shift_v (device [N_x], overwritten), V(dt) with shift_v,

@@ -27,8 +27,8 @@ EXPORTS = ("sldg_plan", "sldg_plan_destroy", "sldg_plan_set_stream", "sldg_line_
            "sldg_scaled_export", "sldg_advect_dim_scaled", "sldg_split_steps_scaled",
            "sldg_plan_set_shape", "sldg_plan_get_shape", "sldg_tune_candidate", "sldg_plan_tune",
            "sldg_device_plane_copy", "sldg_batch_get_class_tuning", "sldg_batch_set_class_tuning",
-           "sldg_poisson_shift", "sldg_vlasov_poisson_steps", "sldg_advect_dim_collocated",
-           "sldg_poisson_shift_2d", "sldg_vlasov_poisson_steps_2d2v")
+           "sldg_poisson_shift", "sldg_poisson_shift_noalloc", "sldg_vlasov_poisson_steps",
+           "sldg_advect_dim_collocated", "sldg_poisson_shift_2d", "sldg_vlasov_poisson_steps_2d2v")
 
 
 class SldgError(RuntimeError):
@@ -122,6 +122,8 @@ def lib():
     L.sldg_advect_dim_collocated.restype = i32
     L.sldg_poisson_shift.argtypes = [vp, vp, vp, dbl, dbl, dbl, vp, vp]
     L.sldg_poisson_shift.restype = i32
+    L.sldg_poisson_shift_noalloc.argtypes = [vp, vp, vp, dbl, dbl, dbl, vp, vp]
+    L.sldg_poisson_shift_noalloc.restype = i32
     L.sldg_vlasov_poisson_steps.argtypes = [vp, i32, vp, dbl, dbl, dbl, vp, vp, vp, vp, vp,
                                             ctypes.POINTER(i32)]
     L.sldg_vlasov_poisson_steps.restype = i32
@@ -324,6 +326,17 @@ class Plan:
     def poisson_shift(self, mass, hi, hx, hv, dt, shift_out=None, field_out=None):
         """The v-sweep displacements E(x_i) dt / hv of the state's field
         (sldg_poisson_shift); returns shift_out (device float64 [N_x])."""
+        return self._poisson_shift("sldg_poisson_shift", mass, hi, hx, hv, dt, shift_out,
+                                   field_out)
+
+    def poisson_shift_noalloc(self, mass, hi, hx, hv, dt, shift_out=None, field_out=None):
+        """poisson_shift through the allocation-free entry point
+        (sldg_poisson_shift_noalloc: static device scratch; calls that overlap
+        on one device race)."""
+        return self._poisson_shift("sldg_poisson_shift_noalloc", mass, hi, hx, hv, dt, shift_out,
+                                   field_out)
+
+    def _poisson_shift(self, entry, mass, hi, hx, hv, dt, shift_out, field_out):
         import torch
         self._check_state(mass, hi, "poisson_shift")
         nx = self.ncells[0]
@@ -334,10 +347,9 @@ class Plan:
                                   not t.is_contiguous() or t.numel() < nx):
                 raise ValueError(f"poisson_shift: {nm} must be a contiguous float64 device "
                                  f"tensor of >= {nx} elements")
-        _check(lib().sldg_poisson_shift(self.handle, _ptr(mass), _ptr(hi), float(hx), float(hv),
-                                        float(dt), _ptr(shift_out),
-                                        None if field_out is None else _ptr(field_out)),
-               "sldg_poisson_shift")
+        _check(getattr(lib(), entry)(self.handle, _ptr(mass), _ptr(hi), float(hx), float(hv),
+                                     float(dt), _ptr(shift_out),
+                                     None if field_out is None else _ptr(field_out)), entry)
         return shift_out
 
     def vlasov_poisson_steps(self, nsteps, shift_x, hx, hv, dt, state0, state1, shift_v=None):

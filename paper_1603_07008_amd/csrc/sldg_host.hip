@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -64,6 +65,20 @@ struct sldg_plan_s {
   int ev_dim[4096];
   int nev_created;
 };
+
+// Device memory of the allocation-free field solve (sldg_poisson_shift_noalloc):
+// a fixed array in the library's code object, one copy per device, held until
+// the process ends.  Host code never passes `scratch` itself to a kernel (on
+// the host it is only a stand-in for the symbol): it looks up each device's
+// address once, with hipGetSymbolAddress, and uses that.
+constexpr int64_t kStaticFieldDoubles = int64_t(1) << 19;    // 4 MiB
+static __device__ __align__(256) double scratch[kStaticFieldDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
 
 namespace sldg {
 
@@ -263,6 +278,24 @@ void free_plan(sldg_plan_s* p) {
   if (p->d_field) (void)hipFree(p->d_field);
   if (p->h_mass_out) (void)hipHostFree(p->h_mass_out);
   delete p;
+}
+
+// Looks up, once per device, the address of that device's copy of the static
+// field scratch (the device must be current).  Devices past kMaxDevices keep
+// no address; the allocation-free entry point then reports it.
+sldg_status scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return SLDG_OK;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return SLDG_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return device_error(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                        "hipGetSymbolAddress of the static field scratch");
+  }
+  g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  return SLDG_OK;
 }
 
 // The absmax partial buffer holds at least n floats (grown with hipMalloc;
@@ -487,6 +520,10 @@ sldg_status sldg_plan_ex(sldg_plan_t* out, int ndim, const int64_t* ncells, int 
   if (e != hipSuccess) {
     free_plan(p);
     return device_error(e, "hipGetDevice");
+  }
+  if (scratch_setup(p->device) != SLDG_OK) {
+    free_plan(p);
+    return SLDG_ERR_DEVICE;
   }
   const int64_t o2 = (int64_t)p->o * p->o;
   e = hipMalloc(&p->d_s, sizeof(int32_t) * p->table_cap);
@@ -973,8 +1010,10 @@ static sldg_status ensure_field(sldg_plan_t p, int64_t need) {
   return SLDG_OK;
 }
 
-sldg_status sldg_poisson_shift(sldg_plan_t p, const double* mass, const void* hi, double hx,
-                               double hv, double dt, double* shift_out, double* field_out) {
+// Arguments of a 1D-1V field solve: checks them and fills the mode planes.
+static sldg_status poisson_shift_args(sldg_plan_t p, const double* mass, const void* hi,
+                                      double hx, double hv, double dt, double* shift_out,
+                                      double* field_out, FieldPlanes& fp) {
   if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
   if (p->ndim != 2) return fail(SLDG_ERR_ARG, "the field solve needs an (x, v) plan (ndim = 2)");
   if (!(hx > 0.0) || !(hv > 0.0) || !std::isfinite(dt))
@@ -982,8 +1021,7 @@ sldg_status sldg_poisson_shift(sldg_plan_t p, const double* mass, const void* hi
   if (!shift_out) return fail(SLDG_ERR_ARG, "null shift_out");
   if (p->n_lo > 0 && !mass) return fail(SLDG_ERR_ARG, "null mass");
   if (p->n_hi > 0 && !hi) return fail(SLDG_ERR_ARG, "null hi");
-  const int32_t nx = (int32_t)p->n[0], nv = (int32_t)p->n[1];
-  const int64_t ob = 8LL * nx;
+  const int64_t ob = 8 * p->n[0];
   const void* outs[2] = {shift_out, field_out};
   for (int i = 0; i < 2; ++i) {
     if (!outs[i]) continue;
@@ -994,7 +1032,7 @@ sldg_status sldg_poisson_shift(sldg_plan_t p, const double* mass, const void* hi
   if (field_out && overlap(shift_out, ob, field_out, ob))
     return fail(SLDG_ERR_ALIAS, "shift_out overlaps field_out");
   // planes of the modes (j, 0): mode id j
-  FieldPlanes fp{};
+  fp = FieldPlanes{};
   for (int j = 0; j < p->o; ++j) {
     const int32_t v = p->h_pmap[j];
     fp.lo[j] = v < 0 ? 1 : 0;
@@ -1002,9 +1040,41 @@ sldg_status sldg_poisson_shift(sldg_plan_t p, const double* mass, const void* hi
                         : static_cast<const void*>(static_cast<const char*>(hi) +
                                                    (int64_t)v * p->cells * elem_size(p->tier));
   }
-  sldg_status st = ensure_field(p, field_scratch_doubles(p->o, nx, nv));
+  return SLDG_OK;
+}
+
+sldg_status sldg_poisson_shift(sldg_plan_t p, const double* mass, const void* hi, double hx,
+                               double hv, double dt, double* shift_out, double* field_out) {
+  FieldPlanes fp;
+  sldg_status st = poisson_shift_args(p, mass, hi, hx, hv, dt, shift_out, field_out, fp);
+  if (st != SLDG_OK) return st;
+  const int32_t nx = (int32_t)p->n[0], nv = (int32_t)p->n[1];
+  st = ensure_field(p, field_scratch_doubles(p->o, nx, nv));
   if (st != SLDG_OK) return st;
   hipError_t e = launch_field((int)p->tier, fp, p->o, nx, nv, hx, hv, dt, p->d_field, shift_out,
+                              field_out, p->stream);
+  if (e != hipSuccess) return device_error(e, "field launch");
+  return ok();
+}
+
+sldg_status sldg_poisson_shift_noalloc(sldg_plan_t p, const double* mass, const void* hi,
+                                       double hx, double hv, double dt, double* shift_out,
+                                       double* field_out) {
+  FieldPlanes fp;
+  sldg_status st = poisson_shift_args(p, mass, hi, hx, hv, dt, shift_out, field_out, fp);
+  if (st != SLDG_OK) return st;
+  const int32_t nx = (int32_t)p->n[0], nv = (int32_t)p->n[1];
+  const int64_t need = field_scratch_doubles(p->o, nx, nv);
+  if (need > kStaticFieldDoubles)
+    return fail(SLDG_ERR_UNSUPPORTED,
+                "allocation-free field solve: N_x = %d at degree %d needs %lld doubles of "
+                "scratch, more than the static %lld (use sldg_poisson_shift)",
+                (int)nx, p->k, (long long)need, (long long)kStaticFieldDoubles);
+  double* buf = (p->device >= 0 && p->device < kMaxDevices) ? g_scratch_ptr[p->device] : nullptr;
+  if (!buf)
+    return fail(SLDG_ERR_UNSUPPORTED, "allocation-free field solve: no static scratch on device %d",
+                p->device);
+  hipError_t e = launch_field((int)p->tier, fp, p->o, nx, nv, hx, hv, dt, buf, shift_out,
                               field_out, p->stream);
   if (e != hipSuccess) return device_error(e, "field launch");
   return ok();
