@@ -294,10 +294,12 @@ def sweep(state, ns, k, dim, sigma, dep=(), tier="fp64", sel=None, absolute=Fals
     return out
 
 
-def sweep_adjoint(grad, ns, k, dim, sigma, dep=()):
+def sweep_adjoint(grad, ns, k, dim, sigma, dep=(), absolute=False):
     """Transpose of `sweep` (FP64, no rounding) with the same displacements:
     the gradient with respect to the sweep's input of a function of its
-    output, given the gradient with respect to the output."""
+    output, given the gradient with respect to the output.  With `absolute`,
+    |A|, |B| and |grad|: the magnitude sum of every output, which bounds the
+    rounding error of any evaluation order (as in `sweep`)."""
     ns = [int(v) for v in ns]
     ndim = len(ns)
     if dim in dep:
@@ -311,6 +313,9 @@ def sweep_adjoint(grad, ns, k, dim, sigma, dep=()):
     if sigma.size != ntab:
         raise ValueError(f"need {ntab} displacements, got {sigma.size}")
     s_tab, ab_tab = line_tables(sigma, k)
+    if absolute:
+        ab_tab = np.abs(ab_tab)
+        grad = np.abs(grad)
     out = np.empty((M, C))
     nsarr = np.asarray(ns, dtype=np.int64)
     _load().oracle_sweep_adjoint(ndim, nsarr.ctypes.data, k, dim, stride.ctypes.data,

@@ -7,7 +7,7 @@ import pytest
 
 from oracle import sldg_oracle as O
 from paper_1603_07008_amd import inputs
-from gpu_helpers import download, have_gpu, upload, weighted_rel_l2
+from gpu_helpers import assert_sweep_close, download, have_gpu, upload, weighted_rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -59,6 +59,43 @@ def test_adjoint_sweep_matches_oracle_transpose(sl, case):
         lhs = math.fsum((download(*mx) * g).ravel().tolist())
         rhs = math.fsum((x * got).ravel().tolist())
         assert abs(lhs - rhs) <= 1e-12 * math.sqrt(g.size) * (1 + abs(lhs))
+
+
+NARROW = [((64,), 2, {0: ()}), ((37, 19), 3, {0: (1,), 1: (0,)}),
+          ((48, 10), 2, {0: (1,), 1: (0,)}), ((12, 10, 8, 9), 2, {0: (2,), 1: (3,), 2: (0, 1)}),
+          ((6, 4, 5, 3), 1, {0: (2, 3), 3: (1,)})]
+
+
+@pytest.mark.parametrize("tier", ["fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("case", NARROW, ids=["x".join(map(str, c[0])) + f"-k{c[1]}" for c in NARROW])
+def test_adjoint_sweep_narrow_tiers_match_oracle(sl, case, tier):
+    # The transpose sweep in a narrow tier is the forward kernels on the
+    # transposed tables, so it rounds as a forward sweep does: each output is
+    # the exact transpose sum up to the tier's accumulation error, rounded to
+    # the storage type (mode 0 computed and stored in FP64).  Compared element
+    # by element with the oracle's FP64 transpose rounded to the tier, under
+    # the single-sweep bound with the transpose's own magnitude sums.
+    import torch
+    ns, k, deps = case
+    cells = int(np.prod(ns))
+    rng = np.random.default_rng(3 * cells + k)
+    g = O.to_tier(inputs.random_coefficients(len(ns), k, cells, seed=cells + k), tier)
+    p = sl.Plan(ns, k, tier)
+    gi = upload(g, tier)
+    go = p.empty_state()
+    for dim, dep in deps.items():
+        nsig = int(np.prod([ns[e] for e in dep])) if dep else 1
+        sig = rng.uniform(-2.5 * ns[dim], 2.5 * ns[dim], nsig)
+        p.advect_dim_adjoint(dim, _dev(sig), sum(1 << e for e in dep), gi[0], gi[1], go[0], go[1])
+        torch.cuda.synchronize()
+        got = download(*go)
+        want = O.to_tier(O.sweep_adjoint(g, ns, k, dim, sig, dep), tier)
+        mag = O.sweep_adjoint(g, ns, k, dim, sig, dep, absolute=True)
+        assert_sweep_close(got, want, mag, tier, k, f"{tier} adjoint {ns} dim {dim}")
+        # the mass output is a transpose sum in FP64 from exactly widened inputs
+        m_ex = O.sweep_adjoint(g, ns, k, dim, sig, dep)[0]
+        assert np.all(np.abs(got[0] - m_ex) <= 8 * (k + 1) * 2.0 ** -52 * mag[0] + 1e-300)
+    p.close()
 
 
 def _setup_diff(sl, n, steps):

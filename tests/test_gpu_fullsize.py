@@ -1,11 +1,15 @@
 """Full-size parity on the benchmark's grid: the 4D workload at 48^4 cells,
 k = 2, 81 coefficients per cell.
 
-* Every sweep direction, in the FP64, FP32-mode and BF16-mode tiers, under
-  every launch shape the autotuner can choose (the shapes the benchmark may
-  time).  Each sweep is compared with the oracle on sampled output cells, with
+* Every sweep direction, in the FP64, FP32-mode, BF16-mode and FP16-mode
+  tiers, under every launch shape the autotuner can choose (the shapes the
+  benchmark may time).  Each sweep is compared with the oracle on sampled output cells, with
   the single-sweep element bound, and each shape must reproduce the first one
   bitwise (a shape splits the work differently, never the arithmetic).
+* Every sweep direction with scaled FP16 storage under every launch shape:
+  exponents and absmax exactly as the oracle's scaling policy decides them
+  (they depend on the whole output), values on sampled cells within the FP16
+  bound at each plane's scale, and every shape bitwise equal to the first.
 * One whole split step (6 sweeps) in FP32-mode and BF16-mode against the
   oracle's FP64 step, in the weighted L2 norm, with the mass drift.
 
@@ -69,7 +73,7 @@ def _gather(torch, mass, hi, sel_d):
     return torch.cat([m[None], h], 0).cpu().numpy()
 
 
-@pytest.mark.parametrize("tier", ["fp32", "fp64", "bf16"])
+@pytest.mark.parametrize("tier", ["fp32", "fp64", "bf16", "fp16"])
 def test_full_size_sweeps_every_direction_and_launch_shape(sl, big, tier):
     import torch
     prob, st0 = big
@@ -127,4 +131,53 @@ def test_full_size_split_step_against_fp64_oracle(sl, big, tier, tol):
     assert rel < tol, rel
     m0, m1 = O.mass_sum(state[0]), O.mass_sum(m)
     assert abs(m1 - m0) <= 1e-14 * abs(m0)
+    plan.close()
+
+
+@pytest.mark.parametrize("dim", [0, 1, 2, 3])
+def test_full_size_scaled_fp16_sweep_every_launch_shape(sl, big, dim):
+    import torch
+    from test_gpu_scaled import _check_sweep
+    prob, st0 = big
+    sw = next(s for s in prob.seq if s.dim == dim)
+    vals, e_in, a_in = O.to_scaled(st0, prob.k, prob.ndim)
+    want = O.sweep_scaled(vals, e_in, a_in, prob.ns, prob.k, dim, sw.sigma, sw.dep)
+    sel = _sample(prob, 3000, 11 + dim)
+    mag = O.sweep(vals, prob.ns, prob.k, dim, sw.sigma, sw.dep, sel=sel, absolute=True)
+    want_sel = (want[0][:, sel], want[1], want[2])
+    plan = sl.Plan(prob.ns, prob.k, "fp16")
+    # upload the scaled state: FP16 planes hold value * 2^e
+    m_in = torch.from_numpy(np.ascontiguousarray(vals[0])).cuda()
+    h_in = torch.empty((plan.n_hi, plan.cells), dtype=torch.float16, device="cuda")
+    for p in range(plan.n_hi):
+        row = torch.from_numpy(np.ldexp(vals[p + 1], int(e_in[p + 1]))).cuda()
+        h_in[p] = row.to(torch.float16)
+        assert torch.equal(h_in[p].to(torch.float64), row), "not an FP16 state"
+    del vals, want
+    s_in = plan.empty_scale()
+    s_in[0] = torch.from_numpy(e_in[1:].astype(np.int32)).cuda()
+    s_in[1] = torch.from_numpy(a_in[1:].astype(np.float32).view(np.int32)).cuda()
+    m_out, h_out = plan.empty_state()
+    s_out = plan.empty_scale()
+    sel_d = torch.from_numpy(sel).cuda()
+    shift = torch.from_numpy(sw.sigma).cuda()
+    keep = O.fp64_modes(prob.ndim, prob.k).astype(bool)
+    first = None
+    for shape in sl.tune_candidates(dim > 0):
+        plan.set_shape(dim, shape["rows"], shape["tuples"], shape["colwaves"])
+        plan.advect_dim_scaled(dim, shift, sw.dep_mask, m_in, h_in, s_in, m_out, h_out, s_out)
+        sc = s_out.cpu().numpy()
+        e_h = sc[0].astype(np.int64)
+        a_h = sc[1].view(np.float32).astype(np.float64)
+        raw = _gather(torch, m_out, h_out, sel_d)
+        if first is None:
+            vals_g = raw.copy()
+            vals_g[1:] = np.ldexp(raw[1:], -e_h[:, None])
+            e = np.concatenate([[0], e_h])
+            a = np.concatenate([[0.0], a_h])
+            _check_sweep((vals_g, e, a), want_sel, mag, keep, prob.k, f"scaled dim {dim}")
+            first = (raw, sc)
+        else:
+            assert np.array_equal(raw, first[0]) and np.array_equal(sc, first[1]), \
+                f"scaled dim {dim}: shape {shape} differs"
     plan.close()

@@ -143,6 +143,12 @@ CASES = [
     ((12, 10, 9), 1, 2, (0, 1), 4),     # strided, partial row chunk, ragged columns
     ((12, 10, 9), 3, 1, (2,), 5),
     ((16, 6, 5), 3, 0, (2,), 6),
+    # 4D (x1, x2, v1, v2): every sweep direction of the split step
+    ((10, 8, 6, 5), 2, 0, (2,), 10),    # dimension-0 window form, shift from v1
+    ((10, 8, 6, 5), 2, 1, (3,), 11),    # strided x2, shift from v2
+    ((10, 8, 6, 5), 2, 2, (0, 1), 12),  # strided v1, per-lane shifts from (x1, x2)
+    ((9, 7, 5, 6), 1, 3, (0, 1), 13),   # strided v2, ragged columns
+    ((9, 7, 5, 6), 3, 0, (2,), 14),     # dimension-0 generic form (N_0 odd)
 ]
 
 

@@ -460,6 +460,13 @@ def test_adjoint_equals_weighted_reflected_forward(k):
     sigma = 2.6
     via_forward = W @ O.sweep(Wi @ g, (n,), k, 0, -sigma)
     assert np.allclose(O.sweep_adjoint(g, (n,), k, 0, sigma), via_forward, atol=1e-13, rtol=0)
+    # the magnitude form: |W F W^-1| = W |F| W^-1 for the positive diagonal W,
+    # so the absolute transpose equals the weight-conjugated absolute forward
+    # sweep with the opposite displacement, and bounds the transpose itself
+    mag = O.sweep_adjoint(g, (n,), k, 0, sigma, absolute=True)
+    via_abs = W @ O.sweep(Wi @ np.abs(g), (n,), k, 0, -sigma, absolute=True)
+    assert np.allclose(mag, via_abs, atol=1e-13, rtol=0)
+    assert np.all(mag >= np.abs(O.sweep_adjoint(g, (n,), k, 0, sigma)) - 1e-15)
 
 
 # --------------------------------------------------------------------------
