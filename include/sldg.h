@@ -44,7 +44,8 @@ typedef enum {
     SLDG_ERR_ARG = 1,          /* null pointer, bad dimension, bad mask, bad size */
     SLDG_ERR_ALIAS = 2,        /* an output buffer overlaps an input or another output */
     SLDG_ERR_UNSUPPORTED = 3,  /* degree or tier without a compiled kernel, grid too large */
-    SLDG_ERR_NOMEM = 4,        /* device allocation of the plan's tables failed */
+    SLDG_ERR_NOMEM = 4,        /* a device allocation of the library failed, or would
+                                  pass the limit of sldg_set_device_alloc_limit */
     SLDG_ERR_DEVICE = 5        /* a HIP call or kernel launch failed */
 } sldg_status;
 
@@ -507,6 +508,23 @@ sldg_status sldg_batch_get_class_tuning(sldg_batch_t batch, int q, int cls, int*
                                         int* tuples, double* ms, int* nitems);
 /* Set the launch shape of class `cls` of sweep q alone. */
 sldg_status sldg_batch_set_class_tuning(sldg_batch_t batch, int q, int cls, int rows, int tuples);
+
+/*
+ * Device memory the library allocates for itself: plan tables, the scaled
+ * FP16 partials, the field scratch and batch work lists (never the caller's
+ * state buffers).  sldg_set_device_alloc_limit caps the bytes of these
+ * allocations held at once, process-wide and over all devices; an allocation
+ * that would pass the cap fails as if the device were out of memory, so the
+ * call that needed it returns SLDG_ERR_NOMEM and leaves its plan or batch
+ * usable (a plan is refused before any device call when its tables alone
+ * pass the cap).  bytes = -1 removes the cap (the default); other negative
+ * values give SLDG_ERR_ARG.  Allocations already held are kept when the cap
+ * falls below them.  sldg_device_alloc_bytes returns the bytes held now.  A
+ * robustness facility for callers that budget device memory, and the way
+ * tests force the out-of-memory paths.
+ */
+sldg_status sldg_set_device_alloc_limit(int64_t bytes);
+int64_t sldg_device_alloc_bytes(void);
 
 const char* sldg_status_string(sldg_status s);
 const char* sldg_last_error(void);

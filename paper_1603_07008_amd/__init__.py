@@ -28,7 +28,8 @@ EXPORTS = ("sldg_plan", "sldg_plan_destroy", "sldg_plan_set_stream", "sldg_line_
            "sldg_plan_set_shape", "sldg_plan_get_shape", "sldg_tune_candidate", "sldg_plan_tune",
            "sldg_device_plane_copy", "sldg_batch_get_class_tuning", "sldg_batch_set_class_tuning",
            "sldg_poisson_shift", "sldg_poisson_shift_noalloc", "sldg_vlasov_poisson_steps",
-           "sldg_advect_dim_collocated", "sldg_poisson_shift_2d", "sldg_vlasov_poisson_steps_2d2v")
+           "sldg_advect_dim_collocated", "sldg_poisson_shift_2d", "sldg_vlasov_poisson_steps_2d2v",
+           "sldg_set_device_alloc_limit", "sldg_device_alloc_bytes")
 
 
 class SldgError(RuntimeError):
@@ -132,6 +133,10 @@ def lib():
     L.sldg_vlasov_poisson_steps_2d2v.argtypes = [vp, i32, vp, vp, ctypes.POINTER(dbl), dbl, vp,
                                                  vp, vp, vp, vp, vp, ctypes.POINTER(i32)]
     L.sldg_vlasov_poisson_steps_2d2v.restype = i32
+    L.sldg_set_device_alloc_limit.argtypes = [i64]
+    L.sldg_set_device_alloc_limit.restype = i32
+    L.sldg_device_alloc_bytes.argtypes = []
+    L.sldg_device_alloc_bytes.restype = i64
     L.sldg_status_string.argtypes = [i32]
     L.sldg_status_string.restype = ctypes.c_char_p
     L.sldg_last_error.argtypes = []
@@ -648,6 +653,18 @@ def device_plane_copy(src, dst, plane_bytes, nplanes, planes_per_thread, stream=
     _check(lib().sldg_device_plane_copy(_ptr(src), _ptr(dst), int(plane_bytes), int(nplanes),
                                         int(planes_per_thread), ctypes.c_void_p(st)),
            "sldg_device_plane_copy")
+
+
+def set_device_alloc_limit(nbytes):
+    """Cap on the device bytes the library holds for its own buffers
+    (sldg_set_device_alloc_limit); None or -1 removes it."""
+    _check(lib().sldg_set_device_alloc_limit(-1 if nbytes is None else int(nbytes)),
+           "sldg_set_device_alloc_limit")
+
+
+def device_alloc_bytes():
+    """Device bytes the library holds for its own buffers now."""
+    return int(lib().sldg_device_alloc_bytes())
 
 
 def device_copy(src, dst, nbytes=None, stream=None):

@@ -86,8 +86,8 @@ void drop_graphs(sldg_batch_s* b) {
 }
 
 void free_work(sldg_batch_s* b) {
-  for (auto* p : b->d_args) if (p) (void)hipFree(p);
-  for (auto* p : b->d_items) if (p) (void)hipFree(p);
+  for (auto* p : b->d_args) if (p) dev_free(p);
+  for (auto* p : b->d_items) if (p) dev_free(p);
   b->d_args.clear();
   b->d_items.clear();
   b->nitems.clear();
@@ -99,9 +99,9 @@ void free_batch(sldg_batch_s* b) {
   if (!b) return;
   drop_graphs(b);
   free_work(b);
-  if (b->d_s) (void)hipFree(b->d_s);
-  if (b->d_ab) (void)hipFree(b->d_ab);
-  if (b->d_pmap) (void)hipFree(b->d_pmap);
+  if (b->d_s) dev_free(b->d_s);
+  if (b->d_ab) dev_free(b->d_ab);
+  if (b->d_pmap) dev_free(b->d_pmap);
   delete b;
 }
 
@@ -110,7 +110,7 @@ const int64_t* ext(const sldg_batch_s* b, int p) { return b->n.data() + (size_t)
 bool aligned16(const void* x) { return ((uintptr_t)x & 15) == 0; }
 
 // Build the device argument blocks and work list of sweep q.
-sldg_status build_sweep(sldg_batch_s* b, int q) {
+sldg_status build_sweep_impl(sldg_batch_s* b, int q) {
   const int dim = b->dims[q];
   std::vector<SweepArgs> args[2];
   std::vector<BatchItem> bucket[kClasses];
@@ -186,7 +186,7 @@ sldg_status build_sweep(sldg_batch_s* b, int q) {
   for (int s = 0; s < 2; ++s) {
     SweepArgs*& d = b->d_args[(size_t)q * 2 + s];
     if (!d) {
-      hipError_t e = hipMalloc(&d, sizeof(SweepArgs) * b->nprob);
+      hipError_t e = dev_malloc(&d, sizeof(SweepArgs) * b->nprob);
       if (e != hipSuccess) return fail(SLDG_ERR_NOMEM, "batch arguments: %s", hipGetErrorString(e));
     }
     hipError_t e = hipMemcpy(d, args[s].data(), sizeof(SweepArgs) * b->nprob, hipMemcpyHostToDevice);
@@ -194,11 +194,11 @@ sldg_status build_sweep(sldg_batch_s* b, int q) {
   }
   BatchItem*& di = b->d_items[q];
   if (di) {
-    (void)hipFree(di);
+    dev_free(di);
     di = nullptr;
   }
   if (!items.empty()) {
-    hipError_t e = hipMalloc(&di, sizeof(BatchItem) * items.size());
+    hipError_t e = dev_malloc(&di, sizeof(BatchItem) * items.size());
     if (e != hipSuccess) return fail(SLDG_ERR_NOMEM, "batch work list: %s", hipGetErrorString(e));
     e = hipMemcpy(di, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return device_error(e, "batch work list upload");
@@ -207,8 +207,17 @@ sldg_status build_sweep(sldg_batch_s* b, int q) {
   return SLDG_OK;
 }
 
+// A sweep whose work list could not be built leaves the batch not ready (run
+// refuses) until the states or the sequence are set again.
+sldg_status build_sweep(sldg_batch_s* b, int q) {
+  const sldg_status st = build_sweep_impl(b, q);
+  if (st != SLDG_OK) b->ready = false;
+  return st;
+}
+
 sldg_status build_all(sldg_batch_s* b) {
   drop_graphs(b);
+  b->ready = false;
   if (!b->bound || b->nseq == 0) return SLDG_OK;
   b->d_args.resize((size_t)b->nseq * 2, nullptr);
   b->d_items.resize(b->nseq, nullptr);
@@ -286,12 +295,13 @@ sldg_status sldg_batch_create(sldg_batch_t* out, int nprob, int ndim, const int6
     pm.push_back(-1);
     for (int64_t m = 1; m < b->modes[p]; ++m) pm.push_back((int32_t)(m - 1));
   }
-  if (e == hipSuccess) e = hipMalloc(&b->d_pmap, sizeof(int32_t) * pm.size());
+  if (e == hipSuccess) e = dev_malloc(&b->d_pmap, sizeof(int32_t) * pm.size());
   if (e == hipSuccess)
     e = hipMemcpy(b->d_pmap, pm.data(), sizeof(int32_t) * pm.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     free_batch(b);
-    return device_error(e, "batch create");
+    return e == hipErrorOutOfMemory ? fail(SLDG_ERR_NOMEM, "batch mode maps: %s", hipGetErrorString(e))
+                                    : device_error(e, "batch create");
   }
   *out = b;
   return ok();
@@ -342,8 +352,8 @@ sldg_status sldg_batch_set_sequence(sldg_batch_t b, int nseq, const int* dims,
   }
   drop_graphs(b);
   free_work(b);
-  if (b->d_s) (void)hipFree(b->d_s);
-  if (b->d_ab) (void)hipFree(b->d_ab);
+  if (b->d_s) dev_free(b->d_s);
+  if (b->d_ab) dev_free(b->d_ab);
   b->d_s = nullptr;
   b->d_ab = nullptr;
   b->nseq = nseq;
@@ -367,16 +377,26 @@ sldg_status sldg_batch_set_sequence(sldg_batch_t b, int nseq, const int* dims,
       tot_s += nt;
       tot_ab += nt * 2 * o * o;
     }
-  hipError_t e = hipMalloc(&b->d_s, sizeof(int32_t) * std::max<int64_t>(1, tot_s));
-  if (e == hipSuccess) e = hipMalloc(&b->d_ab, sizeof(double) * std::max<int64_t>(1, tot_ab));
-  if (e != hipSuccess) return fail(SLDG_ERR_NOMEM, "batch tables: %s", hipGetErrorString(e));
+  // on failure the batch keeps no sequence (and so cannot run on missing tables)
+  auto drop_sequence = [&](sldg_status st) {
+    if (b->d_s) dev_free(b->d_s);
+    if (b->d_ab) dev_free(b->d_ab);
+    b->d_s = nullptr;
+    b->d_ab = nullptr;
+    b->nseq = 0;
+    return st;
+  };
+  hipError_t e = dev_malloc(&b->d_s, sizeof(int32_t) * std::max<int64_t>(1, tot_s));
+  if (e == hipSuccess) e = dev_malloc(&b->d_ab, sizeof(double) * std::max<int64_t>(1, tot_ab));
+  if (e != hipSuccess)
+    return drop_sequence(fail(SLDG_ERR_NOMEM, "batch tables: %s", hipGetErrorString(e)));
   for (int q = 0; q < nseq; ++q)
     for (int p = 0; p < b->nprob; ++p) {
       const size_t i = (size_t)q * b->nprob + p;
       e = launch_line_tables(b->k[p], b->tab_n[i], ext(b, p)[dims[q]], shifts[i],
                              b->d_s + b->tab_off[i], b->d_ab + b->ab_off[i], true, false,
                              b->stream);
-      if (e != hipSuccess) return device_error(e, "batch line tables");
+      if (e != hipSuccess) return drop_sequence(device_error(e, "batch line tables"));
     }
   b->rows.assign((size_t)nseq * kClasses, 4);
   b->tuples.assign((size_t)nseq * kClasses, 9);

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <unordered_map>
 #include <vector>
 
 #include "sldg.h"
@@ -117,6 +118,47 @@ bool overlap(const void* a, int64_t na, const void* b, int64_t nb) {
 
 sldg_status device_error(hipError_t e, const char* what) {
   return fail(SLDG_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+namespace {
+std::mutex g_alloc_mu;
+int64_t g_alloc_limit = -1;                    // bytes; -1: no limit
+int64_t g_alloc_live = 0;                      // bytes held by live allocations
+std::unordered_map<void*, size_t> g_alloc_size;
+}  // namespace
+
+hipError_t dev_malloc_raw(void** p, size_t bytes) {
+  std::lock_guard<std::mutex> lock(g_alloc_mu);
+  *p = nullptr;
+  if (g_alloc_limit >= 0 && g_alloc_live + (int64_t)bytes > g_alloc_limit)
+    return hipErrorOutOfMemory;
+  const hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return e;
+  }
+  g_alloc_size[*p] = bytes;
+  g_alloc_live += (int64_t)bytes;
+  return hipSuccess;
+}
+
+void dev_free(void* p) {
+  if (!p) return;
+  {
+    std::lock_guard<std::mutex> lock(g_alloc_mu);
+    auto it = g_alloc_size.find(p);
+    if (it != g_alloc_size.end()) {
+      g_alloc_live -= (int64_t)it->second;
+      g_alloc_size.erase(it);
+    }
+  }
+  (void)hipFree(p);
+}
+
+bool dev_alloc_fits(int64_t bytes) {
+  std::lock_guard<std::mutex> lock(g_alloc_mu);
+  return g_alloc_limit < 0 || g_alloc_live + bytes <= g_alloc_limit;
 }
 
 void describe_grid(int ndim, const int64_t* n, int o, int64_t modes, int dim, uint32_t dep_mask,
@@ -267,15 +309,15 @@ constexpr int kNumTuneStrided = sizeof(kTuneStrided) / sizeof(kTuneStrided[0]);
 void free_plan(sldg_plan_s* p) {
   if (!p) return;
   for (int q = 0; q < p->nev_created; ++q) (void)hipEventDestroy(p->ev[q]);
-  if (p->d_s) (void)hipFree(p->d_s);
-  if (p->d_ab) (void)hipFree(p->d_ab);
-  if (p->d_mass_part) (void)hipFree(p->d_mass_part);
-  if (p->d_mass_out) (void)hipFree(p->d_mass_out);
-  if (p->d_pmap) (void)hipFree(p->d_pmap);
-  if (p->d_hmode) (void)hipFree(p->d_hmode);
-  if (p->d_redo) (void)hipFree(p->d_redo);
-  if (p->d_part) (void)hipFree(p->d_part);
-  if (p->d_field) (void)hipFree(p->d_field);
+  if (p->d_s) dev_free(p->d_s);
+  if (p->d_ab) dev_free(p->d_ab);
+  if (p->d_mass_part) dev_free(p->d_mass_part);
+  if (p->d_mass_out) dev_free(p->d_mass_out);
+  if (p->d_pmap) dev_free(p->d_pmap);
+  if (p->d_hmode) dev_free(p->d_hmode);
+  if (p->d_redo) dev_free(p->d_redo);
+  if (p->d_part) dev_free(p->d_part);
+  if (p->d_field) dev_free(p->d_field);
   if (p->h_mass_out) (void)hipHostFree(p->h_mass_out);
   delete p;
 }
@@ -298,15 +340,15 @@ sldg_status scratch_setup(int dev) {
   return SLDG_OK;
 }
 
-// The absmax partial buffer holds at least n floats (grown with hipMalloc;
-// hipFree of the old one waits for the device).  It owns d_part alone: the
+// The absmax partial buffer holds at least n floats (grown with dev_malloc;
+// freeing the old one waits for the device).  It owns d_part alone: the
 // field scratch is grown and freed only by ensure_field and free_plan.
 sldg_status ensure_part(sldg_plan_s* p, int64_t n) {
   if (n <= p->part_cap) return SLDG_OK;
-  if (p->d_part) (void)hipFree(p->d_part);
+  if (p->d_part) dev_free(p->d_part);
   p->d_part = nullptr;
   p->part_cap = 0;
-  hipError_t e = hipMalloc(&p->d_part, sizeof(float) * (size_t)n);
+  hipError_t e = dev_malloc(&p->d_part, sizeof(float) * (size_t)n);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return e == hipErrorOutOfMemory ? fail(SLDG_ERR_NOMEM, "absmax partials: %s", hipGetErrorString(e))
@@ -425,6 +467,18 @@ sldg_status run_sweep(sldg_plan_s* p, int dim, const double* shift, uint32_t dep
 
 extern "C" {
 
+sldg_status sldg_set_device_alloc_limit(int64_t bytes) {
+  if (bytes < -1) return fail(SLDG_ERR_ARG, "allocation limit %lld < -1", (long long)bytes);
+  std::lock_guard<std::mutex> lock(g_alloc_mu);
+  g_alloc_limit = bytes;
+  return ok();
+}
+
+int64_t sldg_device_alloc_bytes(void) {
+  std::lock_guard<std::mutex> lock(g_alloc_mu);
+  return g_alloc_live;
+}
+
 const char* sldg_status_string(sldg_status s) {
   switch (s) {
     case SLDG_OK: return "ok";
@@ -516,6 +570,20 @@ sldg_status sldg_plan_ex(sldg_plan_t* out, int ndim, const int64_t* ncells, int 
     p->colwaves_d[d] = colwaves;
   }
   p->rows_d[0] = 0;         // dimension 0: automatic form
+  const int64_t o2 = (int64_t)p->o * p->o;
+  p->mass_nblocks = mass_blocks(cells);
+  // the plan's device tables, checked against the allocation limit before any
+  // device call
+  const int64_t plan_bytes = (int64_t)sizeof(int32_t) * p->table_cap +
+                             (int64_t)sizeof(double) * 2 * o2 * p->table_cap +
+                             (int64_t)sizeof(double) * (2 * p->mass_nblocks + 2) +
+                             (int64_t)sizeof(int32_t) * p->modes +
+                             (tier == SLDG_TIER_FP16 ? (int64_t)sizeof(int32_t) * 2 * p->n_hi : 0);
+  if (!dev_alloc_fits(plan_bytes)) {
+    free_plan(p);
+    return fail(SLDG_ERR_NOMEM, "plan tables: %lld bytes exceed the device allocation limit",
+                (long long)plan_bytes);
+  }
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) {
     free_plan(p);
@@ -525,22 +593,20 @@ sldg_status sldg_plan_ex(sldg_plan_t* out, int ndim, const int64_t* ncells, int 
     free_plan(p);
     return SLDG_ERR_DEVICE;
   }
-  const int64_t o2 = (int64_t)p->o * p->o;
-  e = hipMalloc(&p->d_s, sizeof(int32_t) * p->table_cap);
-  if (e == hipSuccess) e = hipMalloc(&p->d_ab, sizeof(double) * 2 * o2 * p->table_cap);
-  p->mass_nblocks = mass_blocks(cells);
-  if (e == hipSuccess) e = hipMalloc(&p->d_mass_part, sizeof(double) * 2 * p->mass_nblocks);
-  if (e == hipSuccess) e = hipMalloc(&p->d_mass_out, sizeof(double) * 2);
+  e = dev_malloc(&p->d_s, sizeof(int32_t) * p->table_cap);
+  if (e == hipSuccess) e = dev_malloc(&p->d_ab, sizeof(double) * 2 * o2 * p->table_cap);
+  if (e == hipSuccess) e = dev_malloc(&p->d_mass_part, sizeof(double) * 2 * p->mass_nblocks);
+  if (e == hipSuccess) e = dev_malloc(&p->d_mass_out, sizeof(double) * 2);
   if (e == hipSuccess) e = hipHostMalloc(&p->h_mass_out, sizeof(double) * 2, hipHostMallocDefault);
-  if (e == hipSuccess) e = hipMalloc(&p->d_pmap, sizeof(int32_t) * p->modes);
+  if (e == hipSuccess) e = dev_malloc(&p->d_pmap, sizeof(int32_t) * p->modes);
   if (e == hipSuccess)
     e = hipMemcpy(p->d_pmap, p->h_pmap.data(), sizeof(int32_t) * p->modes, hipMemcpyHostToDevice);
   if (e == hipSuccess && tier == SLDG_TIER_FP16 && p->n_hi > 0) {
     std::vector<int32_t> hmode((size_t)p->n_hi);
     for (int64_t m = 0; m < p->modes; ++m)
       if (p->h_pmap[m] >= 0) hmode[(size_t)p->h_pmap[m]] = (int32_t)m;
-    e = hipMalloc(&p->d_hmode, sizeof(int32_t) * p->n_hi);
-    if (e == hipSuccess) e = hipMalloc(&p->d_redo, sizeof(int32_t) * p->n_hi);
+    e = dev_malloc(&p->d_hmode, sizeof(int32_t) * p->n_hi);
+    if (e == hipSuccess) e = dev_malloc(&p->d_redo, sizeof(int32_t) * p->n_hi);
     if (e == hipSuccess)
       e = hipMemcpy(p->d_hmode, hmode.data(), sizeof(int32_t) * p->n_hi, hipMemcpyHostToDevice);
   }
@@ -994,14 +1060,14 @@ sldg_status sldg_advect_dim_collocated(sldg_plan_t p, int dim, int tdim, const d
   return ok();
 }
 
-// Grows the plan's field scratch to `need` doubles (hipFree waits for the
-// device, so earlier solves that used the old buffer have finished).
+// Grows the plan's field scratch to `need` doubles (freeing the old one waits
+// for the device, so earlier solves that used the old buffer have finished).
 static sldg_status ensure_field(sldg_plan_t p, int64_t need) {
   if (need <= p->field_cap) return SLDG_OK;
-  if (p->d_field) (void)hipFree(p->d_field);
+  if (p->d_field) dev_free(p->d_field);
   p->d_field = nullptr;
   p->field_cap = 0;
-  hipError_t e = hipMalloc(&p->d_field, sizeof(double) * (size_t)need);
+  hipError_t e = dev_malloc(&p->d_field, sizeof(double) * (size_t)need);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(SLDG_ERR_NOMEM, "field scratch: %s", hipGetErrorString(e));

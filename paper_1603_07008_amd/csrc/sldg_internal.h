@@ -150,6 +150,22 @@ hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t st
 
 int mass_blocks(int64_t n);
 
+// Device memory of the library's own buffers (plan tables, scratch, batch work
+// lists): every allocation goes through dev_malloc / dev_free, which count the
+// live bytes and honour the process-wide limit of sldg_set_device_alloc_limit
+// (an allocation that would pass it fails with hipErrorOutOfMemory, without
+// calling hipMalloc).  dev_alloc_fits tells whether `bytes` more would fit.
+hipError_t dev_malloc_raw(void** p, size_t bytes);
+template <class T>
+hipError_t dev_malloc(T** p, size_t bytes) {
+  void* v = nullptr;
+  const hipError_t e = dev_malloc_raw(&v, bytes);
+  *p = static_cast<T*>(v);
+  return e;
+}
+void dev_free(void* p);
+bool dev_alloc_fits(int64_t bytes);
+
 // Host helpers shared by the plan and batch front ends (sldg_host.hip).
 sldg_status fail(sldg_status st, const char* fmt, ...);
 sldg_status ok();

@@ -125,3 +125,23 @@ def test_tuner_candidates_are_valid_shapes(L):
     assert {r for r, _, _ in strided} == {0, 2, 4, 8}
     assert all(c in (1, 2, 4) and t >= 0 for _, t, c in contig + strided)
     assert len(set(strided)) == len(strided) and len(set(contig)) == len(contig)
+
+
+def test_allocation_limit_forces_nomem_before_the_device(L):
+    """sldg_set_device_alloc_limit: a plan whose tables pass the cap is
+    refused with SLDG_ERR_NOMEM before any device call (so on a machine
+    without a GPU too); removing the cap restores the normal path."""
+    assert L.sldg_set_device_alloc_limit(-2) == sl.SLDG_ERR_ARG
+    assert L.sldg_set_device_alloc_limit(0) == sl.SLDG_OK
+    try:
+        held = L.sldg_device_alloc_bytes()
+        st, h = _plan(L, 2, [16, 16], 2, 1)
+        assert st == sl.SLDG_ERR_NOMEM and h.value is None
+        assert "allocation limit" in sl.last_error()
+        assert L.sldg_device_alloc_bytes() == held
+    finally:
+        assert L.sldg_set_device_alloc_limit(-1) == sl.SLDG_OK
+    st, h = _plan(L, 2, [16, 16], 2, 1)
+    assert st != sl.SLDG_ERR_NOMEM
+    if st == sl.SLDG_OK:
+        L.sldg_plan_destroy(h)
