@@ -33,7 +33,7 @@ TIER_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}
 ARITH = {"fp64": "f64", "fp32": "f64", "bf16": "f32", "fp16": "f32"}
 KERNEL_SOURCES = ["paper_1603_07008_amd/csrc/sldg_kernels.hip", "paper_1603_07008_amd/csrc/ab_poly.h",
                   "paper_1603_07008_amd/csrc/sldg_internal.h", "paper_1603_07008_amd/csrc/sldg_sweep.h",
-                  "paper_1603_07008_amd/csrc/sldg_sweep_inst.hip"]
+                  "paper_1603_07008_amd/csrc/sldg_sweep_inst.hip", "paper_1603_07008_amd/csrc/sldg_fused.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_vlasov4d_48_k2_fp32.json")
 
 
@@ -147,7 +147,10 @@ def sweep_kernel_name(ns, k, tier, d, shape):
 
 
 def run_tier(sl, torch, prob, tier, init, steps, warmup, tune_cache=None, single_reps=20):
-    """Time `steps` split steps (after `warmup`) of `prob` in `tier`."""
+    """Time `steps` split steps (after `warmup`) of `prob` in `tier`: the
+    split step as the library runs it (the (x1, x2) sweep pairs fused into one
+    pass each), then the same steps with every sweep its own pass (the
+    per-sweep figures)."""
     p = sl.Plan(prob.ns, prob.k, tier)
     mass0, hi0 = init
     s0 = (mass0.clone(), hi0.to(sl.hi_dtype(tier), copy=True).contiguous())
@@ -169,35 +172,46 @@ def run_tier(sl, torch, prob, tier, init, steps, warmup, tune_cache=None, single
         shapes, _ = p.tune_cached(tune_cache, seq, s0, s1, reps=3)
     else:
         shapes, _ = p.tune(seq, s0, s1, reps=3)
-    m_start = p.mass(bufs[cur][0])
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
-    p.timing_enable(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record()
-    for _ in range(steps):
-        step()
-    ev1.record()
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / steps
-    p.timing_enable(False)
     tid = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}[tier]
-    per_dim = {d: p.timing_read(d) for d in range(prob.ndim)}
-    kern = {}                       # kernel (template instance) -> (launches, total ms)
-    for d, (n, tot) in per_dim.items():
-        name = sweep_kernel_name(prob.ns, prob.k, tier, d, shapes[d])
-        n0, t0 = kern.get(name, (0, 0.0))
-        kern[name] = (n0 + n, t0 + tot)
+    out = {"plan": p, "shapes": shapes}
+    m_start = p.mass(bufs[cur][0])
+    for fuse in (True, False):
+        p.set_fusion(fuse)
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        p.timing_enable(True)
+        ev0, ev1 = _events(torch)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(steps):
+            step()
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / steps
+        per_dim = {d: p.timing_read(d) for d in range(prob.ndim)}
+        fused = p.timing_read(-3)
+        p.timing_enable(False)
+        kern = {}                   # kernel (template instance) -> (launches, total ms)
+        for d, (n, tot) in per_dim.items():
+            if n:
+                name = sweep_kernel_name(prob.ns, prob.k, tier, d, shapes[d])
+                n0, t0 = kern.get(name, (0, 0.0))
+                kern[name] = (n0 + n, t0 + tot)
+        if fused[0]:
+            kern[f"sldg::sweep_xy_kernel<{prob.k}, {tid}>"] = fused
+        key = "fused" if fuse else "unfused"
+        out[key] = {"ms_per_step": ms, "kernels": kern, "per_dim": per_dim, "fused": fused}
+    p.set_fusion(True)
     m_end = p.mass(bufs[cur][0])
-    drift = abs((m_end[0] + m_end[1]) - (m_start[0] + m_start[1])) / abs(m_start[0] + m_start[1])
-    final = bufs[cur]
+    out["mass_drift"] = abs((m_end[0] + m_end[1]) - (m_start[0] + m_start[1])) / \
+        abs(m_start[0] + m_start[1])
+    out["ms_per_step"] = out["fused"]["ms_per_step"]
+    out["final"] = bufs[cur]
     # each sweep direction alone (its table launch included): event pairs
     # around single calls, after 3 warm-ups, outside the timed steps
     single = {}
-    other = bufs[1 - cur]
+    final, other = bufs[cur], bufs[1 - cur]
     for d, dep, sig in seq:
         if d in single:
             continue
@@ -214,17 +228,117 @@ def run_tier(sl, torch, prob, tier, init, steps, warmup, tune_cache=None, single
         ts.sort()
         single[d] = {"median_ms": round(ts[len(ts) // 2], 4), "min_ms": round(ts[0], 4),
                      "reps": single_reps}
-    return {"plan": p, "ms_per_step": ms, "kernels": kern, "per_dim": per_dim,
-            "mass_drift": drift, "final": final, "shapes": shapes, "single": single}
+    out["single"] = single
+    return out
 
 
-def cpu_baseline(prob, tier, seconds, seed, state=None, gpu_sweep=None):
+def oracle_errors(sl, torch, prob, tier, mass0, hi0, ncheck, seed):
+    """One sweep per direction, and the fused (x1, x2) pass, from the
+    benchmark's initial state rounded to `tier`, against the FP64 oracle from
+    the same state: relative L2 error in the mode-weighted norm over
+    `ncheck` sampled output cells, and the largest relative error of the FP64
+    mass mode."""
+    import numpy as np
+    from oracle import sldg_oracle as O
+    modes, cells = prob.modes, prob.cells
+    scaled = tier == "fp16_scaled"
+    p = sl.Plan(prob.ns, prob.k, "fp16" if scaled else tier)
+    if scaled:
+        # FP16 planes with per-plane power-of-two scales, imported from FP64
+        h16 = torch.empty((p.n_hi, p.cells), dtype=torch.float16, device="cuda")
+        sc = p.empty_scale()
+        p.scaled_import(hi0, h16, sc)
+        a = (mass0, h16, sc)
+        b = (*p.empty_state(), p.empty_scale())
+        hi_vals = p.scaled_export(h16, sc)
+    else:
+        hi_t = hi0.to(sl.hi_dtype(tier)).contiguous()
+        a = (mass0, hi_t)
+        b = p.empty_state()
+        hi_vals = hi_t.to(torch.float64)
+    host = np.empty((modes, cells))
+    host[0] = mass0.cpu().numpy()
+    host[1:] = hi_vals.cpu().numpy().reshape(modes - 1, cells)
+    del hi_vals
+    rng = np.random.default_rng(seed)
+    probe = np.sort(rng.choice(cells, min(cells, ncheck), replace=False))
+    idx = torch.from_numpy(probe).cuda()
+    w = O.mode_weights(prob.ndim, prob.k)[:, None]
+
+    def gathered(state):
+        got = np.empty((modes, probe.size))
+        got[0] = state[0][idx].cpu().numpy()
+        h = p.scaled_export(state[1], state[2]) if scaled else state[1].reshape(modes - 1, cells)
+        got[1:] = h[:, idx].to(torch.float64).cpu().numpy()
+        return got
+
+    def sweep(dim, sig, mask):
+        if scaled:
+            p.advect_dim_scaled(dim, sig, mask, *a, *b)
+        else:
+            p.advect_dim(dim, sig, mask, *a, *b)
+
+    def compare(got, want):
+        rel = math.sqrt(float(np.sum(w * (got - want) ** 2)) / float(np.sum(w * want ** 2)))
+        return {"rel_l2_vs_oracle_fp64": rel,
+                "mass_mode_max_rel_err": float(np.max(np.abs(got[0] - want[0]) / np.abs(want[0])))}
+
+    names = {0: "X1", 1: "X2", 2: "V1", 3: "V2"}
+    res = {}
+    done = set()
+    for sw in prob.seq:
+        if sw.dim in done:
+            continue
+        done.add(sw.dim)
+        sweep(sw.dim, torch.from_numpy(sw.sigma).cuda(), sw.dep_mask)
+        want = O.sweep(host, prob.ns, prob.k, sw.dim, sw.sigma, sw.dep, "fp64", sel=probe)
+        res[names.get(sw.dim, str(sw.dim))] = compare(gathered(b), want)
+    # the fused pair: the oracle's x1 sweep on the cells the x2 sweep of the
+    # sampled cells reads, then its x2 sweep
+    sx1, sx2 = prob.seq[0], prob.seq[1]
+    if scaled:                      # no fused pass for scaled storage: two sweeps
+        mid_state = (*p.empty_state(), p.empty_scale())
+        p.advect_dim_scaled(0, torch.from_numpy(sx1.sigma).cuda(), sx1.dep_mask, *a, *mid_state)
+        p.advect_dim_scaled(1, torch.from_numpy(sx2.sigma).cuda(), sx2.dep_mask, *mid_state, *b)
+        del mid_state
+    else:
+        p.advect_dims01(torch.from_numpy(sx1.sigma).cuda(), sx1.dep_mask,
+                        torch.from_numpy(sx2.sigma).cuda(), sx2.dep_mask, *a, *b)
+    got = gathered(b)
+    n0, n1 = prob.ns[0], prob.ns[1]
+    i1 = (probe // n0) % n1
+    base = probe - i1 * n0
+    s_tab, _ = O.line_tables(sx2.sigma, prob.k)
+    # the line of each sampled cell in the x2 sweep's table (over the
+    # dimensions its displacement depends on, lowest fastest)
+    line = np.zeros(probe.size, dtype=np.int64)
+    stride = 1
+    for e in sx2.dep:
+        line += ((probe // int(np.prod(prob.ns[:e]))) % prob.ns[e]) * stride
+        stride *= prob.ns[e]
+    s = s_tab[line].astype(np.int64)
+    src = np.concatenate([base + ((i1 - s) % n1) * n0, base + ((i1 - s - 1) % n1) * n0])
+    need = np.unique(src)
+    mid_sel = O.sweep(host, prob.ns, prob.k, sx1.dim, sx1.sigma, sx1.dep, "fp64", sel=need)
+    mid = np.zeros_like(host)
+    mid[:, need] = mid_sel
+    del host
+    want = O.sweep(mid, prob.ns, prob.k, sx2.dim, sx2.sigma, sx2.dep, "fp64", sel=probe)
+    res["X1X2 two sweeps" if scaled else "X1X2 fused"] = compare(got, want)
+    p.close()
+    del b, mid
+    res["cells"] = int(probe.size)
+    return res
+
+
+def cpu_baseline(prob, tier, seconds, seed, state=None):
     """The CPU oracle timed on a sampled subset of one split step: the full
     4D state in host memory (the benchmark's initial state when given),
-    every sweep of the step computed for a random sample of output cells (all
-    81 coefficients of each).  With gpu_sweep (sampled cells -> the GPU's
-    outputs of the step's first sweep from the same state), the GPU result is
-    also compared with the FP64 oracle on a sample of cells."""
+    every sweep of the step computed for the same random sample of output
+    cells (all 81 coefficients of each), once with the oracle's OpenMP
+    threads and once on one thread, so the two rates are taken at the same
+    sample density.  The sample is sized for about `seconds` of one-thread
+    work."""
     import numpy as np
     from oracle import sldg_oracle as O
     from paper_1603_07008_amd import inputs
@@ -233,61 +347,37 @@ def cpu_baseline(prob, tier, seconds, seed, state=None, gpu_sweep=None):
         state = O.to_tier(inputs.random_coefficients(prob.ndim, prob.k, prob.cells, seed=seed), tier)
     log(f"cpu_baseline: host state ready in {time.time() - t0:.1f}s")
     rng = np.random.default_rng(seed + 1)
-    # warm the A/B cache of the oracle, then calibrate the sample size
-    for sw in prob.seq:
+    for sw in prob.seq:                   # the oracle's A/B cache, outside the timing
         O.line_tables(sw.sigma, prob.k)
-    # two probe sizes give the marginal cost per sampled cell (a small probe
-    # alone is dominated by the fixed cost of each call)
-    def timed(n):
-        probe = np.sort(rng.choice(prob.cells, n, replace=False))
+
+    def timed(sel):
         t = time.perf_counter()
         for sw in prob.seq:
-            O.sweep(state, prob.ns, prob.k, sw.dim, sw.sigma, sw.dep, tier, sel=probe)
+            O.sweep(state, prob.ns, prob.k, sw.dim, sw.sigma, sw.dep, tier, sel=sel)
         return time.perf_counter() - t
-    n1, n2 = min(prob.cells, 16384), min(prob.cells, 131072)
-    d1, d2 = timed(n1), timed(n2)
-    per = max((d2 - d1) / max(n2 - n1, 1), d2 / n2 * 0.05, 1e-12)
-    nsel = int(min(prob.cells, max(n2, (seconds - min(d1, seconds / 2)) / per)))
-    sel = np.sort(rng.choice(prob.cells, nsel, replace=False))
-    t0 = time.perf_counter()
-    for sw in prob.seq:
-        O.sweep(state, prob.ns, prob.k, sw.dim, sw.sigma, sw.dep, tier, sel=sel)
-    dt = time.perf_counter() - t0
-    updates = nsel * prob.modes * len(prob.seq)
-    # the same sweeps on one thread: the marginal cost between two samples
-    # (about 1 s and 4 s of work), so the fixed cost of each call drops out
+
     nt = O.num_threads()
-    nb = int(min(nsel, max(4096, 4.0 / (per * nt))))
-    na = max(1024, nb // 4)
     O.set_threads(1)
     try:
-        ta, tb = timed(na), timed(nb)
+        cal = np.sort(rng.choice(prob.cells, min(prob.cells, 8192), replace=False))
+        per = timed(cal) / cal.size           # one-thread seconds per sampled cell (upper bound)
+        nsel = int(min(prob.cells, max(8192, seconds / per)))
+        sel = np.sort(rng.choice(prob.cells, nsel, replace=False))
+        dt1 = timed(sel)
     finally:
         O.set_threads(nt)
-    dt1 = max(tb - ta, 1e-9)
-    n1 = nb - na
-    updates1 = n1 * prob.modes * len(prob.seq)
-    check = None
-    if gpu_sweep is not None:
-        # the GPU's first sweep of the step against the FP64 oracle, element
-        # by element on sampled cells, in the mode-weighted L2 norm
-        sw = prob.seq[0]
-        probe = np.sort(rng.choice(prob.cells, min(prob.cells, 65536), replace=False))
-        want = O.sweep(state, prob.ns, prob.k, sw.dim, sw.sigma, sw.dep, "fp64", sel=probe)
-        got = gpu_sweep(probe)
-        w = O.mode_weights(prob.ndim, prob.k)[:, None]
-        rel = math.sqrt(float(np.sum(w * (got - want) ** 2)) / float(np.sum(w * want ** 2)))
-        mass_rel = float(np.max(np.abs(got[0] - want[0]) / np.abs(want[0])))
-        check = {"sweep": f"dimension {sw.dim}", "cells": int(probe.size),
-                 "rel_l2_vs_oracle_fp64": rel, "mass_mode_max_rel_err": mass_rel}
+    dt = timed(sel)
+    updates = nsel * prob.modes * len(prob.seq)
+    cores = len(os.sched_getaffinity(0))
     return {"value": updates / dt, "unit": "coeff-updates/s", "cores": nt,
-            "oracle_check": check,
-            "kind": "oracle", "value_1_thread": updates1 / dt1,
+            "host_cpus_available": cores,
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS"),
+            "kind": "oracle", "value_1_thread": updates / dt1,
             "sample": f"one split step (6 sweeps) of the {prob.ns} k={prob.k} {tier}-mode "
-                      f"workload on the full host state, evaluated for {nsel} randomly sampled "
-                      f"output cells x {prob.modes} coefficients ({updates} coefficient updates, "
-                      f"{dt:.1f} s); value_1_thread: one thread, the marginal rate between samples "
-                      f"of {na} and {nb} cells ({ta:.1f} s, {tb:.1f} s)"}
+                      f"workload on the full host state, evaluated for the same {nsel} randomly "
+                      f"sampled output cells x {prob.modes} coefficients ({updates} coefficient "
+                      f"updates) on {nt} OpenMP threads ({dt:.2f} s) and on one thread "
+                      f"({dt1:.1f} s)"}
 
 
 def _events(torch):
@@ -382,10 +472,13 @@ def adjoint_extra(sl, torch, seed):
             "coeff_updates_per_s": 2 * nsw * prob.cells * prob.modes / (ms * 1e-3)}
 
 
-def scaled_fp16_extra(sl, torch, prob, init, steps, warmup, ref_final, shapes=None):
+def scaled_fp16_extra(sl, torch, prob, init, steps, warmup, ref_final, shapes=None, wm=None):
     """The headline 4D step with FP16 storage and per-plane scaling, in the
     launch shapes tuned for the BF16 tier (the same 2-byte planes and
-    kernels) when given."""
+    kernels) when given.  The run continues untimed to the step count of
+    the other tiers' runs (fused and unfused timing, 2 (warmup + steps)) for
+    the comparison with the FP64 run; mode weights `wm` give the L2 norm of
+    the piecewise polynomials."""
     p = sl.Plan(prob.ns, prob.k, "fp16")
     for d, sh in enumerate(shapes or []):
         p.set_shape(d, sh["rows"], sh["tuples"], sh["colwaves"])
@@ -408,6 +501,8 @@ def scaled_fp16_extra(sl, torch, prob, init, steps, warmup, ref_final, shapes=No
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    for _ in range(warmup + steps):
+        cur = cur if p.split_steps_scaled(seq, 1, st[cur], st[1 - cur]) == 0 else 1 - cur
     m_end = p.mass(st[cur][0])
     out = {"ms_per_step": round(ms, 4),
            "mass_drift_rel": abs((m_end[0] + m_end[1]) - (m_start[0] + m_start[1]))
@@ -416,8 +511,10 @@ def scaled_fp16_extra(sl, torch, prob, init, steps, warmup, ref_final, shapes=No
         fm = st[cur][0]
         fh = p.scaled_export(st[cur][1], st[cur][2])
         rm, rh = ref_final
-        num = torch.sum((fm - rm) ** 2) + torch.sum((fh - rh) ** 2)
-        den = torch.sum(rm ** 2) + torch.sum(rh ** 2)
+        n_hi = fh.shape[0]
+        num = wm[0] * torch.sum((fm - rm) ** 2) + \
+            torch.sum(wm[1:, None] * (fh - rh.reshape(n_hi, -1)) ** 2)
+        den = wm[0] * torch.sum(rm ** 2) + torch.sum(wm[1:, None] * rh.reshape(n_hi, -1) ** 2)
         out["rel_l2_vs_fp64_gpu_run"] = float(torch.sqrt(num / den))
     p.close()
     return out
@@ -532,46 +629,71 @@ def main():
     updates_per_step = len(prob.seq) * cells * modes
     value = updates_per_step / (ms * 1e-3)
 
-    # roofline of the dominant sweep kernel (largest total time)
+    # roofline of the dominant kernel of the step as the library runs it
+    # (largest total time); every launch, fused or not, reads and writes the
+    # state once
     sbytes = state_bytes(cells, modes, args.tier)
-    launch_bytes = 2 * sbytes                          # every coefficient read once, written once
-    kname, (nl, tot) = max(main_r["kernels"].items(), key=lambda kv: kv[1][1])
+    launch_bytes = 2 * sbytes
+    kname, (nl, tot) = max(main_r["fused"]["kernels"].items(), key=lambda kv: kv[1][1])
     avg_ms = tot / max(nl, 1)
     achieved = launch_bytes / (avg_ms * 1e-3) / 1e9
     traffic = measured_traffic(kname)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "kernel": kname, "launches": nl,
+                "sweeps_per_launch": 2 if "sweep_xy_kernel" in kname else 1,
                 "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": launch_bytes,
                 "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
                 "plane_copy_GBps": plane_gbs}
 
-    names = {0: "X1", 1: "X2", 2: "V1", 3: "V2"}
-    per_sweep = {}
-    for d, (n, tot_d) in main_r["per_dim"].items():
-        if n:
-            a = tot_d / n
-            per_sweep[names.get(d, str(d))] = {
-                "avg_ms": round(a, 4), "GB/s": round(launch_bytes / (a * 1e-3) / 1e9, 1),
-                "frac_hbm_peak": round(launch_bytes / (a * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                "launch_shape": main_r["shapes"][d],
-                "single_call": main_r["single"].get(d)}
+    def rate(tot_ms, n):
+        a = tot_ms / n
+        gbs = launch_bytes / (a * 1e-3) / 1e9
+        return {"avg_ms": round(a, 4), "GB/s": round(gbs, 1),
+                "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
 
-    # mixed vs FP64: speedup and the error of the mixed run against the FP64 run
+    names = {0: "X1", 1: "X2", 2: "V1", 3: "V2"}
+    per_sweep = {}                     # every sweep its own pass
+    for d, (n, tot_d) in main_r["unfused"]["per_dim"].items():
+        if n:
+            per_sweep[names.get(d, str(d))] = dict(rate(tot_d, n),
+                                                   launch_shape=main_r["shapes"][d],
+                                                   single_call=main_r["single"].get(d))
+    per_pass = {}                      # the step as timed: (x1, x2) pairs fused
+    nf, tf = main_r["fused"]["fused"]
+    if nf:
+        per_pass["X1X2 fused"] = dict(rate(tf, nf), sweeps=2)
+    for d, (n, tot_d) in main_r["fused"]["per_dim"].items():
+        if n:
+            per_pass[names.get(d, str(d))] = dict(rate(tot_d, n), sweeps=1)
+
+    # mixed vs FP64: speedup, and the error of the mixed run against the FP64
+    # run after the timed steps (mode-weighted L2 norm, i.e. the L2 norm of the
+    # piecewise polynomials)
+    o = prob.k + 1
+    wm = torch.ones(modes, dtype=torch.float64, device="cuda")
+    for m in range(modes):
+        for e in range(prob.ndim):
+            wm[m] /= 2 * ((m // o ** e) % o) + 1
     tiers_out = {}
     ref = results.get("fp64")
     for t, r in results.items():
         ent = {"ms_per_step": round(r["ms_per_step"], 4),
+               "ms_per_step_unfused": round(r["unfused"]["ms_per_step"], 4),
                "coeff_updates_per_s": updates_per_step / (r["ms_per_step"] * 1e-3),
                "bytes_per_update": round(2 * state_bytes(cells, modes, t) / (cells * modes), 3),
                "mass_drift_rel": r["mass_drift"]}
         if ref is not None:
             ent["speedup_vs_fp64"] = round(ref["ms_per_step"] / r["ms_per_step"], 3)
+            ent["speedup_vs_fp64_unfused"] = round(ref["unfused"]["ms_per_step"] /
+                                                   r["unfused"]["ms_per_step"], 3)
             if t != "fp64":
                 fm, fh = r["final"]
                 rm, rh = ref["final"]
-                num = torch.sum((fm - rm) ** 2) + torch.sum((fh.double() - rh) ** 2)
-                den = torch.sum(rm ** 2) + torch.sum(rh ** 2)
+                num = wm[0] * torch.sum((fm - rm) ** 2) + \
+                    torch.sum(wm[1:, None] * (fh.double() - rh).reshape(modes - 1, -1) ** 2)
+                den = wm[0] * torch.sum(rm ** 2) + \
+                    torch.sum(wm[1:, None] * rh.reshape(modes - 1, -1) ** 2)
                 ent["rel_l2_vs_fp64_gpu_run"] = float(torch.sqrt(num / den))
         tiers_out[t] = ent
 
@@ -590,8 +712,10 @@ def main():
         "data": "synthetic (seeded random coefficients, Vlasov magnitude profile; seeded shift fields)",
         "config": {"workload": f"vlasov-4d split step, {args.n}^4 cells, k=2, 81 coeffs/cell, "
                                f"6 sweeps + mass per step",
-                   "storage": f"mass f64 + modes {args.tier}", "parallelism": "single GPU"},
+                   "storage": f"mass f64 + modes {args.tier}", "parallelism": "single GPU",
+                   "step": "X1 X2 V1 V2 X1 X2, each (X1, X2) pair as one fused pass"},
         "roofline": roofline,
+        "per_pass": per_pass,
         "per_sweep": per_sweep,
         "tiers": tiers_out,
     }
@@ -601,20 +725,21 @@ def main():
         ref = results.get("fp64")
         extras["fp16_scaled"] = scaled_fp16_extra(
             sl, torch, prob, (mass0, hi0), args.steps, args.warmup, ref["final"] if ref else None,
-            shapes=results["bf16"]["shapes"] if "bf16" in results else None)
+            shapes=results["bf16"]["shapes"] if "bf16" in results else None, wm=wm)
         if ref:
             extras["fp16_scaled"]["speedup_vs_fp64"] = round(
                 ref["ms_per_step"] / extras["fp16_scaled"]["ms_per_step"], 3)
-        for r in results.values():
-            r["plan"].close()
-        results.clear()
+        out["extras"] = extras
+    for r in results.values():
+        r["plan"].close()
+    results.clear()
+    if not args.no_extras:
         log("bench: batched workload")
         extras["batched"] = batched_extra(sl, torch, 20, args.seed)
         log("bench: differentiation workload")
         extras["adjoint"] = adjoint_extra(sl, torch, args.seed)
         log("bench: collocated sweep and self-consistent field")
         extras["next4"] = next4_extra(sl, torch, prob, (mass0, hi0))
-        out["extras"] = extras
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle baseline")
         import numpy as np
@@ -623,24 +748,17 @@ def main():
         host = np.empty((modes, cells))
         host[0] = mass0.cpu().numpy()
         host[1:] = hi_t.to(torch.float64).cpu().numpy().reshape(modes - 1, cells)
-
-        def gpu_sweep(probe):
-            sw = prob.seq[0]
-            p = sl.Plan(prob.ns, prob.k, args.tier)
-            a = (mass0, hi_t.contiguous())
-            b = p.empty_state()
-            p.advect_dim(sw.dim, torch.from_numpy(sw.sigma).cuda(), sw.dep_mask, *a, *b)
-            idx = torch.from_numpy(probe).cuda()
-            got = np.empty((modes, probe.size))
-            got[0] = b[0][idx].cpu().numpy()
-            got[1:] = b[1].reshape(modes - 1, cells)[:, idx].to(torch.float64).cpu().numpy()
-            p.close()
-            del b
-            return got
-
-        out["cpu_baseline"] = cpu_baseline(prob, args.tier, args.cpu_seconds, args.seed,
-                                           state=host, gpu_sweep=gpu_sweep)
+        del hi_t
+        out["cpu_baseline"] = cpu_baseline(prob, args.tier, args.cpu_seconds, args.seed, state=host)
         del host
+        # every tier's sweeps against the FP64 oracle from the same initial state
+        log("bench: tier errors against the FP64 oracle")
+        for t in tiers_out:
+            tiers_out[t]["vs_oracle_fp64"] = oracle_errors(sl, torch, prob, t, mass0, hi0, 65536,
+                                                          args.seed + 2)
+        if not args.no_extras:
+            out["extras"]["fp16_scaled"]["vs_oracle_fp64"] = oracle_errors(
+                sl, torch, prob, "fp16_scaled", mass0, hi0, 65536, args.seed + 2)
     print(json.dumps(out), flush=True)
 
 

@@ -160,14 +160,45 @@ typedef struct {
 /*
  * A split time step applied nsteps times (section II: the Vlasov equation is
  * split into a sequence of 1D advections).  Each step applies the nseq
- * sweeps of `seq` in order; sweep number q (counting over all steps) reads
- * buffer q % 2 and writes buffer (q + 1) % 2, so the result lands in buffer
- * (nsteps * nseq) % 2, which is also returned in *result_buffer.
+ * sweeps of `seq` in order, each pass reading one buffer and writing the
+ * other.  A sweep along dimension 0 directly followed by one along dimension
+ * 1 runs as one fused pass (sldg_advect_dims01) where that entry point
+ * accepts the pair and fusion is on (sldg_plan_set_fusion, default on): the
+ * result is bitwise the same, but the pair then takes one pass instead of
+ * two.  *result_buffer receives the buffer (0 or 1) holding the result:
+ * (nsteps * nseq) % 2 without fused pairs.
  * Buffers 0 and 1 must not overlap.  Asynchronous on the plan's stream.
  */
 sldg_status sldg_split_steps(sldg_plan_t plan, const sldg_sweep_desc* seq, int nseq,
                              int nsteps, double* mass0, void* hi0, double* mass1,
                              void* hi1, int* result_buffer);
+
+/*
+ * The sweep along dimension 0 followed by the sweep along dimension 1, as one
+ * pass over the state: bitwise the result of sldg_advect_dim(plan, 0, shift0,
+ * dep_mask0, in -> tmp) then sldg_advect_dim(plan, 1, shift1, dep_mask1,
+ * tmp -> out), including the rounding of the intermediate state to the
+ * storage tier, without the intermediate state in device memory (section II:
+ * consecutive 1D advections of a split step).  Every coefficient is read
+ * once and written once for the two sweeps.  A workgroup holds a tile of one
+ * (dimension 0, dimension 1) slab (all N_0 cells of R + 1 consecutive rows of
+ * dimension 1, the o^2 modes of one spectator group) in LDS.
+ * Conditions, else SLDG_ERR_UNSUPPORTED (nothing is launched): ndim >= 2;
+ * neither displacement depends on dimension 0 or 1 (dep_mask bits 0 and 1
+ * clear), so each is uniform over a slab; at most the cell mean is stored in
+ * FP64 (ndouble <= 1); ncells[0] % 4 == 0; all state pointers 16-byte
+ * aligned; one tile of at least one row fits the LDS budget.  Arguments,
+ * layout and other errors as sldg_advect_dim.  Allocates nothing,
+ * asynchronous on the plan's stream.
+ */
+sldg_status sldg_advect_dims01(sldg_plan_t plan, const double* shift0, uint32_t dep_mask0,
+                               const double* shift1, uint32_t dep_mask1,
+                               const double* in_mass, const void* in_hi, double* out_mass,
+                               void* out_hi);
+
+/* Fusion of (0, 1) sweep pairs inside sldg_split_steps: enable != 0 on (the
+ * default), 0 off (every sweep its own pass).  Errors: SLDG_ERR_ARG. */
+sldg_status sldg_plan_set_fusion(sldg_plan_t plan, int enable);
 
 /*
  * Sum of the mass array, mass[0] + ... + mass[cells-1], as an unevaluated
@@ -422,7 +453,8 @@ sldg_status sldg_vlasov_poisson_steps_2d2v(sldg_plan_t plan, int nsteps, const d
  * sldg_timing_enable(plan, 1) clears earlier records; (plan, 0) stops.
  * sldg_timing_read synchronises the plan's stream and returns, for launches
  * of the sweep along `dim` (dim = -1: along dimension 0; dim = -2: along
- * any dimension > 0), their count and the sum of their durations in ms.
+ * any dimension > 0; dim = -3: the fused (0, 1) passes), their count and the
+ * sum of their durations in ms.
  */
 sldg_status sldg_timing_enable(sldg_plan_t plan, int enable);
 sldg_status sldg_timing_read(sldg_plan_t plan, int dim, int64_t* launches, double* total_ms);

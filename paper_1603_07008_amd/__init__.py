@@ -29,7 +29,8 @@ EXPORTS = ("sldg_plan", "sldg_plan_destroy", "sldg_plan_set_stream", "sldg_line_
            "sldg_device_plane_copy", "sldg_batch_get_class_tuning", "sldg_batch_set_class_tuning",
            "sldg_poisson_shift", "sldg_poisson_shift_noalloc", "sldg_vlasov_poisson_steps",
            "sldg_advect_dim_collocated", "sldg_poisson_shift_2d", "sldg_vlasov_poisson_steps_2d2v",
-           "sldg_set_device_alloc_limit", "sldg_device_alloc_bytes")
+           "sldg_set_device_alloc_limit", "sldg_device_alloc_bytes", "sldg_advect_dims01",
+           "sldg_plan_set_fusion")
 
 
 class SldgError(RuntimeError):
@@ -133,6 +134,10 @@ def lib():
     L.sldg_vlasov_poisson_steps_2d2v.argtypes = [vp, i32, vp, vp, ctypes.POINTER(dbl), dbl, vp,
                                                  vp, vp, vp, vp, vp, ctypes.POINTER(i32)]
     L.sldg_vlasov_poisson_steps_2d2v.restype = i32
+    L.sldg_advect_dims01.argtypes = [vp, vp, u32, vp, u32, vp, vp, vp, vp]
+    L.sldg_advect_dims01.restype = i32
+    L.sldg_plan_set_fusion.argtypes = [vp, i32]
+    L.sldg_plan_set_fusion.restype = i32
     L.sldg_set_device_alloc_limit.argtypes = [i64]
     L.sldg_set_device_alloc_limit.restype = i32
     L.sldg_device_alloc_bytes.argtypes = []
@@ -283,6 +288,22 @@ class Plan:
         _check(lib().sldg_advect_dim(self.handle, int(dim), _ptr(shift), int(dep_mask),
                                      _ptr(in_mass), _ptr(in_hi), _ptr(out_mass), _ptr(out_hi)),
                "sldg_advect_dim")
+
+    def advect_dims01(self, shift0, dep_mask0, shift1, dep_mask1, in_mass, in_hi, out_mass,
+                      out_hi):
+        """The sweep along dimension 0 then the sweep along dimension 1 in one
+        fused pass (sldg_advect_dims01); bitwise two advect_dim calls."""
+        self._check_shift(shift0, dep_mask0, "advect_dims01")
+        self._check_shift(shift1, dep_mask1, "advect_dims01")
+        self._check_state(in_mass, in_hi, "advect_dims01 input")
+        self._check_state(out_mass, out_hi, "advect_dims01 output")
+        _check(lib().sldg_advect_dims01(self.handle, _ptr(shift0), int(dep_mask0), _ptr(shift1),
+                                        int(dep_mask1), _ptr(in_mass), _ptr(in_hi),
+                                        _ptr(out_mass), _ptr(out_hi)), "sldg_advect_dims01")
+
+    def set_fusion(self, enable):
+        """Fusion of (0, 1) sweep pairs in split_steps (sldg_plan_set_fusion)."""
+        _check(lib().sldg_plan_set_fusion(self.handle, 1 if enable else 0), "sldg_plan_set_fusion")
 
     def advect_dim_adjoint(self, dim, shift, dep_mask, in_mass, in_hi, out_mass, out_hi):
         """The transposed sweep (sldg_advect_dim_adjoint)."""

@@ -20,6 +20,7 @@
 #include "sldg_ref.h"
 #include "sldg_field.h"
 #include "sldg_colloc.h"
+#include "sldg_fused.h"
 
 using namespace sldg;
 
@@ -51,6 +52,10 @@ struct sldg_plan_s {
   int colwaves_d[kMaxDim];// strided sweep: waves of a workgroup along the columns (1, 2, 4)
   int xcd_contig;         // XCD-aware tile order (run length) of the dimension-0 sweep
   int xcd_strided;        // ... and of the strided sweeps
+  // fused pair of sweeps along dimensions 0 and 1 (sldg_advect_dims01)
+  int fuse;               // split steps fuse eligible (0, 1) pairs
+  int xy_rows;            // tile rows of dimension 1 (0: the most that fit)
+  int xcd_xy;             // XCD-aware tile order of the fused pass
   // scaled FP16 storage
   int scale_headroom;     // binades between a plane's absmax and 2^15
   int32_t* d_hmode;       // [n_hi] mode id of every hi plane
@@ -249,6 +254,7 @@ void describe_grid(int ndim, const int64_t* n, int o, int64_t modes, int dim, ui
 namespace {
 
 constexpr int kMaxTimed = 4096;
+constexpr int kXYTimingDim = -3;   // timing code of the fused (0, 1) pair
 
 sldg_status check_sweep(const sldg_plan_s* p, int dim, const double* shift, uint32_t dep_mask,
                         const double* in_lo, const void* in_hi, const double* out_lo,
@@ -385,6 +391,35 @@ sldg_status check_scaled(const sldg_plan_s* p, const void* in_scale, const void*
   return SLDG_OK;
 }
 
+// Kernel timing: an event before and after a sweep launch (the line-table
+// launch stays outside); `code` is the swept dimension, or kXYTimingDim for
+// the fused pair.
+sldg_status timing_begin(sldg_plan_s* p, bool& timed) {
+  timed = p->timing && p->ntimed < kMaxTimed;
+  if (!timed) return SLDG_OK;
+  const int i = p->ntimed;
+  if (2 * i + 1 >= p->nev_created) {
+    for (int q = p->nev_created; q < 2 * i + 2; ++q) {
+      hipError_t e = hipEventCreate(&p->ev[q]);
+      if (e != hipSuccess) return device_error(e, "hipEventCreate");
+      p->nev_created = q + 1;
+    }
+  }
+  hipError_t e = hipEventRecord(p->ev[2 * i], p->stream);
+  if (e != hipSuccess) return device_error(e, "hipEventRecord");
+  return SLDG_OK;
+}
+
+sldg_status timing_end(sldg_plan_s* p, bool timed, int code) {
+  if (!timed) return SLDG_OK;
+  const int i = p->ntimed;
+  hipError_t e = hipEventRecord(p->ev[2 * i + 1], p->stream);
+  if (e != hipSuccess) return device_error(e, "hipEventRecord");
+  p->ev_dim[i] = code;
+  p->ntimed = i + 1;
+  return SLDG_OK;
+}
+
 sldg_status run_sweep(sldg_plan_s* p, int dim, const double* shift, uint32_t dep_mask,
                       const double* in_lo, const void* in_hi, double* out_lo, void* out_hi,
                       bool adjoint = false, const void* in_scale = nullptr,
@@ -424,19 +459,9 @@ sldg_status run_sweep(sldg_plan_s* p, int dim, const double* shift, uint32_t dep
   a.s_tab = p->d_s;
   a.ab_tab = p->d_ab;
   a.ab_cs = ntab;
-  const bool timed = p->timing && p->ntimed < kMaxTimed;
-  if (timed) {
-    const int i = p->ntimed;
-    if (2 * i + 1 >= p->nev_created) {
-      for (int q = p->nev_created; q < 2 * i + 2; ++q) {
-        e = hipEventCreate(&p->ev[q]);
-        if (e != hipSuccess) return device_error(e, "hipEventCreate");
-        p->nev_created = q + 1;
-      }
-    }
-    e = hipEventRecord(p->ev[2 * i], p->stream);
-    if (e != hipSuccess) return device_error(e, "hipEventRecord");
-  }
+  bool timed = false;
+  sldg_status tst = timing_begin(p, timed);
+  if (tst != SLDG_OK) return tst;
   if (scaled) {
     e = launch_scale_predict(p->n_hi, sin.exp, sin.amax, sout.exp, p->scale_headroom, p->d_part,
                              p->n_hi * (int64_t)a.nslot, p->stream);
@@ -453,14 +478,102 @@ sldg_status run_sweep(sldg_plan_s* p, int dim, const double* shift, uint32_t dep
     e = launch_scale_redo(p->k, dim, a, p->n_hi, p->d_redo, p->d_hmode, p->stream);
     if (e != hipSuccess) return device_error(e, "scale repair launch");
   }
-  if (timed) {
-    const int i = p->ntimed;
-    e = hipEventRecord(p->ev[2 * i + 1], p->stream);
-    if (e != hipSuccess) return device_error(e, "hipEventRecord");
-    p->ev_dim[i] = dim;
-    p->ntimed = i + 1;
+  return timing_end(p, timed, dim);
+}
+
+// The fused pair of sweeps along dimensions 0 and 1 (sldg_fused.h): the
+// tile rows R of dimension 1 that fit the LDS budget and the phase-2 item
+// limit, 0 if none does.  The budget keeps four workgroups per CU (160 KB of
+// LDS): on the 48^4 workload taller tiles with fewer workgroups per CU
+// measured slower in every tier (FP32: R = 24 at 3 per CU 0.81 ms, R = 16 at
+// 4 per CU 0.64 ms).
+constexpr int64_t kXYLdsBudget = 40 * 1024;
+int32_t xy_tile_rows(const sldg_plan_s* p) {
+  const int64_t N0 = p->n[0], N1 = p->n[1];
+  static const int kCand[] = {48, 32, 24, 16, 12, 8, 6, 4, 3, 2, 1};
+  for (int R : kCand) {
+    if (p->xy_rows > 0 && R != p->xy_rows) continue;
+    if (R > N1 && R > 1) continue;
+    if (xy_lds_bytes(p->k, (int)elem_size(p->tier), (int32_t)N0, R) > kXYLdsBudget) continue;
+    if ((int64_t)p->o * (R + 1) * (N0 / 4) > (int64_t)kXYMaxItems * 256) continue;
+    return R;
   }
-  return SLDG_OK;
+  return 0;
+}
+
+// Whether the pair can run fused: the displacements of both sweeps are
+// uniform over every (dimension 0, dimension 1) slab, at most the cell mean is
+// FP64, rows of dimension 0 are whole 4-cell blocks, the buffers are 16-byte
+// aligned and a tile fits.  Sets *why on refusal.
+bool xy_eligible(const sldg_plan_s* p, uint32_t mask0, uint32_t mask1, const double* in_lo,
+                 const void* in_hi, const double* out_lo, const void* out_hi, const char** why) {
+  *why = nullptr;
+  if (p->ndim < 2) *why = "needs two or more dimensions";
+  else if ((mask0 | mask1) & 3u) *why = "a displacement depends on dimension 0 or 1";
+  else if (p->n_lo > 1) *why = "more modes than the cell mean are FP64";
+  else if (p->n[0] % 4) *why = "ncells[0] is not a multiple of 4";
+  else if (((uintptr_t)in_hi | (uintptr_t)out_hi |
+            (p->n_lo ? ((uintptr_t)in_lo | (uintptr_t)out_lo) : 0)) & 15)
+    *why = "buffers not 16-byte aligned";
+  else if (xy_tile_rows(p) == 0) *why = "a tile of the (0, 1) slab does not fit in LDS";
+  else if (p->cells / (p->n[0] * p->n[1]) * (p->modes / (p->o * p->o)) *
+               ((p->n[1] + xy_tile_rows(p) - 1) / xy_tile_rows(p)) > INT32_MAX)
+    *why = "too many tiles for one launch";
+  return *why == nullptr;
+}
+
+sldg_status run_xy(sldg_plan_s* p, const double* shift0, uint32_t mask0, const double* shift1,
+                   uint32_t mask1, const double* in_lo, const void* in_hi, double* out_lo,
+                   void* out_hi) {
+  SweepArgs a0{}, a1{};
+  int64_t nt0 = 0, nt1 = 0;
+  describe(p, 0, mask0, a0, nt0);
+  describe(p, 1, mask1, a1, nt1);
+  if (nt0 + nt1 > p->table_cap)
+    return fail(SLDG_ERR_UNSUPPORTED, "fused sweeps: line tables of %lld + %lld entries exceed %lld",
+                (long long)nt0, (long long)nt1, (long long)p->table_cap);
+  const int64_t o2 = (int64_t)p->o * p->o;
+  hipError_t e = launch_line_tables(p->k, nt0, p->n[0], shift0, p->d_s, p->d_ab, true, false,
+                                    p->stream);
+  if (e == hipSuccess)
+    e = launch_line_tables(p->k, nt1, p->n[1], shift1, p->d_s + nt0, p->d_ab + 2 * o2 * nt0,
+                           true, false, p->stream);
+  if (e != hipSuccess) return device_error(e, "line-table launch");
+  const int32_t R = xy_tile_rows(p);
+  XYArgs x{};
+  x.in_lo = in_lo;
+  x.in_hi = in_hi;
+  x.out_lo = out_lo;
+  x.out_hi = out_hi;
+  x.n_lo = (int32_t)p->n_lo;
+  x.cells = p->cells;
+  x.N0 = (int32_t)p->n[0];
+  x.N1 = (int32_t)p->n[1];
+  x.Q = (int32_t)(p->cells / (p->n[0] * p->n[1]));
+  x.R = R;
+  x.nrc = (x.N1 + R - 1) / R;
+  x.tstride = (int32_t)xy_tile_stride(x.N0, R);
+  x.xcd = p->xcd_xy;
+  x.one = 1.0f;
+  x.fnb = FastDiv::make((uint32_t)(x.N0 / 4));
+  x.fnrc = FastDiv::make((uint32_t)x.nrc);
+  x.fQ = FastDiv::make((uint32_t)x.Q);
+  x.s0 = p->d_s;
+  x.ab0 = p->d_ab;
+  x.cs0 = nt0;
+  x.map0 = a0.map;
+  x.s1 = p->d_s + nt0;
+  x.ab1 = p->d_ab + 2 * o2 * nt0;
+  x.cs1 = nt1;
+  x.map1 = a1.map;
+  const int64_t nblocks = (int64_t)x.nrc * x.Q * (p->modes / o2);
+  bool timed = false;
+  sldg_status tst = timing_begin(p, timed);
+  if (tst != SLDG_OK) return tst;
+  e = launch_xy(p->k, (int)p->tier, x, xy_lds_bytes(p->k, (int)elem_size(p->tier), x.N0, R),
+                (int32_t)nblocks, p->stream);
+  if (e != hipSuccess) return device_error(e, "fused sweep launch");
+  return timing_end(p, timed, kXYTimingDim);
 }
 
 }  // namespace
@@ -549,6 +662,11 @@ sldg_status sldg_plan_ex(sldg_plan_t* out, int ndim, const int64_t* ncells, int 
   int rows = 4, tuples = 9, colwaves = 1;
   p->xcd_contig = 8;           // run lengths measured best on MI355X (4D k = 2)
   p->xcd_strided = 16;
+  p->fuse = 1;
+  p->xy_rows = 0;
+  p->xcd_xy = 8;
+  if (const char* env = getenv("SLDG_XY_ROWS")) p->xy_rows = std::max(0, atoi(env));
+  if (const char* env = getenv("SLDG_XCD_XY")) p->xcd_xy = std::max(0, atoi(env));
   if (const char* env = getenv("SLDG_COLWAVES")) {
     const int c = atoi(env);
     if (c == 1 || c == 2 || c == 4) colwaves = c;
@@ -655,14 +773,17 @@ sldg_status sldg_timing_enable(sldg_plan_t p, int enable) {
 sldg_status sldg_timing_read(sldg_plan_t p, int dim, int64_t* launches, double* total_ms) {
   if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
   if (!launches || !total_ms) return fail(SLDG_ERR_ARG, "null output pointer");
-  if (dim < -2 || dim >= p->ndim) return fail(SLDG_ERR_ARG, "dim %d out of range", dim);
+  if (dim < -3 || dim >= p->ndim) return fail(SLDG_ERR_ARG, "dim %d out of range", dim);
   hipError_t e = hipStreamSynchronize(p->stream);
   if (e != hipSuccess) return device_error(e, "hipStreamSynchronize");
   int64_t n = 0;
   double tot = 0.0;
   for (int i = 0; i < p->ntimed; ++i) {
     const int d = p->ev_dim[i];
-    const bool match = (dim >= 0) ? (d == dim) : (dim == -1 ? d == 0 : d > 0);
+    const bool match = (dim >= 0)    ? (d == dim)
+                       : dim == -1   ? d == 0
+                       : dim == -2   ? d > 0
+                                     : d == kXYTimingDim;
     if (!match) continue;
     float ms = 0.f;
     e = hipEventElapsedTime(&ms, p->ev[2 * i], p->ev[2 * i + 1]);
@@ -721,16 +842,56 @@ sldg_status sldg_split_steps(sldg_plan_t p, const sldg_sweep_desc* seq, int nseq
       if (st != SLDG_OK) return st;
     }
   }
+  // sweeps along dimension 0 then 1 run as one fused pass where they can
+  // (same result, one read and one write of the state instead of two); the
+  // pair's result then lands in the other buffer than two sweeps would leave
+  // it in, which *result_buffer reports
+  std::vector<char> fused((size_t)std::max(nseq, 1), 0);
+  for (int q = 0; p->fuse && q + 1 < nseq; ++q) {
+    const char* why = nullptr;
+    if (seq[q].dim == 0 && seq[q + 1].dim == 1 &&
+        xy_eligible(p, seq[q].dep_mask, seq[q + 1].dep_mask, m[0], h[0], m[1], h[1], &why)) {
+      fused[(size_t)q] = 1;
+      ++q;
+    }
+  }
   int cur = 0;
   for (int n = 0; n < nsteps; ++n) {
     for (int q = 0; q < nseq; ++q) {
-      sldg_status st = run_sweep(p, seq[q].dim, seq[q].shift, seq[q].dep_mask, m[cur], h[cur],
-                                 m[1 - cur], h[1 - cur]);
+      sldg_status st;
+      if (fused[(size_t)q]) {
+        st = run_xy(p, seq[q].shift, seq[q].dep_mask, seq[q + 1].shift, seq[q + 1].dep_mask,
+                    m[cur], h[cur], m[1 - cur], h[1 - cur]);
+        ++q;
+      } else {
+        st = run_sweep(p, seq[q].dim, seq[q].shift, seq[q].dep_mask, m[cur], h[cur], m[1 - cur],
+                       h[1 - cur]);
+      }
       if (st != SLDG_OK) return st;
       cur = 1 - cur;
     }
   }
   if (result_buffer) *result_buffer = cur;
+  return ok();
+}
+
+sldg_status sldg_advect_dims01(sldg_plan_t p, const double* shift0, uint32_t dep_mask0,
+                               const double* shift1, uint32_t dep_mask1, const double* in_mass,
+                               const void* in_hi, double* out_mass, void* out_hi) {
+  sldg_status st = check_sweep(p, 0, shift0, dep_mask0, in_mass, in_hi, out_mass, out_hi);
+  if (st != SLDG_OK) return st;
+  st = check_sweep(p, 1, shift1, dep_mask1, in_mass, in_hi, out_mass, out_hi);
+  if (st != SLDG_OK) return st;
+  const char* why = nullptr;
+  if (!xy_eligible(p, dep_mask0, dep_mask1, in_mass, in_hi, out_mass, out_hi, &why))
+    return fail(SLDG_ERR_UNSUPPORTED, "fused sweeps along dimensions 0 and 1: %s", why);
+  st = run_xy(p, shift0, dep_mask0, shift1, dep_mask1, in_mass, in_hi, out_mass, out_hi);
+  return st == SLDG_OK ? ok() : st;
+}
+
+sldg_status sldg_plan_set_fusion(sldg_plan_t p, int enable) {
+  if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
+  p->fuse = enable != 0;
   return ok();
 }
 

@@ -118,6 +118,13 @@ hipError_t launch_sweep_inst(int dim, const SweepArgs& a, hipStream_t st);
 template <int K, int TIER>
 hipError_t launch_class_inst(int kind, int rows, const SweepArgs* args, const BatchItem* items,
                              int32_t nitems, int32_t xcd, hipStream_t st);
+// The fused pair of sweeps along dimensions 0 and 1 (sldg_fused.h):
+// nblocks workgroups of 256 threads with lds_bytes of dynamic LDS.
+struct XYArgs;
+hipError_t launch_xy(int k, int tier, const XYArgs& a, int64_t lds_bytes, int32_t nblocks,
+                     hipStream_t st);
+template <int K, int TIER>
+hipError_t launch_xy_inst(const XYArgs& a, int64_t lds_bytes, int32_t nblocks, hipStream_t st);
 // Waves of one sweep launch that compute a given output plane (the absmax
 // partial slots per plane of a scaled FP16 sweep).
 int64_t sweep_slots(int dim, const SweepArgs& a);

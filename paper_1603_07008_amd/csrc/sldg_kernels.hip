@@ -179,6 +179,39 @@ hipError_t launch_sweep(int k, int tier, int dim, const SweepArgs& a, hipStream_
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_xy(int k, int tier, const XYArgs& a, int64_t lds_bytes, int32_t nblocks,
+                     hipStream_t st) {
+#define SLDG_XY_CALL(KK, TT) launch_xy_inst<KK, TT>(a, lds_bytes, nblocks, st)
+  switch (k) {
+    case 1:
+      switch (tier) {
+        case 0: return SLDG_XY_CALL(1, 0);
+        case 1: return SLDG_XY_CALL(1, 1);
+        case 2: return SLDG_XY_CALL(1, 2);
+        case 3: return SLDG_XY_CALL(1, 3);
+      }
+      break;
+    case 2:
+      switch (tier) {
+        case 0: return SLDG_XY_CALL(2, 0);
+        case 1: return SLDG_XY_CALL(2, 1);
+        case 2: return SLDG_XY_CALL(2, 2);
+        case 3: return SLDG_XY_CALL(2, 3);
+      }
+      break;
+    case 3:
+      switch (tier) {
+        case 0: return SLDG_XY_CALL(3, 0);
+        case 1: return SLDG_XY_CALL(3, 1);
+        case 2: return SLDG_XY_CALL(3, 2);
+        case 3: return SLDG_XY_CALL(3, 3);
+      }
+      break;
+  }
+#undef SLDG_XY_CALL
+  return hipErrorInvalidValue;
+}
+
 // ---------------------------------------------------------------------------
 // Batched sweep: many independent problems (own grid, degree and tables).
 // The work list of a sweep holds one item per workgroup-sized tile of one

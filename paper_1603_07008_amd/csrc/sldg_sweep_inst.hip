@@ -5,6 +5,7 @@
 // the batched sweep classes; the dispatch over (k, tier) is in
 // sldg_kernels.hip.
 #include "sldg_sweep.h"
+#include "sldg_fused.h"
 
 #if !defined(SLDG_K) || !defined(SLDG_TIER)
 #error "compile with -DSLDG_K=<degree> -DSLDG_TIER=<tier>"
@@ -106,7 +107,14 @@ hipError_t launch_class_inst(int kind, int rows, const SweepArgs* args, const Ba
   return launch_class_kt<K, TIER>(kind, rows, args, items, nitems, xcd, st);
 }
 
+template <int K, int TIER>
+hipError_t launch_xy_inst(const XYArgs& a, int64_t lds_bytes, int32_t nblocks, hipStream_t st) {
+  sweep_xy_kernel<K, TIER><<<nblocks, 256, (size_t)lds_bytes, st>>>(a);
+  return hipGetLastError();
+}
+
 template hipError_t launch_sweep_inst<SLDG_K, SLDG_TIER>(int, const SweepArgs&, hipStream_t);
+template hipError_t launch_xy_inst<SLDG_K, SLDG_TIER>(const XYArgs&, int64_t, int32_t, hipStream_t);
 template hipError_t launch_class_inst<SLDG_K, SLDG_TIER>(int, int, const SweepArgs*,
                                                          const BatchItem*, int32_t, int32_t,
                                                          hipStream_t);

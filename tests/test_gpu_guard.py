@@ -170,6 +170,26 @@ def test_leading_fp64_mode_kernels_write_exactly_their_outputs(sl, k, case):
     plan.close()
 
 
+@pytest.mark.parametrize("tier", ["fp64", "fp32", "bf16", "fp16"])
+def test_fused_pair_writes_exactly_its_outputs(sl, tier):
+    for ns, rows in (((48, 13, 5), "0"), ((12, 7, 3, 2), "3")):
+        import os
+        old = os.environ.get("SLDG_XY_ROWS")
+        os.environ["SLDG_XY_ROWS"] = rows
+        try:
+            plan = sl.Plan(ns, 2, tier)
+        finally:
+            if old is None:
+                os.environ.pop("SLDG_XY_ROWS")
+            else:
+                os.environ["SLDG_XY_ROWS"] = old
+        s0 = shift_for(plan, (2,), 60)
+        s1 = shift_for(plan, (2,), 61)
+        run_guarded(lambda: list(state_inputs(sl, plan, 62)), state_specs(sl, plan),
+                    lambda i, o: plan.advect_dims01(s0, 4, s1, 4, *i, *o))
+        plan.close()
+
+
 def test_scaled_fp16_sweep_and_repair_write_exactly_their_outputs(sl):
     import torch
     from test_gpu_scaled import upload_scaled
