@@ -8,11 +8,19 @@ This module only orders the calls and manages buffers.
 
 Checkpointing: with `checkpoint_every = C`, the forward pass keeps the state
 at the start of every C-th step.  The backward pass walks the segments from
-the last to the first; for a split whose displacements depend on the state
-(`shifts_fn` given) it rebuilds the segment's displacement fields from the
-checkpoint by re-running the segment forward; with fixed fields (the default)
-the transposed sweeps need no forward state and the checkpoints are not read,
-so the gradient is bitwise the same with or without them.
+the last to the first.  With fixed fields (the default) the transposed sweeps
+need no forward state and the checkpoints are not read, so the gradient is
+bitwise the same with or without them.
+
+Frozen fields (`frozen_shifts_fn`): the displacements of each step may be
+computed from the state at the start of the step (a self-consistent field).
+The gradient then treats those displacements as constants: it is the
+transposed product of the sweeps the forward pass ran, i.e. the derivative
+at frozen fields, and not the gradient of the self-consistent map (which
+would add the field solve's transpose and the derivatives of A and B with
+respect to the displacement).  With checkpoints the backward pass rebuilds
+each segment's fields from its checkpoint by re-running the segment forward;
+without them the forward pass keeps every step's fields.
 """
 import torch
 
@@ -21,7 +29,7 @@ from . import Plan, hi_dtype
 
 class _SplitSteps(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, mass, hi, plan, seq, nsteps, checkpoint_every, shifts_fn):
+    def forward(ctx, mass, hi, plan, seq, nsteps, checkpoint_every, frozen_shifts_fn):
         cur = [(mass.detach().clone(), hi.detach().clone()), plan.empty_state()]
         idx = 0
         ckpts = []
@@ -29,8 +37,8 @@ class _SplitSteps(torch.autograd.Function):
         for n in range(nsteps):
             if checkpoint_every and n % checkpoint_every == 0:
                 ckpts.append((n, cur[idx][0].clone(), cur[idx][1].clone()))
-            step_seq = seq if shifts_fn is None else shifts_fn(cur[idx])
-            if shifts_fn is not None and not checkpoint_every:
+            step_seq = seq if frozen_shifts_fn is None else frozen_shifts_fn(cur[idx])
+            if frozen_shifts_fn is not None and not checkpoint_every:
                 seqs.append(step_seq)
             res = plan.split_steps(step_seq, 1, cur[idx], cur[1 - idx])
             idx = idx if res == 0 else 1 - idx
@@ -39,7 +47,7 @@ class _SplitSteps(torch.autograd.Function):
         ctx.nsteps = nsteps
         ctx.checkpoint_every = checkpoint_every
         ctx.checkpoints = ckpts
-        ctx.shifts_fn = shifts_fn
+        ctx.shifts_fn = frozen_shifts_fn
         ctx.seqs = seqs
         return cur[idx][0], cur[idx][1]
 
@@ -79,11 +87,14 @@ class _SplitSteps(torch.autograd.Function):
         return g[0], g[1], None, None, None, None, None
 
 
-def split_steps(plan: Plan, seq, nsteps, mass, hi, checkpoint_every=None, shifts_fn=None):
+def split_steps(plan: Plan, seq, nsteps, mass, hi, checkpoint_every=None, frozen_shifts_fn=None):
     """Differentiable split steps: returns (mass, hi) after `nsteps` steps of
     the sweeps `seq` [(dim, dep_mask, shift tensor), ...]; gradients flow to
-    `mass` and `hi` through the transposed sweeps."""
-    return _SplitSteps.apply(mass, hi, plan, seq, nsteps, checkpoint_every, shifts_fn)
+    `mass` and `hi` through the transposed sweeps.  frozen_shifts_fn(state)
+    -> seq, if given, supplies each step's sweeps from the state at the start
+    of the step, and the gradient holds those displacements fixed (the
+    derivative at frozen fields; see the module docstring)."""
+    return _SplitSteps.apply(mass, hi, plan, seq, nsteps, checkpoint_every, frozen_shifts_fn)
 
 
 def weighted_l2_misfit(mass, hi, t_mass, t_hi, ndim, k, cell_volume):

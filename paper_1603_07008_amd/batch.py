@@ -1,9 +1,10 @@
 """Batched sweeps: many independent sLdG problems advanced together.
 
 ctypes binding of the sldg_batch_* entry points (include/sldg.h).  Each sweep
-of a split step is one persistent launch over tiles of every problem; a step
+of a split step is one work list of tiles over every problem, launched as one
+kernel per class (tile kind x degree, each class compiled for itself); a step
 can be captured into a HIP graph and replayed; the launch shape of every
-sweep is tuned on the bound data, and tuned shapes can be stored in a JSON
+class is tuned on the bound data, and tuned shapes can be stored in a JSON
 cache keyed by the batch's shape signature.  Marshalling only: every step runs
 in the library's kernels.
 """

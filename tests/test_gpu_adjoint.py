@@ -176,3 +176,61 @@ def test_gradient_matches_central_finite_differences(sl, n, steps, ndir):
         worst = max(worst, abs(fd - gd) / tol)
         assert abs(fd - gd) <= tol, (fd, gd, tol)
     print(f"finite differences n={n}: worst error / bound = {worst:.3f}")
+
+
+def test_frozen_field_gradient_is_the_transpose_of_the_sweeps_run(sl):
+    """With displacements computed from the state at the start of each step
+    (the self-consistent field of section II), the gradient holds them fixed:
+    it must equal the transposed sweeps, in reverse order, with exactly the
+    displacements the forward pass used, and must not depend on
+    checkpointing (the fields are rebuilt bitwise from the checkpoints)."""
+    import torch
+    from paper_1603_07008_amd import autograd as AG
+    prob = inputs.landau_2d(32, 24, 2, 0.2, 0.5, eps=0.05)
+    hx, hv = prob.h
+    p = sl.Plan(prob.ns, prob.k, "fp64")
+    sx = _dev(prob.seq[0].sigma)
+    recorded = []
+
+    def fields(state):
+        sv = p.poisson_shift(state[0], state[1], hx, hv, prob.dt)
+        recorded.append(sv.clone())
+        return [(0, 2, sx), (1, 1, sv), (0, 2, sx)]
+
+    c0 = O.project_separable(prob.f0_terms, prob.ns, prob.los, prob.his, prob.k)
+    m0, h0 = upload(c0, "fp64")
+    rng = np.random.default_rng(3)
+    tm = _dev(c0[0] + 1e-3 * rng.standard_normal(c0.shape[1]))
+    th = _dev(c0[1:] + 1e-3 * rng.standard_normal(c0[1:].shape))
+    steps, vol = 6, hx * hv
+    grads = {}
+    for ckpt in (None, 2):
+        recorded.clear()
+        mm = m0.clone().requires_grad_(True)
+        hh = h0.clone().requires_grad_(True)
+        fm, fh = AG.split_steps(p, None, steps, mm, hh, checkpoint_every=ckpt,
+                                frozen_shifts_fn=fields)
+        loss = AG.weighted_l2_misfit(fm, fh, tm, th, 2, prob.k, vol)
+        loss.backward()
+        grads[ckpt] = (mm.grad.clone(), hh.grad.clone())
+        if ckpt is None:
+            fields_used = [r.clone() for r in recorded]
+            final = (fm.detach().clone(), fh.detach().clone())
+    assert len(fields_used) == steps
+    for a, b in zip(grads[None], grads[2]):
+        assert torch.equal(a, b)
+    # the transposed sweeps with the recorded fields, from the loss gradient
+    w = O.mode_weights(2, prob.k)
+    g = (vol * w[0] * (final[0] - tm),
+         (vol * torch.from_numpy(w[1:, None]).cuda() * (final[1] - th)).contiguous())
+    tmp = p.empty_state()
+    for n in range(steps - 1, -1, -1):
+        for dim, mask, sh in reversed([(0, 2, sx), (1, 1, fields_used[n]), (0, 2, sx)]):
+            p.advect_dim_adjoint(dim, sh, mask, g[0], g[1], tmp[0], tmp[1])
+            g, tmp = tmp, g
+    want = download(*g)
+    got = download(*grads[None])
+    scale = np.max(np.abs(want))
+    assert np.max(np.abs(got - want)) <= 1e-13 * scale
+    # and the fields really changed from step to step (a self-consistent run)
+    assert not torch.equal(fields_used[0], fields_used[-1])
