@@ -125,6 +125,50 @@ __device__ __forceinline__ void raw_set(Raw<K, TIER, ND>& r, int l, typename Tie
 
 constexpr int kXYMaxItems = 4;     // phase-2 items per thread (host checks)
 
+// The items tid, tid + 256, ... of a flat index space (q, r, b), b fastest
+// (extents nq x nr x nb): the start is split with float reciprocals (exact
+// for these small integers: tid < 256 and the quotient's fractional part is
+// at least 1/(2 nr nb)), then every step adds 256 items without division.
+struct Walk {
+  int32_t q, r, b;
+  int32_t dq, dr, db, nr, nb;
+  __device__ __forceinline__ void init(int32_t tid, int32_t nr_, int32_t nb_) {
+    nr = nr_;
+    nb = nb_;
+    const int32_t ne = nr * nb;
+    q = (int32_t)(((float)tid + 0.5f) * (1.0f / (float)ne));
+    const int32_t e = tid - q * ne;
+    r = (int32_t)(((float)e + 0.5f) * (1.0f / (float)nb));
+    b = e - r * nb;
+    dq = 256 / ne;
+    const int32_t de = 256 - dq * ne;
+    dr = de / nb;
+    db = de - dr * nb;
+  }
+  __device__ __forceinline__ void next() {
+    q += dq;
+    r += dr;
+    b += db;
+    if (b >= nb) {
+      b -= nb;
+      ++r;
+    }
+    if (r >= nr) {
+      r -= nr;
+      ++q;
+    }
+  }
+};
+
+// A 64-bit offset j * stride for a small per-lane j (0 <= j < O), by selects.
+template <int O>
+__device__ __forceinline__ int64_t small_mul(int32_t j, int64_t stride) {
+  int64_t r = 0;
+#pragma unroll
+  for (int v = 1; v < O; ++v) r = j == v ? (int64_t)v * stride : r;
+  return r;
+}
+
 template <int K, int TIER>
 __global__ __launch_bounds__(256) void sweep_xy_kernel(XYArgs a) {
   constexpr int O = K + 1, O2 = O * O;
@@ -150,12 +194,12 @@ __global__ __launch_bounds__(256) void sweep_xy_kernel(XYArgs a) {
   const int32_t t0 = table_index(a.map0, 0, N1 * slab);
   const int32_t t1 = table_index(a.map1, 0, slab);
   const int32_t sh0 = a.s0[t0], sh1 = a.s1[t1];
-  Mat<K, TIER> M0, M1;
+  // the dimension-0 sweep's matrices now, the dimension-1 sweep's after the
+  // tile is built (fewer scalar registers live at once)
+  Mat<K, TIER> M0;
   M0.load(a.ab0 + t0, a.cs0);
-  M1.load(a.ab1 + t1, a.cs1);
-  Rows64<K, 1> R0, R1;
+  Rows64<K, 1> R0;
   R0.load(M0.ab, M0.cs);
-  R1.load(M1.ab, M1.cs);
 
   const T* hin = reinterpret_cast<const T*>(a.in_hi);
   T* hout = reinterpret_cast<T*>(a.out_hi);
@@ -268,54 +312,61 @@ __global__ __launch_bounds__(256) void sweep_xy_kernel(XYArgs a) {
   }
   __syncthreads();
 
-  // phase 3: the dimension-1 sweep from the tile, to HBM.  Item (j0, e4):
-  // output row t = e4 / nb of the chunk, cells i0..i0+3, the tuple of modes
-  // (j0, j1), j1 = 0..k, from tile rows t + 1 (cell i - s1) and t (cell
-  // i - s1 - 1).
-  double* lout = a.out_lo;
-  for (int32_t item = (int32_t)threadIdx.x; item < O * n * nb; item += 256) {
-    const int32_t j0 = item / (n * nb);
-    const int32_t e4 = item - j0 * (n * nb);
-    const int32_t t = (int32_t)a.fnb.div((uint32_t)e4);
-    const int32_t i0 = 4 * (e4 - t * nb);
-    const bool nd1 = has64 && j0 == 0;
-    Blk4<T> xb[O], yb[O];
+  Mat<K, TIER> M1;
+  M1.load(a.ab1 + t1, a.cs1);
+  Rows64<K, 1> R1;
+  R1.load(M1.ab, M1.cs);
+
+  // phase 3: the dimension-1 sweep from the tile, to HBM.  Items (j0, t, b):
+  // output row t of the chunk, cells 4b .. 4b+3, the tuple of modes (j0, j1),
+  // j1 = 0..k, from tile rows t + 1 (cell i - s1) and t (cell i - s1 - 1).
+  {
+    const int64_t cells = a.cells;
+    T* hout_g = hout + ((int64_t)g * O2 - a.n_lo) * cells;      // mode g O2 + l at l * cells
+    Walk w;
+    w.init((int32_t)threadIdx.x, n, nb);
+    for (; w.q < O; w.next()) {
+      const int32_t j0 = w.q, t = w.r, i0 = 4 * w.b;
+      const bool nd1 = has64 && j0 == 0;
+      const int32_t eoff = (int32_t)__umul24((uint32_t)t, (uint32_t)N0) + i0;
+      const T* tcol = tile + (int32_t)__umul24((uint32_t)j0, (uint32_t)a.tstride) + eoff;
+      Blk4<T> xb[O], yb[O];
 #pragma unroll
-    for (int l1 = 0; l1 < O; ++l1) {
-      const T* pl = tile + (int64_t)(j0 + O * l1) * a.tstride;
-      yb[l1] = lds_blk4<T>(pl + t * N0 + i0);
-      xb[l1] = lds_blk4<T>(pl + (t + 1) * N0 + i0);
-    }
-    Blk4<double> x64, y64;
-    if (nd1) {
-      y64 = lds_blk4<double>(tile64 + t * N0 + i0);
-      x64 = lds_blk4<double>(tile64 + (t + 1) * N0 + i0);
-    }
-    T out[O][4];
-    double out64[4];
-    auto run = [&](auto ndc) {
-      constexpr int ND = decltype(ndc)::value;
-      Raw<K, TIER, ND> x[4], y[4];
+      for (int l1 = 0; l1 < O; ++l1) {
+        yb[l1] = lds_blk4<T>(tcol + O * l1 * a.tstride);
+        xb[l1] = lds_blk4<T>(tcol + O * l1 * a.tstride + N0);
+      }
+      Blk4<double> x64, y64;
+      if (nd1) {
+        y64 = lds_blk4<double>(tile64 + eoff);
+        x64 = lds_blk4<double>(tile64 + eoff + N0);
+      }
+      T out[O][4];
+      double out64[4];
+      auto run = [&](auto ndc) {
+        constexpr int ND = decltype(ndc)::value;
+        Raw<K, TIER, ND> x[4], y[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
+        for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int l1 = 0; l1 < O; ++l1) {
-          raw_set<K, TIER, ND>(x[v], l1, xb[l1].v[v], ND ? x64.v[v] : 0.0, a.one);
-          raw_set<K, TIER, ND>(y[v], l1, yb[l1].v[v], ND ? y64.v[v] : 0.0, a.one);
+          for (int l1 = 0; l1 < O; ++l1) {
+            raw_set<K, TIER, ND>(x[v], l1, xb[l1].v[v], ND ? x64.v[v] : 0.0, a.one);
+            raw_set<K, TIER, ND>(y[v], l1, yb[l1].v[v], ND ? y64.v[v] : 0.0, a.one);
+          }
+        tuple4<K, TIER, ND>(M1, R1, x, y, out, out64, a.one);
+      };
+      if (nd1) run(std::integral_constant<int, 1>{});
+      else run(std::integral_constant<int, 0>{});
+      const int64_t off = slab_off + (int32_t)__umul24((uint32_t)(r0 + t), (uint32_t)N0) + i0;
+      const int64_t poff = off + small_mul<O>(j0, cells);
+#pragma unroll
+      for (int j1 = 0; j1 < O; ++j1) {
+        if (nd1 && j1 == 0) {
+          const double v4[4] = {out64[0], out64[1], out64[2], out64[3]};
+          store4<double>(a.out_lo + off, v4);
+        } else {
+          store4<T>(hout_g + poff + (int64_t)(O * j1) * cells, out[j1]);
         }
-      tuple4<K, TIER, ND>(M1, R1, x, y, out, out64, a.one);
-    };
-    if (nd1) run(std::integral_constant<int, 1>{});
-    else run(std::integral_constant<int, 0>{});
-    const int64_t off = slab_off + (int64_t)(r0 + t) * N0 + i0;
-#pragma unroll
-    for (int j1 = 0; j1 < O; ++j1) {
-      const int32_t m = g * O2 + j0 + O * j1;
-      if (nd1 && j1 == 0) {
-        const double v4[4] = {out64[0], out64[1], out64[2], out64[3]};
-        store4<double>(lout + off, v4);
-      } else {
-        store4<T>(hout + (int64_t)(m - a.n_lo) * a.cells + off, out[j1]);
       }
     }
   }

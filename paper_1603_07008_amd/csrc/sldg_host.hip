@@ -667,6 +667,7 @@ sldg_status sldg_plan_ex(sldg_plan_t* out, int ndim, const int64_t* ncells, int 
   p->xcd_xy = 8;
   if (const char* env = getenv("SLDG_XY_ROWS")) p->xy_rows = std::max(0, atoi(env));
   if (const char* env = getenv("SLDG_XCD_XY")) p->xcd_xy = std::max(0, atoi(env));
+
   if (const char* env = getenv("SLDG_COLWAVES")) {
     const int c = atoi(env);
     if (c == 1 || c == 2 || c == 4) colwaves = c;
