@@ -181,3 +181,30 @@ def test_full_size_scaled_fp16_sweep_every_launch_shape(sl, big, dim):
             assert np.array_equal(raw, first[0]) and np.array_equal(sc, first[1]), \
                 f"scaled dim {dim}: shape {shape} differs"
     plan.close()
+
+
+@pytest.mark.parametrize("tier", ["fp32", "bf16", "fp64", "fp16"])
+def test_full_size_fused_step_is_bitwise_the_unfused_step(sl, big, tier):
+    """One split step at 48^4 with the (x1, x2) pairs fused (the benchmark's
+    step) and with every sweep its own pass: the same bits, with the fused
+    pass really taken (two fused launches per step)."""
+    import torch
+    prob, st0 = big
+    state = O.to_tier(st0, tier)
+    plan = sl.Plan(prob.ns, prob.k, tier)
+    seq = [(s.dim, s.dep_mask, torch.from_numpy(s.sigma).cuda()) for s in prob.seq]
+    out = {}
+    for fuse in (True, False):
+        plan.set_fusion(fuse)
+        s0 = _upload(sl, torch, state, tier)
+        s1 = plan.empty_state()
+        plan.timing_enable(True)
+        res = plan.split_steps(seq, 1, s0, s1)
+        n_fused, _ = plan.timing_read(-3)
+        plan.timing_enable(False)
+        assert n_fused == (2 if fuse else 0)
+        out[fuse] = (s0, s1)[res]
+        del s0, s1
+    for a, b in zip(out[True], out[False]):
+        assert torch.equal(a.view(torch.uint8), b.view(torch.uint8)), tier
+    plan.close()
