@@ -33,7 +33,8 @@ TIER_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}
 ARITH = {"fp64": "f64", "fp32": "f64", "bf16": "f32", "fp16": "f32"}
 KERNEL_SOURCES = ["paper_1603_07008_amd/csrc/sldg_kernels.hip", "paper_1603_07008_amd/csrc/ab_poly.h",
                   "paper_1603_07008_amd/csrc/sldg_internal.h", "paper_1603_07008_amd/csrc/sldg_sweep.h",
-                  "paper_1603_07008_amd/csrc/sldg_sweep_inst.hip", "paper_1603_07008_amd/csrc/sldg_fused.h"]
+                  "paper_1603_07008_amd/csrc/sldg_sweep_inst.hip", "paper_1603_07008_amd/csrc/sldg_fused.h",
+                  "paper_1603_07008_amd/csrc/sldg_staged.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_vlasov4d_48_k2.json")
 
 
@@ -113,15 +114,19 @@ def measured_plane_copy(sl, torch, cells, nplanes, tiers=(1, 3, 9, 27), reps=10)
     return out
 
 
-def sweep_kernel_name(ns, k, tier, d, shape):
+def sweep_kernel_name(ns, k, tier, d, shape, form=None):
     """The template instance the library launches for the sweep along d (as
-    the profiler names it): the window or lane form along dimension 0; the
-    strided kernel with its rows per thread and which of its one-value-per-
-    lane stores carry the non-temporal hint (where a wave's stores cover
-    whole 128-byte lines: the column stride P is a multiple of 64, or P times
-    the value size a multiple of 128 bytes): 0 none, 1 the 4- and 8-byte
-    values, 2 the 2-byte values too."""
+    the profiler names it; `form` as sldg_plan_sweep_form reports it): the
+    window or lane form along dimension 0; the staged strided kernel with its
+    rows per thread and column waves; the strided kernel with its rows per
+    thread and which of its one-value-per-lane stores carry the non-temporal
+    hint (where a wave's stores cover whole 128-byte lines: the column stride
+    P is a multiple of 64, or P times the value size a multiple of 128
+    bytes): 0 none, 1 the 4- and 8-byte values, 2 the 2-byte values too."""
     tid = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}[tier]
+    if form == "staged":
+        return (f"sldg::sweep_staged_kernel<{k}, {tid}, {shape['rows']}, "
+                f"{shape['colwaves'] & 7}, {1 if tier == 'fp32' else 2}>")
     if d == 0:
         if ns[0] % 4 == 0:
             return f"sldg::sweep_contig_window_kernel<{k}, {tid}, 1>"
@@ -173,7 +178,8 @@ def run_tier(sl, torch, prob, tier, init, steps, warmup, tune_cache=None, single
     else:
         shapes, _ = p.tune(seq, s0, s1, reps=3)
     tid = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}[tier]
-    out = {"plan": p, "shapes": shapes}
+    forms = {d: p.sweep_form(d, dep, s0, s1) for d, dep, _ in seq}
+    out = {"plan": p, "shapes": shapes, "forms": forms}
     m_start = p.mass(bufs[cur][0])
     for fuse in (True, False):
         p.set_fusion(fuse)
@@ -199,7 +205,7 @@ def run_tier(sl, torch, prob, tier, init, steps, warmup, tune_cache=None, single
         kern = {}                   # kernel (template instance) -> (launches, total ms)
         for d, (n, tot) in per_dim.items():
             if n:
-                name = sweep_kernel_name(prob.ns, prob.k, tier, d, shapes[d])
+                name = sweep_kernel_name(prob.ns, prob.k, tier, d, shapes[d], forms[d])
                 n0, t0 = kern.get(name, (0, 0.0))
                 kern[name] = (n0 + n, t0 + tot)
         if fused[0]:
@@ -663,6 +669,7 @@ def main():
         if n:
             per_sweep[names.get(d, str(d))] = dict(rate(tot_d, n),
                                                    launch_shape=main_r["shapes"][d],
+                                                   form=main_r["forms"][d],
                                                    single_call=main_r["single"].get(d))
     per_pass = {}                      # the step as timed: (x1, x2) pairs fused
     nf, tf = main_r["fused"]["fused"]

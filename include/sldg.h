@@ -232,13 +232,33 @@ sldg_status sldg_mass_device(sldg_plan_t plan, const double* mass, double* out_d
  *             (tuples is then ignored where the window form does not apply)
  *   tuples    spectator mode tuples per thread (0: all)
  *   colwaves  strided sweeps: waves of a workgroup side by side along the
- *             columns (1, 2 or 4; the others stack along the rows)
+ *             columns (1, 2 or 4; the others stack along the rows).  1, 2 or
+ *             4 plus SLDG_SHAPE_STAGED: the workgroup loads the source rows of
+ *             its tile (64 colwaves columns x 4 rows-per-thread chunks) into
+ *             LDS with 16-byte accesses, and every thread takes its column
+ *             from there (narrow tiers, rows 4 or 8, at most the cell mean
+ *             in FP64, tiles of whole 64-column runs, 16-byte aligned input;
+ *             elsewhere, and in a tile whose displacements spread over more
+ *             rows than it holds, the same shape runs direct)
  * Plans start from a shape measured on MI355X; sldg_plan_tune picks one per
  * dimension.  Errors: SLDG_ERR_ARG.
  */
+#define SLDG_SHAPE_STAGED 16
 sldg_status sldg_plan_set_shape(sldg_plan_t plan, int dim, int rows, int tuples, int colwaves);
 sldg_status sldg_plan_get_shape(sldg_plan_t plan, int dim, int* rows, int* tuples,
                                 int* colwaves);
+
+/*
+ * Kernel form that a sweep along `dim` with the plan's current shape runs in
+ * for these buffers (host only, no device work; dep_mask as for
+ * sldg_advect_dim): 0 dimension-0 window form, 1 dimension-0 group form,
+ * 2 strided, 3 lane form, 4 strided staged through LDS.  Errors: SLDG_ERR_ARG
+ * (null plan or form, dim or dep_mask out of range), SLDG_ERR_UNSUPPORTED
+ * (the grid does not launch).
+ */
+sldg_status sldg_plan_sweep_form(sldg_plan_t plan, int dim, uint32_t dep_mask,
+                                 const double* in_mass, const void* in_hi,
+                                 const double* out_mass, const void* out_hi, int* form);
 
 /* Candidate i of the shapes sldg_plan_tune tries, for dimension-0 (strided =
  * 0) or strided (strided = 1) sweeps; SLDG_ERR_ARG past the last one. */

@@ -15,6 +15,8 @@ LIB_PATH = os.path.join(PKG, "libsldg.so")
 SLDG_OK, SLDG_ERR_ARG, SLDG_ERR_ALIAS, SLDG_ERR_UNSUPPORTED, SLDG_ERR_NOMEM, SLDG_ERR_DEVICE = range(6)
 TIERS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
 TIER_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}
+SLDG_SHAPE_STAGED = 16    # colwaves flag: strided tile staged through LDS
+SWEEP_FORMS = ("window", "group", "strided", "lane", "staged")
 
 EXPORTS = ("sldg_plan", "sldg_plan_destroy", "sldg_plan_set_stream", "sldg_line_tables",
            "sldg_advect_dim", "sldg_split_steps", "sldg_mass", "sldg_hi_bytes",
@@ -25,7 +27,8 @@ EXPORTS = ("sldg_plan", "sldg_plan_destroy", "sldg_plan_set_stream", "sldg_line_
            "sldg_plan_ex", "sldg_lo_planes", "sldg_hi_planes", "sldg_plane_map",
            "sldg_scale_bytes", "sldg_set_scale_headroom", "sldg_scaled_import",
            "sldg_scaled_export", "sldg_advect_dim_scaled", "sldg_split_steps_scaled",
-           "sldg_plan_set_shape", "sldg_plan_get_shape", "sldg_tune_candidate", "sldg_plan_tune",
+           "sldg_plan_set_shape", "sldg_plan_get_shape", "sldg_plan_sweep_form",
+           "sldg_tune_candidate", "sldg_plan_tune",
            "sldg_device_plane_copy", "sldg_batch_get_class_tuning", "sldg_batch_set_class_tuning",
            "sldg_poisson_shift", "sldg_poisson_shift_noalloc", "sldg_vlasov_poisson_steps",
            "sldg_advect_dim_collocated", "sldg_poisson_shift_2d", "sldg_vlasov_poisson_steps_2d2v",
@@ -113,6 +116,9 @@ def lib():
     L.sldg_plan_get_shape.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                       ctypes.POINTER(i32)]
     L.sldg_plan_get_shape.restype = i32
+    L.sldg_plan_sweep_form.argtypes = [vp, i32, ctypes.c_uint32, vp, vp, vp, vp,
+                                       ctypes.POINTER(i32)]
+    L.sldg_plan_sweep_form.restype = i32
     L.sldg_tune_candidate.argtypes = [i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                       ctypes.POINTER(i32)]
     L.sldg_tune_candidate.restype = i32
@@ -470,6 +476,16 @@ class Plan:
 
     def shapes(self):
         return [self.shape(d) for d in range(self.ndim)]
+
+    def sweep_form(self, dim, dep_mask, state_in, state_out):
+        """Kernel form of a sweep along `dim` with the current shape and these
+        buffers (sldg_plan_sweep_form): one of SWEEP_FORMS."""
+        f = ctypes.c_int()
+        _check(lib().sldg_plan_sweep_form(self.handle, int(dim), int(dep_mask),
+                                          _ptr(state_in[0]), _ptr(state_in[1]),
+                                          _ptr(state_out[0]), _ptr(state_out[1]),
+                                          ctypes.byref(f)), "sldg_plan_sweep_form")
+        return SWEEP_FORMS[f.value]
 
     def tune(self, seq, state0, state1, reps=3):
         """Time the candidate shapes of every swept dimension from state0 into

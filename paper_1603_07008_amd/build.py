@@ -23,7 +23,7 @@ TIERS = (0, 1, 2, 3)
 SOURCES = [os.path.join(CSRC, f) for f in PLAIN + [INST]]
 HEADERS = [os.path.join(CSRC, f) for f in ("sldg_internal.h", "sldg_sweep.h", "ab_poly.h",
                                           "sldg_ref.h", "sldg_field.h", "sldg_colloc.h",
-                                          "sldg_fused.h")] + \
+                                          "sldg_fused.h", "sldg_staged.h")] + \
     [os.path.join(ROOT, "include", "sldg.h")]
 ARCH = os.environ.get("SLDG_OFFLOAD_ARCH", "gfx950")
 

@@ -292,7 +292,26 @@ sldg_status check_sweep(const sldg_plan_s* p, int dim, const double* shift, uint
 void describe(const sldg_plan_s* p, int dim, uint32_t dep_mask, SweepArgs& a, int64_t& ntab) {
   describe_grid(p->ndim, p->n, p->o, p->modes, dim, dep_mask, p->rows_d[dim], p->tuples_d[dim],
                 a, ntab);
-  a.colwaves = dim > 0 ? p->colwaves_d[dim] : 1;
+  a.colwaves = dim > 0 ? (p->colwaves_d[dim] & 7) : 1;
+}
+
+// Whether the strided sweep described by `a` (with the plan's shape for its
+// dimension) can run staged through LDS (sldg_staged.h): a narrow tier with
+// at most the cell mean in FP64, 4 or 8 rows per thread, 1, 2 or 4 column
+// waves, tiles of whole 64-column runs (P % (64 cw) == 0) and whole row
+// chunks (N % ((4 / cw) L) == 0), 16-byte aligned planes, a tile within the
+// LDS limit, and the planes of a tuple within 2^31 bytes (its buffer
+// accesses take 32-bit byte offsets, with 2^31 as the out-of-range mark).
+bool staged_fits(const sldg_plan_s* p, int dim, const SweepArgs& a, const void* in_hi,
+                 const void* out_hi) {
+  if (dim == 0 || a.lane || p->tier == SLDG_TIER_FP64 || p->ndouble > 1 || p->n_lo > 1) return false;
+  const int L = a.chunk, cw = a.colwaves;
+  if (!(L == 4 || L == 8) || !(cw == 1 || cw == 2 || cw == 4)) return false;
+  if (a.P % (64 * cw) != 0 || a.N % ((4 / cw) * L) != 0) return false;
+  if (((uintptr_t)in_hi | (uintptr_t)out_hi) & 15) return false;
+  const int64_t sz = elem_size(p->tier);
+  if (staged_lds_bytes(p->k, (int)sz, L, cw) > kStagedLdsMax) return false;
+  return ((int64_t)(p->o - 1) * a.mstride + 1) * a.cells * sz <= (int64_t)INT32_MAX;
 }
 
 // Launch shapes the tuner tries: (rows, tuples, column waves).  Dimension-0
@@ -307,7 +326,11 @@ constexpr int kTuneStrided[][3] = {
     {4, 1, 4},  {4, 3, 1},  {4, 3, 2},  {4, 3, 4},  {4, 9, 1},  {4, 9, 2},  {4, 9, 4},
     {4, 27, 1}, {4, 27, 2}, {4, 27, 4}, {8, 1, 1},  {8, 1, 2},  {8, 1, 4},  {8, 3, 1},
     {8, 3, 2},  {8, 3, 4},  {8, 9, 1},  {8, 9, 2},  {8, 9, 4},  {8, 27, 1}, {8, 27, 2},
-    {8, 27, 4}, {0, 1, 1},  {0, 3, 1},  {0, 9, 1},  {0, 27, 1}, {0, 0, 1}};
+    {8, 27, 4}, {0, 1, 1},  {0, 3, 1},  {0, 9, 1},  {0, 27, 1}, {0, 0, 1},
+    // staged through LDS (column waves + SLDG_SHAPE_STAGED)
+    {4, 3, 17}, {4, 9, 17}, {4, 27, 17}, {4, 3, 18}, {4, 9, 18}, {4, 27, 18},
+    {8, 3, 17}, {8, 9, 17}, {8, 27, 17}, {8, 3, 18}, {8, 9, 18}, {8, 27, 18},
+    {4, 9, 20}, {4, 27, 20}, {8, 9, 20}, {8, 27, 20}};
 constexpr int kNumTuneContig = sizeof(kTuneContig) / sizeof(kTuneContig[0]);
 constexpr int kNumTuneStrided = sizeof(kTuneStrided) / sizeof(kTuneStrided[0]);
 
@@ -459,6 +482,7 @@ sldg_status run_sweep(sldg_plan_s* p, int dim, const double* shift, uint32_t dep
   a.s_tab = p->d_s;
   a.ab_tab = p->d_ab;
   a.ab_cs = ntab;
+  a.stage = (p->colwaves_d[dim] & SLDG_SHAPE_STAGED) && staged_fits(p, dim, a, in_hi, out_hi) ? 1 : 0;
   bool timed = false;
   sldg_status tst = timing_begin(p, timed);
   if (tst != SLDG_OK) return tst;
@@ -670,7 +694,9 @@ sldg_status sldg_plan_ex(sldg_plan_t* out, int ndim, const int64_t* ncells, int 
 
   if (const char* env = getenv("SLDG_COLWAVES")) {
     const int c = atoi(env);
-    if (c == 1 || c == 2 || c == 4) colwaves = c;
+    if (c == 1 || c == 2 || c == 4 || c == (1 | SLDG_SHAPE_STAGED) ||
+        c == (2 | SLDG_SHAPE_STAGED) || c == (4 | SLDG_SHAPE_STAGED))
+      colwaves = c;
   }
   if (const char* env = getenv("SLDG_XCD_CONTIG")) p->xcd_contig = std::max(-1, atoi(env));
   if (const char* env = getenv("SLDG_XCD_STRIDED")) p->xcd_strided = std::max(-1, atoi(env));
@@ -902,8 +928,9 @@ sldg_status sldg_plan_set_shape(sldg_plan_t p, int dim, int rows, int tuples, in
   if (!(rows == 0 || rows == 1 || rows == 2 || rows == 4 || rows == 8))
     return fail(SLDG_ERR_ARG, "rows %d not in {0, 1, 2, 4, 8}", rows);
   if (tuples < 0) return fail(SLDG_ERR_ARG, "tuples %d < 0", tuples);
-  if (!(colwaves == 1 || colwaves == 2 || colwaves == 4))
-    return fail(SLDG_ERR_ARG, "colwaves %d not in {1, 2, 4}", colwaves);
+  if (!(colwaves == 1 || colwaves == 2 || colwaves == 4 || colwaves == (1 | SLDG_SHAPE_STAGED) ||
+        colwaves == (2 | SLDG_SHAPE_STAGED) || colwaves == (4 | SLDG_SHAPE_STAGED)))
+    return fail(SLDG_ERR_ARG, "colwaves %d not in {1, 2, 4, 17, 18, 20}", colwaves);
   p->rows_d[dim] = rows;
   p->tuples_d[dim] = tuples;
   p->colwaves_d[dim] = colwaves;
@@ -916,6 +943,30 @@ sldg_status sldg_plan_get_shape(sldg_plan_t p, int dim, int* rows, int* tuples, 
   if (rows) *rows = p->rows_d[dim];
   if (tuples) *tuples = p->tuples_d[dim];
   if (colwaves) *colwaves = p->colwaves_d[dim];
+  return ok();
+}
+
+sldg_status sldg_plan_sweep_form(sldg_plan_t p, int dim, uint32_t dep_mask, const double* in_lo,
+                                 const void* in_hi, const double* out_lo, const void* out_hi,
+                                 int* form) {
+  if (!p) return fail(SLDG_ERR_ARG, "plan is NULL");
+  if (!form) return fail(SLDG_ERR_ARG, "form is NULL");
+  if (dim < 0 || dim >= p->ndim) return fail(SLDG_ERR_ARG, "dim %d out of range", dim);
+  if ((dep_mask >> p->ndim) || (dep_mask & (1u << dim)))
+    return fail(SLDG_ERR_ARG, "dep_mask 0x%x invalid for dim %d", dep_mask, dim);
+  SweepArgs a{};
+  int64_t ntab = 0;
+  describe(p, dim, dep_mask, a, ntab);
+  a.in_lo = in_lo;
+  a.in_hi = in_hi;
+  a.out_lo = const_cast<double*>(out_lo);
+  a.out_hi = const_cast<void*>(out_hi);
+  a.n_lo = (int32_t)p->n_lo;
+  a.wide_fp64 = p->ndouble > 1 ? 1 : 0;
+  a.stage = (p->colwaves_d[dim] & SLDG_SHAPE_STAGED) && staged_fits(p, dim, a, in_hi, out_hi) ? 1 : 0;
+  const int f = sweep_form(dim, a);
+  if (f < 0) return fail(SLDG_ERR_UNSUPPORTED, "sweep along dim %d: grid too large", dim);
+  *form = f;
   return ok();
 }
 
@@ -974,6 +1025,12 @@ sldg_status sldg_plan_tune(sldg_plan_t p, const sldg_sweep_desc* seq, int nseq,
       p->rows_d[dim] = c[0];
       p->tuples_d[dim] = c[1];
       p->colwaves_d[dim] = c[2];
+      if (c[2] & SLDG_SHAPE_STAGED) {   // staged shapes the grid cannot take: not timed
+        SweepArgs a{};
+        int64_t nt = 0;
+        describe(p, dim, seq[q].dep_mask, a, nt);
+        if (!staged_fits(p, dim, a, hi0, hi1)) continue;
+      }
       st = run_sweep(p, dim, seq[q].shift, seq[q].dep_mask, mass0, hi0, mass1, hi1);
       if (st == SLDG_ERR_UNSUPPORTED) {    // shape not launchable on this grid: skip it
         st = SLDG_OK;

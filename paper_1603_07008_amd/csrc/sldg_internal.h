@@ -82,7 +82,28 @@ struct SweepArgs {
   const int32_t* out_exp; // [n_hi] exponent every output hi plane is written with
   float* amax_part;       // [n_hi][nslot] per-wave absmax of the outputs (before scaling)
   int32_t nslot;          // partial slots per plane of the launch (sweep_slots)
+  int32_t stage;          // strided sweep: 1 stages the tile's sources through LDS
+                          // (sldg_staged.h; the host sets it where staged_fits)
 };
+
+// Shape of a staged strided tile (sldg_staged.h) for degree k, storage size
+// sz bytes, rows per thread L and column waves cw: 16-byte load slots per
+// thread (the tile without shift spread, plus one for the 16-bit tiers; the
+// single-row-chunk tiles, cw = 4, take enough for a spread of two rows),
+// tile rows per plane they cover, and the LDS bytes of its two buffers.
+constexpr int staged_slots(int k, int sz, int L, int cw) {
+  const int ch = 64 * cw / (16 / sz), rt = (4 / cw) * L;
+  const int base = ((k + 1) * (rt + 1) * ch + 255) / 256 + (sz == 2 ? 1 : 0);
+  const int two = ((k + 1) * (rt + 3) * ch + 255) / 256;
+  return cw == 4 && two > base ? two : base;
+}
+constexpr int staged_umax(int k, int sz, int L, int cw) {
+  return staged_slots(k, sz, L, cw) * 256 / ((k + 1) * (64 * cw / (16 / sz)));
+}
+constexpr int64_t staged_lds_bytes(int k, int sz, int L, int cw) {
+  return 2LL * (k + 1) * staged_umax(k, sz, L, cw) * (64 * cw) * sz;
+}
+constexpr int64_t kStagedLdsMax = 64 * 1024;
 
 // One workgroup-sized tile of one problem of a batched sweep.
 //   kind 0: dimension-0 sweep, window form: groups [x*256, x*256+256) of 4 cells
@@ -128,6 +149,9 @@ hipError_t launch_xy_inst(const XYArgs& a, int64_t lds_bytes, int32_t nblocks, h
 // Waves of one sweep launch that compute a given output plane (the absmax
 // partial slots per plane of a scaled FP16 sweep).
 int64_t sweep_slots(int dim, const SweepArgs& a);
+// Kernel form of a sweep launch: 0 dimension-0 window, 1 group, 2 strided,
+// 3 lane, 4 strided staged through LDS; -1 if the grid does not launch.
+int sweep_form(int dim, const SweepArgs& a);
 
 // Scaled FP16 storage (sldg_kernels.hip).  A scale block holds int32 exp[n_hi]
 // followed by float amax[n_hi].

@@ -139,6 +139,13 @@ bool contig_window_ok(const SweepArgs& a) {
   return a.N % 4 == 0 && (align & 15) == 0;
 }
 
+int sweep_form(int dim, const SweepArgs& a) {
+  int form;
+  dim3 grid, block;
+  if (!sweep_grid(dim, a, form, grid, block)) return -1;
+  return form == 2 && a.stage && block.x == 256 ? 4 : form;
+}
+
 int64_t sweep_slots(int dim, const SweepArgs& a) {
   int form;
   dim3 grid, block;

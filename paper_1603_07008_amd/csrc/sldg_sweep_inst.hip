@@ -6,6 +6,7 @@
 // sldg_kernels.hip.
 #include "sldg_sweep.h"
 #include "sldg_fused.h"
+#include "sldg_staged.h"
 
 #if !defined(SLDG_K) || !defined(SLDG_TIER)
 #error "compile with -DSLDG_K=<degree> -DSLDG_TIER=<tier>"
@@ -25,6 +26,39 @@ static void launch_strided(int nt, dim3 grid, dim3 block, hipStream_t st, const 
   else sweep_strided_kernel<K, TIER, L, NDMAX, 0><<<grid, block, 0, st>>>(a);
 }
 
+// Staged strided sweep (sldg_staged.h).  The host stages only grids whose
+// columns come in runs of 64 (P % 64 == 0), where every store of a wave
+// covers whole lines: the non-temporal hint on 4-byte values (FP32) and on
+// 2-byte values too (16-bit tiers), as the direct kernel takes it there.
+template <int K, int TIER>
+static bool launch_staged(dim3 grid, hipStream_t st, const SweepArgs& a) {
+  constexpr int NT = TIER == 1 ? 1 : 2;
+  constexpr int SZ = (int)sizeof(typename Tier<TIER>::T);
+  const dim3 block(256);
+  switch (a.chunk * 8 + a.colwaves) {
+    case 4 * 8 + 1:
+      sweep_staged_kernel<K, TIER, 4, 1, NT><<<grid, block, staged_lds_bytes(K, SZ, 4, 1), st>>>(a);
+      return true;
+    case 4 * 8 + 2:
+      sweep_staged_kernel<K, TIER, 4, 2, NT><<<grid, block, staged_lds_bytes(K, SZ, 4, 2), st>>>(a);
+      return true;
+    case 8 * 8 + 1:
+      sweep_staged_kernel<K, TIER, 8, 1, NT><<<grid, block, staged_lds_bytes(K, SZ, 8, 1), st>>>(a);
+      return true;
+    case 8 * 8 + 2:
+      sweep_staged_kernel<K, TIER, 8, 2, NT><<<grid, block, staged_lds_bytes(K, SZ, 8, 2), st>>>(a);
+      return true;
+    case 4 * 8 + 4:
+      sweep_staged_kernel<K, TIER, 4, 4, NT><<<grid, block, staged_lds_bytes(K, SZ, 4, 4), st>>>(a);
+      return true;
+    case 8 * 8 + 4:
+      sweep_staged_kernel<K, TIER, 8, 4, NT><<<grid, block, staged_lds_bytes(K, SZ, 8, 4), st>>>(a);
+      return true;
+    default:
+      return false;
+  }
+}
+
 template <int K, int TIER, int NDMAX>
 static hipError_t launch_sweep_ktn(int dim, const SweepArgs& a, hipStream_t st) {
   int form;
@@ -41,6 +75,9 @@ static hipError_t launch_sweep_ktn(int dim, const SweepArgs& a, hipStream_t st) 
     // ntmask: bit 0, 1, 2 for 2-, 4-, 8-byte values.  The narrow planes'
     // value size decides; on the 16-bit tiers, the FP64 mean may take the
     // hint (mode 1) where the 2-byte planes may not (mode 2)
+    if constexpr (TIER >= 1 && NDMAX == 1) {
+      if (a.stage && block.x == 256 && launch_staged<K, TIER>(grid, st, a)) return hipGetLastError();
+    }
     int nt;
     if (TIER == 0) nt = (a.ntmask & 4) ? 1 : 0;
     else if (TIER == 1) nt = (a.ntmask & 2) ? 1 : 0;

@@ -76,6 +76,9 @@ def test_calls_on_a_null_plan(L):
     assert L.sldg_device_copy(16, 40, 16, None) == sl.SLDG_ERR_ARG
     assert L.sldg_device_copy(16, 32, 32, None) == sl.SLDG_ERR_ALIAS
     assert L.sldg_hi_bytes(None) == -1
+    f = ctypes.c_int(-1)
+    assert L.sldg_plan_sweep_form(None, 1, 0, None, None, None, None, ctypes.byref(f)) == \
+        sl.SLDG_ERR_ARG and f.value == -1
     L.sldg_plan_destroy(None)
 
 
@@ -123,7 +126,10 @@ def test_tuner_candidates_are_valid_shapes(L):
     assert {r for r, _, _ in contig} == {1, 4}
     assert {t for r, t, _ in contig if r == 1} == {t for r, t, _ in contig if r == 4}
     assert {r for r, _, _ in strided} == {0, 2, 4, 8}
-    assert all(c in (1, 2, 4) and t >= 0 for _, t, c in contig + strided)
+    assert all(c in (1, 2, 4) and t >= 0 for _, t, c in contig)
+    assert all(c in (1, 2, 4, 17, 18, 20) and t >= 0 for _, t, c in strided)
+    staged = [(r, c) for r, _, c in strided if c & sl.SLDG_SHAPE_STAGED]
+    assert staged and all(r in (4, 8) for r, _ in staged)
     assert len(set(strided)) == len(strided) and len(set(contig)) == len(contig)
 
 

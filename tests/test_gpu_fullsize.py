@@ -104,6 +104,39 @@ def test_full_size_sweeps_every_direction_and_launch_shape(sl, big, tier):
     plan.close()
 
 
+@pytest.mark.parametrize("tier", ["fp32", "bf16", "fp16"])
+def test_full_size_staged_sweeps_are_bitwise_the_direct_sweeps(sl, big, tier):
+    """The v sweeps of the 48^4 workload staged through LDS, on every cell:
+    bitwise the direct strided kernel's results (section II-A update; the
+    staged form changes only how the source values reach the threads)."""
+    import torch
+    prob, st0 = big
+    state = O.to_tier(st0, tier)
+    plan = sl.Plan(prob.ns, prob.k, tier)
+    s_in = _upload(sl, torch, state, tier)
+    ity = torch.int32 if tier == "fp32" else torch.int16
+    for sw in prob.seq:
+        if sw.dim < 2:
+            continue
+        shift = torch.from_numpy(sw.sigma).cuda()
+        plan.set_shape(sw.dim, 4, 9, 2)
+        ref = plan.empty_state()
+        assert plan.sweep_form(sw.dim, sw.dep_mask, s_in, ref) == "strided"
+        plan.advect_dim(sw.dim, shift, sw.dep_mask, *s_in, *ref)
+        for rows, tuples, cw in ((4, 27, 2), (4, 27, 4), (8, 9, 2), (4, 9, 1)):
+            plan.set_shape(sw.dim, rows, tuples, cw | sl.SLDG_SHAPE_STAGED)
+            out = plan.empty_state()
+            assert plan.sweep_form(sw.dim, sw.dep_mask, s_in, out) == "staged"
+            plan.advect_dim(sw.dim, shift, sw.dep_mask, *s_in, *out)
+            torch.cuda.synchronize()
+            what = f"{tier} dim {sw.dim} rows {rows} tuples {tuples} cw {cw}"
+            assert torch.equal(out[0], ref[0]), what
+            assert torch.equal(out[1].view(ity), ref[1].view(ity)), what
+            del out
+        del ref
+    plan.close()
+
+
 @pytest.mark.parametrize("tier,tol", [("fp32", 1e-6), ("bf16", 5e-3)])
 def test_full_size_split_step_against_fp64_oracle(sl, big, tier, tol):
     import torch
