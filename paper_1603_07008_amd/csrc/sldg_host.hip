@@ -688,7 +688,7 @@ sldg_status sldg_plan_ex(sldg_plan_t* out, int ndim, const int64_t* ncells, int 
   p->xcd_strided = 16;
   p->fuse = 1;
   p->xy_rows = 0;
-  p->xcd_xy = 8;
+  p->xcd_xy = 0;               // the fused pass: dispatch order measured best
   if (const char* env = getenv("SLDG_XY_ROWS")) p->xy_rows = std::max(0, atoi(env));
   if (const char* env = getenv("SLDG_XCD_XY")) p->xcd_xy = std::max(0, atoi(env));
 
