@@ -443,10 +443,14 @@ sldg_status timing_end(sldg_plan_s* p, bool timed, int code) {
   return SLDG_OK;
 }
 
+// One sweep.  With `pre` (a table offset into the plan's tables, entries
+// first), its line tables were computed beforehand (split steps compute
+// the tables of a whole sequence in one launch); otherwise they are computed
+// here.
 sldg_status run_sweep(sldg_plan_s* p, int dim, const double* shift, uint32_t dep_mask,
                       const double* in_lo, const void* in_hi, double* out_lo, void* out_hi,
                       bool adjoint = false, const void* in_scale = nullptr,
-                      void* out_scale = nullptr) {
+                      void* out_scale = nullptr, int64_t pre = -1) {
   SweepArgs a{};
   int64_t ntab = 0;
   describe(p, dim, dep_mask, a, ntab);
@@ -469,9 +473,14 @@ sldg_status run_sweep(sldg_plan_s* p, int dim, const double* shift, uint32_t dep
   if (ntab > p->table_cap)
     return fail(SLDG_ERR_ARG, "line table of %lld entries exceeds the plan's %lld",
                 (long long)ntab, (long long)p->table_cap);
-  hipError_t e = launch_line_tables(p->k, ntab, p->n[dim], shift, p->d_s, p->d_ab, true,
-                                    adjoint, p->stream);
-  if (e != hipSuccess) return device_error(e, "line-table launch");
+  const int64_t o2 = (int64_t)p->o * p->o;
+  const int64_t toff = pre >= 0 ? pre : 0;
+  hipError_t e = hipSuccess;
+  if (pre < 0) {
+    e = launch_line_tables(p->k, ntab, p->n[dim], shift, p->d_s, p->d_ab, true, adjoint,
+                           p->stream);
+    if (e != hipSuccess) return device_error(e, "line-table launch");
+  }
   a.in_lo = in_lo;
   a.in_hi = in_hi;
   a.out_lo = out_lo;
@@ -479,8 +488,8 @@ sldg_status run_sweep(sldg_plan_s* p, int dim, const double* shift, uint32_t dep
   a.pmap = p->d_pmap;
   a.n_lo = (int32_t)p->n_lo;
   a.wide_fp64 = p->ndouble > 1 ? 1 : 0;
-  a.s_tab = p->d_s;
-  a.ab_tab = p->d_ab;
+  a.s_tab = p->d_s + toff;
+  a.ab_tab = p->d_ab + 2 * o2 * toff;
   a.ab_cs = ntab;
   a.stage = (p->colwaves_d[dim] & SLDG_SHAPE_STAGED) && staged_fits(p, dim, a, in_hi, out_hi) ? 1 : 0;
   bool timed = false;
@@ -546,9 +555,11 @@ bool xy_eligible(const sldg_plan_s* p, uint32_t mask0, uint32_t mask1, const dou
   return *why == nullptr;
 }
 
+// The fused (0, 1) pair.  With pre0 >= 0 the two sweeps' tables were
+// computed beforehand, at entries pre0 and pre1 of the plan's tables.
 sldg_status run_xy(sldg_plan_s* p, const double* shift0, uint32_t mask0, const double* shift1,
                    uint32_t mask1, const double* in_lo, const void* in_hi, double* out_lo,
-                   void* out_hi) {
+                   void* out_hi, int64_t pre0 = -1, int64_t pre1 = -1) {
   SweepArgs a0{}, a1{};
   int64_t nt0 = 0, nt1 = 0;
   describe(p, 0, mask0, a0, nt0);
@@ -557,12 +568,16 @@ sldg_status run_xy(sldg_plan_s* p, const double* shift0, uint32_t mask0, const d
     return fail(SLDG_ERR_UNSUPPORTED, "fused sweeps: line tables of %lld + %lld entries exceed %lld",
                 (long long)nt0, (long long)nt1, (long long)p->table_cap);
   const int64_t o2 = (int64_t)p->o * p->o;
-  hipError_t e = launch_line_tables(p->k, nt0, p->n[0], shift0, p->d_s, p->d_ab, true, false,
-                                    p->stream);
-  if (e == hipSuccess)
-    e = launch_line_tables(p->k, nt1, p->n[1], shift1, p->d_s + nt0, p->d_ab + 2 * o2 * nt0,
-                           true, false, p->stream);
-  if (e != hipSuccess) return device_error(e, "line-table launch");
+  hipError_t e = hipSuccess;
+  if (pre0 < 0) {
+    pre0 = 0;
+    pre1 = nt0;
+    e = launch_line_tables(p->k, nt0, p->n[0], shift0, p->d_s, p->d_ab, true, false, p->stream);
+    if (e == hipSuccess)
+      e = launch_line_tables(p->k, nt1, p->n[1], shift1, p->d_s + nt0, p->d_ab + 2 * o2 * nt0,
+                             true, false, p->stream);
+    if (e != hipSuccess) return device_error(e, "line-table launch");
+  }
   const int32_t R = xy_tile_rows(p);
   XYArgs x{};
   x.in_lo = in_lo;
@@ -582,12 +597,12 @@ sldg_status run_xy(sldg_plan_s* p, const double* shift0, uint32_t mask0, const d
   x.fnb = FastDiv::make((uint32_t)(x.N0 / 4));
   x.fnrc = FastDiv::make((uint32_t)x.nrc);
   x.fQ = FastDiv::make((uint32_t)x.Q);
-  x.s0 = p->d_s;
-  x.ab0 = p->d_ab;
+  x.s0 = p->d_s + pre0;
+  x.ab0 = p->d_ab + 2 * o2 * pre0;
   x.cs0 = nt0;
   x.map0 = a0.map;
-  x.s1 = p->d_s + nt0;
-  x.ab1 = p->d_ab + 2 * o2 * nt0;
+  x.s1 = p->d_s + pre1;
+  x.ab1 = p->d_ab + 2 * o2 * pre1;
   x.cs1 = nt1;
   x.map1 = a1.map;
   const int64_t nblocks = (int64_t)x.nrc * x.Q * (p->modes / o2);
@@ -882,17 +897,42 @@ sldg_status sldg_split_steps(sldg_plan_t p, const sldg_sweep_desc* seq, int nseq
       ++q;
     }
   }
+  // The line tables of every sweep of the sequence, in one launch before the
+  // steps: the displacements are fixed over the call, so every step's tables
+  // are these.  Where the sequence's tables do not fit the plan's table
+  // storage together, each sweep computes its own.
+  std::vector<int64_t> pre((size_t)std::max(nseq, 1), -1);
+  if (nsteps > 0 && nseq > 0 && nseq <= kMaxTableSet) {
+    TableSet set{};
+    set.count = nseq;
+    int64_t tot = 0;
+    for (int q = 0; q < nseq; ++q) {
+      SweepArgs a{};
+      int64_t nt = 0;
+      describe(p, seq[q].dim, seq[q].dep_mask, a, nt);
+      set.first[q] = tot;
+      set.period[q] = p->n[seq[q].dim];
+      set.sigma[q] = seq[q].shift;
+      tot += nt;
+    }
+    set.first[nseq] = tot;
+    if (tot <= p->table_cap) {
+      const hipError_t e = launch_line_tables_set(p->k, set, p->d_s, p->d_ab, p->stream);
+      if (e != hipSuccess) return device_error(e, "line-table launch");
+      for (int q = 0; q < nseq; ++q) pre[(size_t)q] = set.first[q];
+    }
+  }
   int cur = 0;
   for (int n = 0; n < nsteps; ++n) {
     for (int q = 0; q < nseq; ++q) {
       sldg_status st;
       if (fused[(size_t)q]) {
         st = run_xy(p, seq[q].shift, seq[q].dep_mask, seq[q + 1].shift, seq[q + 1].dep_mask,
-                    m[cur], h[cur], m[1 - cur], h[1 - cur]);
+                    m[cur], h[cur], m[1 - cur], h[1 - cur], pre[(size_t)q], pre[(size_t)q + 1]);
         ++q;
       } else {
         st = run_sweep(p, seq[q].dim, seq[q].shift, seq[q].dep_mask, m[cur], h[cur], m[1 - cur],
-                       h[1 - cur]);
+                       h[1 - cur], false, nullptr, nullptr, pre[(size_t)q]);
       }
       if (st != SLDG_OK) return st;
       cur = 1 - cur;

@@ -116,10 +116,23 @@ struct BatchItem {
   int32_t prob, kind, x, qg, z;
 };
 
+// The line tables of up to kMaxTableSet sweeps computed in one launch
+// (forward tables, component-major): sweep q has first[q + 1] - first[q]
+// entries, period[q] cells along its dimension and displacements sigma[q].
+constexpr int kMaxTableSet = 16;
+struct TableSet {
+  int32_t count;
+  int64_t first[kMaxTableSet + 1];
+  int64_t period[kMaxTableSet];
+  const double* sigma[kMaxTableSet];
+};
+
 // Launchers (defined in sldg_kernels.hip).  All return hipGetLastError().
 hipError_t launch_line_tables(int k, int64_t n, int64_t period, const double* sigma,
                               int32_t* s_out, double* ab_out, bool component_major,
                               bool adjoint, hipStream_t st);
+hipError_t launch_line_tables_set(int k, const TableSet& set, int32_t* s_out, double* ab_out,
+                                  hipStream_t st);
 hipError_t launch_sweep(int k, int tier, int dim, const SweepArgs& a, hipStream_t st);
 hipError_t launch_mass(const double* mass, int64_t n, double* partial, int nblocks,
                        double* result, hipStream_t st);

@@ -58,15 +58,11 @@ __device__ __forceinline__ double horner_comp(const double (&c)[2 * K + 2], doub
 // the same (snapped, exact-mass-row) A and B, so it is the exact transpose of
 // the forward map.
 template <int K, bool ADJ>
-__global__ __launch_bounds__(256) void line_tables_kernel(int64_t n, int64_t period,
-                                                          const double* __restrict__ sigma,
-                                                          int32_t* __restrict__ s_out,
-                                                          double* __restrict__ ab_out,
-                                                          int64_t cs, int64_t ts) {
+__device__ __forceinline__ void line_table_entry(int64_t t, double sg, int64_t period,
+                                                 int32_t* __restrict__ s_out,
+                                                 double* __restrict__ ab_out, int64_t cs,
+                                                 int64_t ts) {
   constexpr int O = K + 1;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const double sg = sigma[t];
   double fs = floor(sg);
   double alpha = sg - fs;
   const double beta0 = 1.0 - alpha;
@@ -112,6 +108,34 @@ __global__ __launch_bounds__(256) void line_tables_kernel(int64_t n, int64_t per
     }
 }
 
+template <int K, bool ADJ>
+__global__ __launch_bounds__(256) void line_tables_kernel(int64_t n, int64_t period,
+                                                          const double* __restrict__ sigma,
+                                                          int32_t* __restrict__ s_out,
+                                                          double* __restrict__ ab_out,
+                                                          int64_t cs, int64_t ts) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  line_table_entry<K, ADJ>(t, sigma[t], period, s_out, ab_out, cs, ts);
+}
+
+// The tables of several sweeps (forward, component-major) in one launch:
+// entry t of the flat range belongs to sweep q with first[q] <= t <
+// first[q + 1]; sweep q's table is the one line_tables_kernel writes, at
+// s_out + first[q] and ab_out + 2 (k+1)^2 first[q].
+template <int K>
+__global__ __launch_bounds__(256) void line_tables_set_kernel(TableSet set,
+                                                              int32_t* __restrict__ s_out,
+                                                              double* __restrict__ ab_out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= set.first[set.count]) return;
+  int q = 0;
+  while (q + 1 < set.count && t >= set.first[q + 1]) ++q;
+  const int64_t f = set.first[q], n = set.first[q + 1] - f;
+  line_table_entry<K, false>(t - f, set.sigma[q][t - f], set.period[q], s_out + f,
+                             ab_out + 2LL * (K + 1) * (K + 1) * f, n, 1);
+}
+
 hipError_t launch_line_tables(int k, int64_t n, int64_t period, const double* sigma,
                               int32_t* s_out, double* ab_out, bool component_major,
                               bool adjoint, hipStream_t st) {
@@ -130,6 +154,20 @@ hipError_t launch_line_tables(int k, int64_t n, int64_t period, const double* si
     default: return hipErrorInvalidValue;
   }
 #undef SLDG_TABLES
+  return hipGetLastError();
+}
+
+hipError_t launch_line_tables_set(int k, const TableSet& set, int32_t* s_out, double* ab_out,
+                                  hipStream_t st) {
+  const int64_t n = set.first[set.count];
+  if (n <= 0) return hipSuccess;
+  dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  switch (k) {
+    case 1: line_tables_set_kernel<1><<<grid, block, 0, st>>>(set, s_out, ab_out); break;
+    case 2: line_tables_set_kernel<2><<<grid, block, 0, st>>>(set, s_out, ab_out); break;
+    case 3: line_tables_set_kernel<3><<<grid, block, 0, st>>>(set, s_out, ab_out); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
