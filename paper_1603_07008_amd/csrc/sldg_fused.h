@@ -125,6 +125,14 @@ __device__ __forceinline__ void raw_set(Raw<K, TIER, ND>& r, int l, typename Tie
 
 constexpr int kXYMaxItems = 4;     // phase-2 items per thread (host checks)
 
+// The 5-cell window at a compile-time offset D of the first of two
+// consecutive 4-cell blocks.
+template <class T, int D>
+__device__ __forceinline__ void window5_at(const Blk4<T>& b0, const Blk4<T>& b1, T (&w)[5]) {
+#pragma unroll
+  for (int v = 0; v < 5; ++v) w[v] = D + v < 4 ? b0.v[D + v] : b1.v[D + v - 4];
+}
+
 // The items tid, tid + 256, ... of a flat index space (q, r, b), b fastest
 // (extents nq x nr x nb): the start is split with float reciprocals (exact
 // for these small integers: tid < 256 and the quotient's fractional part is
@@ -243,52 +251,65 @@ __global__ __launch_bounds__(256) void sweep_xy_kernel(XYArgs a) {
   // j0 = 0..k.  The sources of output cells i0..i0+3 are the 5 cells from
   // c = i0 - s0 - 1 (periodic in the row), inside the aligned blocks at
   // c & ~3 and the next one.
+  // The window's offset in its first block, (i0 - s0 - 1) mod 4, is the
+  // same for every item (i0 and N0 are multiples of 4, s0 is uniform over
+  // the slab): phase 2 is compiled for each of the 4 offsets and takes the
+  // window by fixed indices instead of per-lane selects.
   T res[kXYMaxItems][O][4];
   double res64[kXYMaxItems][4];
   const int32_t nitem = O * rows * nb;
+  auto phase2 = [&](auto dc) {
+    constexpr int D = decltype(dc)::value;
 #pragma unroll
-  for (int it = 0; it < kXYMaxItems; ++it) {
-    const int32_t item = (int32_t)threadIdx.x + 256 * it;
-    if (item >= nitem) break;
-    const int32_t j1 = item / (rows * nb);
-    const int32_t e4 = item - j1 * (rows * nb);
-    const int32_t u = (int32_t)a.fnb.div((uint32_t)e4);
-    const int32_t i0 = 4 * (e4 - u * nb);
-    int32_t c = i0 - sh0 - 1;
-    if (c < 0) c += N0;
-    const int32_t blk0 = c & ~3, d = c & 3;
-    int32_t blk1 = blk0 + 4;
-    if (blk1 == N0) blk1 = 0;
-    const int32_t rowoff = u * N0;
-    T wv[O][5];
-    double w64[5];
+    for (int it = 0; it < kXYMaxItems; ++it) {
+      const int32_t item = (int32_t)threadIdx.x + 256 * it;
+      if (item >= nitem) break;
+      const int32_t j1 = item / (rows * nb);
+      const int32_t e4 = item - j1 * (rows * nb);
+      const int32_t u = (int32_t)a.fnb.div((uint32_t)e4);
+      const int32_t i0 = 4 * (e4 - u * nb);
+      int32_t c = i0 - sh0 - 1;
+      if (c < 0) c += N0;
+      const int32_t blk0 = c & ~3;
+      int32_t blk1 = blk0 + 4;
+      if (blk1 == N0) blk1 = 0;
+      const int32_t rowoff = u * N0;
+      T wv[O][5];
+      double w64[5];
 #pragma unroll
-    for (int l0 = 0; l0 < O; ++l0) {
-      const int32_t l = l0 + O * j1;
-      const T* pl = tile + (int64_t)l * a.tstride + rowoff;
-      const Blk4<T> b0 = lds_blk4<T>(pl + blk0), b1 = lds_blk4<T>(pl + blk1);
-      window5<T>(b0, b1, d, wv[l0]);
+      for (int l0 = 0; l0 < O; ++l0) {
+        const int32_t l = l0 + O * j1;
+        const T* pl = tile + (int64_t)l * a.tstride + rowoff;
+        const Blk4<T> b0 = lds_blk4<T>(pl + blk0), b1 = lds_blk4<T>(pl + blk1);
+        window5_at<T, D>(b0, b1, wv[l0]);
+      }
+      const bool nd1 = has64 && j1 == 0;
+      if (nd1) {
+        const Blk4<double> b0 = lds_blk4<double>(tile64 + rowoff + blk0);
+        const Blk4<double> b1 = lds_blk4<double>(tile64 + rowoff + blk1);
+        window5_at<double, D>(b0, b1, w64);
+      }
+      auto run = [&](auto ndc) {
+        constexpr int ND = decltype(ndc)::value;
+        Raw<K, TIER, ND> x[4], y[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int l0 = 0; l0 < O; ++l0) {
+            raw_set<K, TIER, ND>(x[v], l0, wv[l0][v + 1], ND ? w64[v + 1] : 0.0, a.one);
+            raw_set<K, TIER, ND>(y[v], l0, wv[l0][v], ND ? w64[v] : 0.0, a.one);
+          }
+        tuple4<K, TIER, ND>(M0, R0, x, y, res[it], res64[it], a.one);
+      };
+      if (nd1) run(std::integral_constant<int, 1>{});
+      else run(std::integral_constant<int, 0>{});
     }
-    const bool nd1 = has64 && j1 == 0;
-    if (nd1) {
-      const Blk4<double> b0 = lds_blk4<double>(tile64 + rowoff + blk0);
-      const Blk4<double> b1 = lds_blk4<double>(tile64 + rowoff + blk1);
-      window5<double>(b0, b1, d, w64);
-    }
-    auto run = [&](auto ndc) {
-      constexpr int ND = decltype(ndc)::value;
-      Raw<K, TIER, ND> x[4], y[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int l0 = 0; l0 < O; ++l0) {
-          raw_set<K, TIER, ND>(x[v], l0, wv[l0][v + 1], ND ? w64[v + 1] : 0.0, a.one);
-          raw_set<K, TIER, ND>(y[v], l0, wv[l0][v], ND ? w64[v] : 0.0, a.one);
-        }
-      tuple4<K, TIER, ND>(M0, R0, x, y, res[it], res64[it], a.one);
-    };
-    if (nd1) run(std::integral_constant<int, 1>{});
-    else run(std::integral_constant<int, 0>{});
+  };
+  switch (__builtin_amdgcn_readfirstlane((-sh0 - 1) & 3)) {
+    case 0: phase2(std::integral_constant<int, 0>{}); break;
+    case 1: phase2(std::integral_constant<int, 1>{}); break;
+    case 2: phase2(std::integral_constant<int, 2>{}); break;
+    default: phase2(std::integral_constant<int, 3>{}); break;
   }
   __syncthreads();
 #pragma unroll
