@@ -459,7 +459,8 @@ sldg_status run_sweep(sldg_plan_s* p, int dim, const double* shift, uint32_t dep
   ScaleBlock sin{}, sout{};
   if (scaled) {
     const int64_t nslot = sweep_slots(dim, a);
-    if (nslot < 0 || nslot > INT32_MAX)
+    // the kernels address the partials with 32-bit byte offsets
+    if (nslot < 0 || nslot > INT32_MAX || p->n_hi * nslot > INT32_MAX / 4)
       return fail(SLDG_ERR_UNSUPPORTED, "sweep along dim %d: grid too large for one launch", dim);
     sldg_status st = ensure_part(p, std::max<int64_t>(1, p->n_hi * nslot));
     if (st != SLDG_OK) return st;
