@@ -239,11 +239,19 @@ sldg_status sldg_mass_device(sldg_plan_t plan, const double* mass, double* out_d
  *             from there (narrow tiers, rows 4 or 8, at most the cell mean
  *             in FP64, tiles of whole 64-column runs, 16-byte aligned input;
  *             elsewhere, and in a tile whose displacements spread over more
- *             rows than it holds, the same shape runs direct)
+ *             rows than it holds, the same shape runs direct).  Plus
+ *             SLDG_SHAPE_MEMORDER (with or without SLDG_SHAPE_STAGED): the
+ *             workgroups take their tiles in memory order, the column blocks
+ *             of a row chunk group before the next group (where the blocks
+ *             tile the P columns below the swept dimension exactly; elsewhere
+ *             the flag has no effect); without it the row chunk groups of a
+ *             column block come one after the other.  The order changes no
+ *             result bit.
  * Plans start from a shape measured on MI355X; sldg_plan_tune picks one per
  * dimension.  Errors: SLDG_ERR_ARG.
  */
 #define SLDG_SHAPE_STAGED 16
+#define SLDG_SHAPE_MEMORDER 32
 sldg_status sldg_plan_set_shape(sldg_plan_t plan, int dim, int rows, int tuples, int colwaves);
 sldg_status sldg_plan_get_shape(sldg_plan_t plan, int dim, int* rows, int* tuples,
                                 int* colwaves);

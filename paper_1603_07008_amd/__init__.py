@@ -16,6 +16,7 @@ SLDG_OK, SLDG_ERR_ARG, SLDG_ERR_ALIAS, SLDG_ERR_UNSUPPORTED, SLDG_ERR_NOMEM, SLD
 TIERS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
 TIER_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}
 SLDG_SHAPE_STAGED = 16    # colwaves flag: strided tile staged through LDS
+SLDG_SHAPE_MEMORDER = 32  # colwaves flag: strided tiles in memory order
 SWEEP_FORMS = ("window", "group", "strided", "lane", "staged")
 
 EXPORTS = ("sldg_plan", "sldg_plan_destroy", "sldg_plan_set_stream", "sldg_line_tables",

@@ -77,6 +77,8 @@ struct SweepArgs {
   FastDiv fG;             // division by ceil(N / 4) (dimension-0 group form)
   LineMap map;
   int32_t xcd;            // XCD-aware tile order: run length G (0 off, -1 one range per XCD)
+  int32_t nblk;           // strided sweep: column blocks per slab (P / columns per tile) for
+                          // tiles in memory order, 0 for row chunk groups fastest
   // FP16 storage with per-plane power-of-two scaling (all null: unscaled)
   const int32_t* in_exp;  // [n_hi] storage exponent of every input hi plane
   const int32_t* out_exp; // [n_hi] exponent every output hi plane is written with

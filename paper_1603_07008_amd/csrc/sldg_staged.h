@@ -76,8 +76,8 @@ __device__ __forceinline__ void staged_direct(const SweepArgs& a, int32_t ilow, 
     const int32_t low = q % ms;
     const TupleMap tm = tuple_map<1>(a, low + (q / ms) * ms * O, ms, O);
     dispatch_nd<1>(tm.nd, [&](auto ndc) {
-      strided_single<K, TIER, decltype(ndc)::value, L, NT>(a, tm, M, base, roff, r0, n, slot,
-                                                         true);
+      strided_single<K, TIER, decltype(ndc)::value, L, NT>(a, tm, M, base, roff, r0, n, false,
+                                                         slot, true);
     });
   }
 }
@@ -93,18 +93,10 @@ __global__ __launch_bounds__(256) void sweep_staged_kernel(SweepArgs a) {
   __shared__ int32_t red[3];
 
   // tile coordinates: as the direct kernel (x column block, y tuple run,
-  // z row chunk group, XCD-aware order)
-  uint32_t bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
-  const uint32_t gx = gridDim.x, gz = gridDim.z;
-  if (a.xcd) {
-    const uint32_t t = xcd_tile(blockIdx.x + gx * (blockIdx.y + gridDim.y * blockIdx.z),
-                                gx * gridDim.y * gz, a.xcd);
-    const uint32_t xz = gx * gz;
-    by = t / xz;
-    const uint32_t r = t - by * xz;
-    bx = r / gz;
-    bz = r - bx * gz;
-  }
+  // z row chunk group, in the same order)
+  uint32_t bx, by, bz;
+  strided_tile(a, bx, by, bz);
+  const uint32_t gx = gridDim.x;
   const int32_t tid = (int32_t)threadIdx.x;
   const int32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int32_t wc = wave % CW, wz = wave / CW;

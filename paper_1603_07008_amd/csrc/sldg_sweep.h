@@ -827,6 +827,37 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t w, uint32_t n, int32_t G) 
   return ((i / g) * 8 + xcd) * g + i % g;
 }
 
+// Tile of a strided-sweep workgroup: x column block, y tuple run, z row
+// chunk group.  The tuple run is the slowest index.  Within a run, either the
+// row chunk groups of a column block follow one another (nblk = 0), or the
+// tiles go in memory order: the nblk column blocks of a slab (one value of the
+// dimensions above the swept one) for one row chunk group, then the slab's
+// next row chunk group, then the next slab, so that the tiles in flight cover
+// one contiguous range of every plane.  XCD runs of length xcd are laid over
+// either order; the hardware order (x fastest) is kept when both are off.
+__device__ __forceinline__ void strided_tile(const SweepArgs& a, uint32_t& bx, uint32_t& by,
+                                             uint32_t& bz) {
+  bx = blockIdx.x;
+  by = blockIdx.y;
+  bz = blockIdx.z;
+  if (!a.xcd && !a.nblk) return;
+  const uint32_t gx = gridDim.x, gz = gridDim.z, xz = gx * gz;
+  const uint32_t t = xcd_tile(blockIdx.x + gx * (blockIdx.y + gridDim.y * blockIdx.z),
+                              xz * gridDim.y, a.xcd);
+  by = t / xz;
+  const uint32_t r = t - by * xz;
+  if (a.nblk) {
+    const uint32_t nb = (uint32_t)a.nblk;
+    const uint32_t rest = r / nb;
+    const uint32_t ih = rest / gz;
+    bz = rest - ih * gz;
+    bx = ih * nb + (r - rest * nb);
+  } else {
+    bx = r / gz;
+    bz = r - bx * gz;
+  }
+}
+
 template <int K, int TIER, int NDMAX>
 __global__ __launch_bounds__(256) void sweep_contig_window_kernel(SweepArgs a) {
   uint32_t bx = blockIdx.x, by = blockIdx.y;
@@ -869,71 +900,97 @@ __global__ __launch_bounds__(256) void sweep_contig_group_kernel(SweepArgs a) {
 // neighbouring chunk, loaded by a wave of the same workgroup.
 // ---------------------------------------------------------------------------
 
-template <int K, int TIER, int ND, int L>
+// Source rows of a thread: L+1 rows from row i-s-1 of its own shift s, or
+// with SP = 1 the L+2 rows from the wave's larger shift (see strided_cell).
+template <int K, int TIER, int ND, int L, int SP = 0>
 struct Rows {
-  Raw<K, TIER, ND> v[L + 1];
+  Raw<K, TIER, ND> v[L + 1 + SP];
 };
 
-template <int K, int TIER, int ND, int L>
+template <int K, int TIER, int ND, int L, int SP>
 __device__ __forceinline__ void strided_load(const Planes<K, TIER, ND>& pl, int64_t base,
-                                             const int32_t (&roff)[L + 1],
-                                             Rows<K, TIER, ND, L>& R) {
-  // all L+1 rows are loaded (row offsets wrap); only the stores are cut
+                                             const int32_t (&roff)[L + 1 + SP],
+                                             Rows<K, TIER, ND, L, SP>& R) {
+  // all rows are loaded (row offsets wrap); only the stores are cut
 #pragma unroll
-  for (int u = 0; u <= L; ++u) pl.load(base + roff[u], R.v[u]);
+  for (int u = 0; u <= L + SP; ++u) pl.load(base + roff[u], R.v[u]);
 }
 
-template <int K, int TIER, int ND, int L, int NT>
+// dl ? x1 : x0, field by field (lanes one row below the wave's shift take
+// their window one row further down)
+template <int K, int TIER, int ND>
+__device__ __forceinline__ Raw<K, TIER, ND> pick_row(bool dl, const Raw<K, TIER, ND>& x1,
+                                                     const Raw<K, TIER, ND>& x0) {
+  Raw<K, TIER, ND> r;
+#pragma unroll
+  for (int l = 0; l < K + 1; ++l) {
+    if (l < ND) r.d[l] = dl ? x1.d[l] : x0.d[l];
+    else r.h[l] = dl ? x1.h[l] : x0.h[l];
+  }
+  return r;
+}
+
+template <int K, int TIER, int ND, int L, int NT, int SP>
 __device__ __forceinline__ void strided_store(const SweepArgs& a, const Planes<K, TIER, ND>& pl,
                                               int64_t base, int32_t r0, int32_t n,
                                               const Mat<K, TIER>& M, const Rows64<K, ND>& R64,
-                                              const Rows<K, TIER, ND, L>& R, int32_t slot,
-                                              bool active) {
+                                              const Rows<K, TIER, ND, L, SP>& R, bool dl,
+                                              int32_t slot, bool active) {
   const int32_t P = a.P;
   float am[K + 1];
   zero_amax(am);
+  auto row = [&](int u) {
+    const int64_t c = base + (int64_t)(r0 + u) * P;
+    if constexpr (SP == 0) {
+      pl.template store<NT>(c, M, R64, R.v[u + 1], R.v[u], am, active);
+    } else {
+      const Raw<K, TIER, ND> x = pick_row<K, TIER, ND>(dl, R.v[u + 2], R.v[u + 1]);
+      const Raw<K, TIER, ND> y = pick_row<K, TIER, ND>(dl, R.v[u + 1], R.v[u]);
+      pl.template store<NT>(c, M, R64, x, y, am, active);
+    }
+  };
   if (n == L) {            // full chunk: no per-row predicate
 #pragma unroll
-    for (int u = 0; u < L; ++u)
-      pl.template store<NT>(base + (int64_t)(r0 + u) * P, M, R64, R.v[u + 1], R.v[u], am, active);
+    for (int u = 0; u < L; ++u) row(u);
   } else {                 // the last chunk of a line whose length L does not divide
 #pragma unroll
     for (int u = 0; u < L; ++u)
-      if (u < n)
-        pl.template store<NT>(base + (int64_t)(r0 + u) * P, M, R64, R.v[u + 1], R.v[u], am, active);
+      if (u < n) row(u);
   }
   flush_amax<K, TIER, ND>(a, pl, am, slot);
 }
 
-template <int K, int TIER, int ND, int L, int NT>
+template <int K, int TIER, int ND, int L, int NT, int SP = 0>
 __device__ __forceinline__ void strided_single(const SweepArgs& a, const TupleMap& tm,
                                                const Mat<K, TIER>& M, int64_t base,
-                                               const int32_t (&roff)[L + 1], int32_t r0,
-                                               int32_t n, int32_t slot, bool active) {
+                                               const int32_t (&roff)[L + 1 + SP], int32_t r0,
+                                               int32_t n, bool dl, int32_t slot, bool active) {
   Planes<K, TIER, ND> pl;
   pl.bind(a, tm);
   Rows64<K, ND> R64;
   R64.load(M.ab, M.cs);
-  Rows<K, TIER, ND, L> R;
-  strided_load<K, TIER, ND, L>(pl, base, roff, R);
-  strided_store<K, TIER, ND, L, NT>(a, pl, base, r0, n, M, R64, R, slot, active);
+  Rows<K, TIER, ND, L, SP> R;
+  strided_load<K, TIER, ND, L, SP>(pl, base, roff, R);
+  strided_store<K, TIER, ND, L, NT, SP>(a, pl, base, r0, n, M, R64, R, dl, slot, active);
 }
 
-template <int K, int TIER, int L, int NDMAX, int NT>
+// One thread's column: table entry t, rows from i - s - 1 on.  SP = 0: s is
+// the column's shift.  SP = 1: s is the larger of the wave's two shifts
+// (modulo N) and dl says that the column's shift is one less.
+template <int K, int TIER, int L, int NDMAX, int NT, int SP = 0>
 __device__ __forceinline__ void strided_body(const SweepArgs& a, int32_t ilow, int32_t chunk,
-                                             int32_t ihigh, int32_t t, int32_t q, int32_t qe,
-                                             int32_t slot, bool active) {
+                                             int32_t ihigh, int32_t t, int32_t s, bool dl,
+                                             int32_t q, int32_t qe, int32_t slot, bool active) {
   constexpr int O = K + 1;
-  const int32_t s = a.s_tab[t];
   const int32_t N = a.N, P = a.P, ms = a.mstride;
   const int64_t base = (int64_t)ihigh * P * N + ilow;
   const int32_t r0 = chunk * L;
   const int32_t n = min(L, N - r0);
-  int32_t roff[L + 1];
+  int32_t roff[L + 1 + SP];
   int32_t row = r0 - s - 1;
   if (row < 0) row += N;
 #pragma unroll
-  for (int u = 0; u <= L; ++u) {
+  for (int u = 0; u <= L + SP; ++u) {
     roff[u] = row * P;
     if (++row == N) row = 0;
   }
@@ -955,8 +1012,8 @@ __device__ __forceinline__ void strided_body(const SweepArgs& a, int32_t ilow, i
     const TupleMap tm = tuple_map<NDMAX>(a, m0, ms, O);
     if (tm.nd != 0) {
       dispatch_nd<NDMAX>(tm.nd, [&](auto ndc) {
-        strided_single<K, TIER, decltype(ndc)::value, L, NT>(a, tm, M, base, roff, r0, n, slot,
-                                                         active);
+        strided_single<K, TIER, decltype(ndc)::value, L, NT, SP>(a, tm, M, base, roff, r0, n, dl,
+                                                             slot, active);
       });
       advance(q, low, m0);
       continue;
@@ -965,26 +1022,26 @@ __device__ __forceinline__ void strided_body(const SweepArgs& a, int32_t ilow, i
     // in flight would wait for it).
     Planes<K, TIER, 0> pa, pb;
     Rows64<K, 0> R64;
-    Rows<K, TIER, 0, L> ra, rb;
+    Rows<K, TIER, 0, L, SP> ra, rb;
     pa.bind(a, tm);
-    strided_load<K, TIER, 0, L>(pa, base, roff, ra);
+    strided_load<K, TIER, 0, L, SP>(pa, base, roff, ra);
     // the tuple after (q, low, m0): binds and loads it if it exists and has no
     // FP64 mode; (q, low, m0) move on to it either way
-    auto next = [&](Planes<K, TIER, 0>& p, Rows<K, TIER, 0, L>& r) {
+    auto next = [&](Planes<K, TIER, 0>& p, Rows<K, TIER, 0, L, SP>& r) {
       advance(q, low, m0);
       if (q >= qe) return false;
       const TupleMap t1 = tuple_map<NDMAX>(a, m0, ms, O);
       if (t1.nd != 0) return false;
       p.bind(a, t1);
-      strided_load<K, TIER, 0, L>(p, base, roff, r);
+      strided_load<K, TIER, 0, L, SP>(p, base, roff, r);
       return true;
     };
     for (;;) {
       const bool mb = next(pb, rb);
-      strided_store<K, TIER, 0, L, NT>(a, pa, base, r0, n, M, R64, ra, slot, active);
+      strided_store<K, TIER, 0, L, NT, SP>(a, pa, base, r0, n, M, R64, ra, dl, slot, active);
       if (!mb) break;
       const bool ma = next(pa, ra);
-      strided_store<K, TIER, 0, L, NT>(a, pb, base, r0, n, M, R64, rb, slot, active);
+      strided_store<K, TIER, 0, L, NT, SP>(a, pb, base, r0, n, M, R64, rb, dl, slot, active);
       if (!ma) break;
     }
   }
@@ -1014,10 +1071,28 @@ __device__ __forceinline__ void strided_cell(const SweepArgs& a, int32_t col, in
   const int32_t ihigh = (int32_t)ih;
   const int32_t t = table_index(a.map, ilow, ihigh);
   const int32_t t0 = __builtin_amdgcn_readfirstlane(t);
-  if (__all(t == t0))
-    strided_body<K, TIER, L, NDMAX, NT>(a, ilow, chunk, ihigh, t0, q, qe, slot, active);
+  if (__all(t == t0)) {
+    strided_body<K, TIER, L, NDMAX, NT>(a, ilow, chunk, ihigh, t0, a.s_tab[t0], false, q, qe,
+                                        slot, active);
+    return;
+  }
+  // Shifts that differ across the wave put its lanes on different rows in
+  // every load.  Where they take two values one apart (modulo N: a field
+  // around zero gives N-1 and 0), the wave loads one more row, the same rows
+  // in every lane, and each lane picks its window.
+  const int32_t s = a.s_tab[t];
+  const int32_t s0 = __builtin_amdgcn_readfirstlane(s);
+  const int32_t N = a.N;
+  const int32_t up = s0 + 1 == N ? 0 : s0 + 1;
+  const int32_t dn = s0 == 0 ? N - 1 : s0 - 1;
+  if (__all(s == s0 || s == up))
+    strided_body<K, TIER, L, NDMAX, NT, 1>(a, ilow, chunk, ihigh, t, up, s == s0, q, qe, slot,
+                                           active);
+  else if (__all(s == s0 || s == dn))
+    strided_body<K, TIER, L, NDMAX, NT, 1>(a, ilow, chunk, ihigh, t, s0, s == dn, q, qe, slot,
+                                           active);
   else
-    strided_body<K, TIER, L, NDMAX, NT>(a, ilow, chunk, ihigh, t, q, qe, slot, active);
+    strided_body<K, TIER, L, NDMAX, NT>(a, ilow, chunk, ihigh, t, s, false, q, qe, slot, active);
 }
 
 // Lane form of a sweep along any dimension: one output cell per lane,
@@ -1050,9 +1125,11 @@ __device__ __forceinline__ void lane_cell(const SweepArgs& a, int64_t c, int32_t
   const int32_t t = table_index(a.map, ilow, ihigh);
   const int32_t t0 = __builtin_amdgcn_readfirstlane(t);
   if (__all(t == t0))
-    strided_body<K, TIER, 1, NDMAX, NT>(a, ilow, row, ihigh, t0, q, qe, slot, active);
+    strided_body<K, TIER, 1, NDMAX, NT>(a, ilow, row, ihigh, t0, a.s_tab[t0], false, q, qe, slot,
+                                        active);
   else
-    strided_body<K, TIER, 1, NDMAX, NT>(a, ilow, row, ihigh, t, q, qe, slot, active);
+    strided_body<K, TIER, 1, NDMAX, NT>(a, ilow, row, ihigh, t, a.s_tab[t], false, q, qe, slot,
+                                        active);
 }
 
 // Work decomposition: a wave takes 64 consecutive columns (column =
@@ -1067,17 +1144,9 @@ __device__ __forceinline__ void lane_cell(const SweepArgs& a, int64_t c, int32_t
 // short) run on one XCD, one after the other.
 template <int K, int TIER, int L, int NDMAX, int NT>
 __global__ __launch_bounds__(256) void sweep_strided_kernel(SweepArgs a) {
-  uint32_t bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
-  const uint32_t gx = gridDim.x, gz = gridDim.z;
-  if (a.xcd) {
-    const uint32_t t = xcd_tile(blockIdx.x + gx * (blockIdx.y + gridDim.y * blockIdx.z),
-                                gx * gridDim.y * gz, a.xcd);
-    const uint32_t xz = gx * gz;
-    by = t / xz;
-    const uint32_t r = t - by * xz;
-    bx = r / gz;
-    bz = r - bx * gz;
-  }
+  uint32_t bx, by, bz;
+  strided_tile(a, bx, by, bz);
+  const uint32_t gx = gridDim.x;
   // the workgroup's waves: cw side by side along the columns, waves / cw
   // stacked along the row chunks
   // the wave index is uniform across the wave: said so, the row chunk and

@@ -127,9 +127,12 @@ def test_tuner_candidates_are_valid_shapes(L):
     assert {t for r, t, _ in contig if r == 1} == {t for r, t, _ in contig if r == 4}
     assert {r for r, _, _ in strided} == {0, 2, 4, 8}
     assert all(c in (1, 2, 4) and t >= 0 for _, t, c in contig)
-    assert all(c in (1, 2, 4, 17, 18, 20) and t >= 0 for _, t, c in strided)
+    flags = sl.SLDG_SHAPE_STAGED | sl.SLDG_SHAPE_MEMORDER
+    assert all(c & ~flags in (1, 2, 4) and t >= 0 for _, t, c in strided)
     staged = [(r, c) for r, _, c in strided if c & sl.SLDG_SHAPE_STAGED]
     assert staged and all(r in (4, 8) for r, _ in staged)
+    memorder = [(r, c) for r, _, c in strided if c & sl.SLDG_SHAPE_MEMORDER]
+    assert memorder and all(r > 0 for r, _ in memorder)
     assert len(set(strided)) == len(strided) and len(set(contig)) == len(contig)
 
 

@@ -508,3 +508,74 @@ def test_strided_lane_form_agrees_bitwise(sl, case, tier):
                                    what=f"{ns} k={k} {tier} dim={dim} lane form")
             else:
                 assert np.array_equal(got, ref), (rows, tuples)
+
+
+
+TWO_SHIFT_CASES = [
+    # (ns, k, swept dim, dep, ndouble): partial waves (columns not a multiple
+    # of 64), row counts that 8 does not divide, extra FP64 modes
+    ((37, 19), 3, 1, (0,), 1),
+    ((96, 13, 3), 2, 1, (0,), 1),
+    ((5, 7, 6), 2, 2, (0, 1), 1),
+    ((16, 6, 5), 2, 2, (0, 1), 2),
+    ((48, 4, 9, 10), 2, 3, (0, 1), 1),
+]
+
+
+def _two_shift_field(kind, n_line, nsig, rng):
+    """Displacements whose integer parts take two neighbouring values inside a
+    wave (modulo the line length n_line)."""
+    eps = rng.uniform(-0.01, 0.01, nsig)
+    if kind == "zero":          # s = N-1 next to s = 0
+        return eps
+    if kind == "int":           # s = 2 next to s = 3
+        return 3.0 + eps
+    if kind == "top":           # s = N-2 next to s = N-1
+        return n_line - 1.0 + eps
+    if kind == "far":           # several periods back, s = N-1 next to 0
+        return -2.0 * n_line + eps
+    # smooth: waves with one, two and three distinct shifts
+    return 1.3 * np.sin(2 * np.pi * np.arange(nsig) / max(nsig, 2)) + 0.1 * eps
+
+
+@pytest.mark.parametrize("tier", TIERS)
+@pytest.mark.parametrize("field", ["zero", "int", "top", "far", "smooth"])
+@pytest.mark.parametrize("case", TWO_SHIFT_CASES,
+                         ids=[_case_id(c) + f"-d{c[2]}" for c in TWO_SHIFT_CASES])
+def test_strided_two_shift_waves_agree_bitwise(sl, case, field, tier):
+    """A wave whose columns have two neighbouring integer shifts loads one
+    row more, the same rows in every lane, and each lane picks its window:
+    the strided sweep must give the bits of the lane form (one cell per lane,
+    own rows), under every row count and column-wave shape, and stay within
+    the arithmetic's bound of the oracle (section II-A update)."""
+    import torch
+    from gpu_helpers import download_nd, upload_nd
+    ns, k, dim, dep, nd = case
+    ndim = len(ns)
+    cells = int(np.prod(ns))
+    rng = np.random.default_rng(zlib.crc32(repr(("twoshift", ns, k, dim, field, tier, nd)).encode()))
+    state = O.to_tier(inputs.random_coefficients(ndim, k, cells, seed=int(rng.integers(1 << 30))),
+                      tier, nd, k=k, ndim=ndim)
+    p = sl.Plan(ns, k, tier, ndouble=nd)
+    m_in, h_in = upload_nd(state, p)
+    nsig = int(np.prod([ns[e] for e in dep]))
+    sig = _two_shift_field(field, ns[dim], nsig, rng)
+    mask = sum(1 << e for e in dep)
+    ref = None
+    for rows, tuples, cw in ((0, 0, 1), (1, 1, 1), (2, 0, 1), (4, 1, 2), (8, 0, 1), (8, 1, 4)):
+        p.set_shape(dim, rows, tuples, cw)
+        m_out, h_out = p.empty_state()
+        p.advect_dim(dim, _dev(sig), mask, m_in, h_in, m_out, h_out)
+        torch.cuda.synchronize()
+        got = download_nd(m_out, h_out, p)
+        if ref is None:
+            ref = got
+        else:
+            assert np.array_equal(got, ref), (rows, tuples, cw)
+        if rows == 8 and cw == 1:
+            keep = O.fp64_modes(ndim, k, nd).astype(bool)
+            want = O.sweep(state, ns, k, dim, sig, dep, tier, ndouble=nd)
+            mag = O.sweep(state, ns, k, dim, sig, dep, absolute=True)
+            assert_sweep_close(got, want, mag, tier, k, keep=keep,
+                               what=f"{ns} k={k} {tier} dim={dim} {field} two-shift waves")
+    p.close()

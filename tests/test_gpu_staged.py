@@ -1,6 +1,7 @@
 """GPU parity of the strided sweep staged through LDS (column waves plus
 SLDG_SHAPE_STAGED): a workgroup loads its tile's source rows with 16-byte
-accesses and each thread reads its own column from LDS with its own shift.
+accesses and each thread reads its own column from LDS with its own shift;
+with SLDG_SHAPE_MEMORDER the tiles (staged or direct) go in memory order.
 The arithmetic of every output is the direct strided kernel's, so the staged
 sweep must give the direct sweep's bits on every cell (section II-A update
 out[i] = A in[i-s] + B in[i-s-1]); one sweep per case is also held to the
@@ -102,21 +103,26 @@ def test_staged_sweep_is_bitwise_the_direct_sweep(sl, case, field, tier):
     for rows, cw in SHAPES:
         for tuples in (3, 0):
             outs = []
-            for flag in (0, sl.SLDG_SHAPE_STAGED):
+            flags = (0, sl.SLDG_SHAPE_STAGED, sl.SLDG_SHAPE_MEMORDER,
+                     sl.SLDG_SHAPE_STAGED | sl.SLDG_SHAPE_MEMORDER)
+            for flag in flags:
                 p.set_shape(dim, rows, tuples, cw | flag)
                 s_out = p.empty_state()
                 form = p.sweep_form(dim, mask, s_in, s_out)
-                want_form = _expected_form(ns, k, dim, tier, rows, cw) if flag else "strided"
+                staged = flag & sl.SLDG_SHAPE_STAGED
+                want_form = _expected_form(ns, k, dim, tier, rows, cw) if staged else "strided"
                 assert form == want_form, (rows, cw, flag, form)
                 nstaged += form == "staged"
                 p.advect_dim(dim, shift, mask, s_in[0], s_in[1], s_out[0], s_out[1])
                 outs.append(s_out)
             torch.cuda.synchronize()
-            what = f"{ns} k={k} d={dim} {tier} {field} rows={rows} cw={cw} tuples={tuples}"
-            assert torch.equal(outs[0][0], outs[1][0]), what + ": mass differs"
-            assert torch.equal(outs[0][1].view(torch.int16 if tier != "fp32" else torch.int32),
-                               outs[1][1].view(torch.int16 if tier != "fp32" else torch.int32)), \
-                what + ": staged differs from direct"
+            iview = torch.int16 if tier != "fp32" else torch.int32
+            for flag, o in zip(flags[1:], outs[1:]):
+                what = (f"{ns} k={k} d={dim} {tier} {field} rows={rows} cw={cw} tuples={tuples} "
+                        f"flags={flag}")
+                assert torch.equal(outs[0][0], o[0]), what + ": mass differs"
+                assert torch.equal(outs[0][1].view(iview), o[1].view(iview)), \
+                    what + ": differs from the direct sweep in the default order"
             if not checked:
                 got = download_nd(outs[1][0], outs[1][1], p)
                 want = O.sweep(state, ns, k, dim, sig, dep, tier)
