@@ -13,6 +13,7 @@ sldg_scaled_* and sldg_*_scaled entry points) against the oracle's emulation
   exponent decisions agree.
 """
 import math
+import zlib
 
 import numpy as np
 import pytest
@@ -284,3 +285,51 @@ def test_scaled_entry_points_reject_bad_arguments(sl):
     with pytest.raises(sl.SldgError) as ei:
         p16.set_scale_headroom(15)
     assert ei.value.status == sl.SLDG_ERR_ARG
+
+
+TWO_SHIFT_SCALED = [
+    # ns, k, swept dim, dep: partial waves, row counts that 8 does not divide
+    ((37, 19), 3, 1, (0,)),
+    ((96, 13, 3), 2, 1, (0,)),
+    ((48, 4, 9, 10), 2, 3, (0, 1)),
+]
+
+
+@pytest.mark.parametrize("field", ["zero", "int"])
+@pytest.mark.parametrize("ns,k,dim,dep", TWO_SHIFT_SCALED)
+def test_scaled_two_shift_waves_agree_across_shapes(sl, ns, k, dim, dep, field):
+    """Scaled FP16 sweeps whose waves hold two neighbouring integer shifts
+    (s = N-1 next to 0, or 2 next to 3): every strided launch shape, with
+    tiles in either order, gives the lane form's values, exponents and
+    absmax bits (the per-wave absmax partials see the same outputs), and the
+    result stays within the oracle's bound (section II-A update)."""
+    import torch
+    ndim = len(ns)
+    st = _random_state(ns, k, 77)
+    plan = sl.Plan(ns, k, "fp16")
+    rng = np.random.default_rng(zlib.crc32(repr((ns, k, dim, field)).encode()))
+    ntab = int(np.prod([ns[e] for e in dep]))
+    sigma = rng.uniform(-0.01, 0.01, ntab) + (3.0 if field == "int" else 0.0)
+    scaled = O.to_scaled(st, k, ndim)
+    m_in, h_in, s_in = upload_scaled(plan, scaled)
+    mask = sum(1 << e for e in dep)
+    ref = None
+    shapes = ((0, 0, 1), (1, 1, 1), (4, 1, 2), (8, 0, 1), (8, 3, 4),
+              (8, 3, 4 | sl.SLDG_SHAPE_MEMORDER), (4, 1, 1 | sl.SLDG_SHAPE_MEMORDER))
+    for rows, tuples, cw in shapes:
+        plan.set_shape(dim, rows, tuples, cw)
+        m_out, h_out = plan.empty_state()
+        s_out = plan.empty_scale()
+        plan.advect_dim_scaled(dim, _dev(sigma), mask, m_in, h_in, s_in, m_out, h_out, s_out)
+        torch.cuda.synchronize()
+        got = (m_out.cpu(), h_out.cpu().view(torch.int16), s_out.cpu())
+        if ref is None:
+            ref = got
+            want = O.sweep_scaled(*scaled, ns, k, dim, sigma, dep)
+            mag = O.sweep(scaled[0], ns, k, dim, sigma, dep, absolute=True)
+            _check_sweep(download_scaled(plan, m_out, h_out, s_out), want, mag,
+                         O.fp64_modes(ndim, k).astype(bool), k, f"{ns} dim {dim} {field}")
+        else:
+            for a, b, nm in zip(got, ref, ("mass", "hi", "scale")):
+                assert torch.equal(a, b), (rows, tuples, cw, nm)
+    plan.close()
