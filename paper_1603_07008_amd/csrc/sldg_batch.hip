@@ -166,10 +166,17 @@ sldg_status build_sweep_impl(sldg_batch_s* b, int q) {
       const int64_t xt = ((int64_t)a.P * a.Q + 63) / 64;
       const int64_t zt = ((int64_t)a.nchunk + 3) / 4;
       auto& bk = bucket[class_of(2, b->k[p])];
-      // row chunk groups fastest: the halo rows shared between them meet on one XCD
+      // Memory order: the column blocks of a row chunk group first.  Rows of
+      // N_x cells rarely start on a cache line, so neighbouring blocks share a
+      // line in every row; with the blocks of a group next to each other (and
+      // the next group N_x / 64 items later) those lines meet on one XCD.
+      // Measured on the batched Landau workload: the v classes fetched
+      // 1.21-1.32 x the state per launch with the row chunk groups of a
+      // block together, 1.09-1.16 x in this order; the step went from 2.51
+      // to 2.43 ms.
       for (int32_t qg = 0; qg < nq; ++qg)
-        for (int64_t x = 0; x < xt; ++x)
-          for (int64_t z = 0; z < zt; ++z) bk.push_back({p, 2, (int32_t)x, qg, (int32_t)z});
+        for (int64_t z = 0; z < zt; ++z)
+          for (int64_t x = 0; x < xt; ++x) bk.push_back({p, 2, (int32_t)x, qg, (int32_t)z});
     }
   }
   std::vector<BatchItem> items;
