@@ -255,20 +255,19 @@ __global__ __launch_bounds__(256) void sweep_xy_kernel(XYArgs a) {
   // same for every item (i0 and N0 are multiples of 4, s0 is uniform over
   // the slab): phase 2 is compiled for each of the 4 offsets and takes the
   // window by fixed indices instead of per-lane selects.
-  // Items (j1, u, b) are walked as (q, r, b) of a Walk over O x rows x nb:
-  // thread tid takes items tid, tid + 256, ... without a division per item.
   T res[kXYMaxItems][O][4];
   double res64[kXYMaxItems][4];
-  Walk w2;
-  w2.init((int32_t)threadIdx.x, rows, nb);
+  const int32_t nitem = O * rows * nb;
   auto phase2 = [&](auto dc) {
     constexpr int D = decltype(dc)::value;
-    Walk w = w2;
 #pragma unroll
-    for (int it = 0; it < kXYMaxItems; ++it, w.next()) {
-      if (w.q >= O) break;
-      const int32_t j1 = w.q, u = w.r;
-      const int32_t i0 = 4 * w.b;
+    for (int it = 0; it < kXYMaxItems; ++it) {
+      const int32_t item = (int32_t)threadIdx.x + 256 * it;
+      if (item >= nitem) break;
+      const int32_t j1 = item / (rows * nb);
+      const int32_t e4 = item - j1 * (rows * nb);
+      const int32_t u = (int32_t)a.fnb.div((uint32_t)e4);
+      const int32_t i0 = 4 * (e4 - u * nb);
       int32_t c = i0 - sh0 - 1;
       if (c < 0) c += N0;
       const int32_t blk0 = c & ~3;
@@ -314,10 +313,12 @@ __global__ __launch_bounds__(256) void sweep_xy_kernel(XYArgs a) {
   }
   __syncthreads();
 #pragma unroll
-  for (int it = 0; it < kXYMaxItems; ++it, w2.next()) {
-    if (w2.q >= O) break;
-    const int32_t j1 = w2.q;
-    const int32_t poff = w2.r * N0 + 4 * w2.b;
+  for (int it = 0; it < kXYMaxItems; ++it) {
+    const int32_t item = (int32_t)threadIdx.x + 256 * it;
+    if (item >= nitem) break;
+    const int32_t j1 = item / (rows * nb);
+    const int32_t e4 = item - j1 * (rows * nb);
+    const int32_t poff = 4 * e4;
     const bool nd1 = has64 && j1 == 0;
 #pragma unroll
     for (int j0 = 0; j0 < O; ++j0) {
