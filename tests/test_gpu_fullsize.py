@@ -241,3 +241,39 @@ def test_full_size_fused_step_is_bitwise_the_unfused_step(sl, big, tier):
     for a, b in zip(out[True], out[False]):
         assert torch.equal(a.view(torch.uint8), b.view(torch.uint8)), tier
     plan.close()
+
+
+@pytest.mark.parametrize("tier", ["fp32", "bf16"])
+def test_full_size_memory_order_covers_every_cell(sl, big, tier):
+    """The v sweeps of the 48^4 workload with memory-order tiles
+    (SLDG_SHAPE_MEMORDER; v1 in dispatch order, v2 in XCD runs), direct and
+    staged: outputs filled with NaN beforehand, every cell bitwise the
+    default order's result, so that no tile is skipped or written twice
+    with other data (section II-A update; the order changes no arithmetic)."""
+    import torch
+    prob, st0 = big
+    state = O.to_tier(st0, tier)
+    plan = sl.Plan(prob.ns, prob.k, tier)
+    s_in = _upload(sl, torch, state, tier)
+    ity = torch.int32 if tier == "fp32" else torch.int16
+    mo = sl.SLDG_SHAPE_MEMORDER
+    for sw in prob.seq:
+        if sw.dim < 2:
+            continue
+        shift = torch.from_numpy(sw.sigma).cuda()
+        plan.set_shape(sw.dim, 8, 3, 4)
+        ref = plan.empty_state()
+        plan.advect_dim(sw.dim, shift, sw.dep_mask, *s_in, *ref)
+        out = plan.empty_state()
+        for rows, tuples, cw in ((8, 3, 4 | mo), (4, 9, 4 | mo), (8, 9, 2 | mo),
+                                 (4, 27, 4 | mo | sl.SLDG_SHAPE_STAGED),
+                                 (8, 9, 2 | mo | sl.SLDG_SHAPE_STAGED)):
+            plan.set_shape(sw.dim, rows, tuples, cw)
+            out[0].fill_(float("nan"))
+            out[1].fill_(float("nan"))
+            plan.advect_dim(sw.dim, shift, sw.dep_mask, *s_in, *out)
+            torch.cuda.synchronize()
+            what = f"{tier} dim {sw.dim} rows {rows} tuples {tuples} colwaves {cw}"
+            assert torch.equal(out[0], ref[0]), what
+            assert torch.equal(out[1].view(ity), ref[1].view(ity)), what
+    plan.close()

@@ -565,6 +565,8 @@ def test_strided_two_shift_waves_agree_bitwise(sl, case, field, tier):
     for rows, tuples, cw in ((0, 0, 1), (1, 1, 1), (2, 0, 1), (4, 1, 2), (8, 0, 1), (8, 1, 4)):
         p.set_shape(dim, rows, tuples, cw)
         m_out, h_out = p.empty_state()
+        m_out.fill_(float("nan"))                 # a cell left unwritten fails
+        h_out.fill_(float("nan"))
         p.advect_dim(dim, _dev(sig), mask, m_in, h_in, m_out, h_out)
         torch.cuda.synchronize()
         got = download_nd(m_out, h_out, p)

@@ -108,6 +108,8 @@ def test_staged_sweep_is_bitwise_the_direct_sweep(sl, case, field, tier):
             for flag in flags:
                 p.set_shape(dim, rows, tuples, cw | flag)
                 s_out = p.empty_state()
+                s_out[0].fill_(float("nan"))      # a cell left unwritten fails
+                s_out[1].fill_(float("nan"))
                 form = p.sweep_form(dim, mask, s_in, s_out)
                 staged = flag & sl.SLDG_SHAPE_STAGED
                 want_form = _expected_form(ns, k, dim, tier, rows, cw) if staged else "strided"
