@@ -465,7 +465,9 @@ class Plan:
     # --- launch shapes and the autotuner -----------------------------------
 
     def set_shape(self, dim, rows, tuples, colwaves=1):
-        """Launch shape of the sweeps along `dim` (sldg_plan_set_shape)."""
+        """Launch shape of the sweeps along `dim` (sldg_plan_set_shape).
+        colwaves is 1, 2 or 4, plus the flags SLDG_SHAPE_STAGED (sources
+        staged through LDS) and SLDG_SHAPE_MEMORDER (tiles in memory order)."""
         _check(lib().sldg_plan_set_shape(self.handle, int(dim), int(rows), int(tuples),
                                          int(colwaves)), "sldg_plan_set_shape")
 
