@@ -1079,20 +1079,22 @@ __device__ __forceinline__ void strided_cell(const SweepArgs& a, int32_t col, in
   // Shifts that differ across the wave put its lanes on different rows in
   // every load.  Where they take two values one apart (modulo N: a field
   // around zero gives N-1 and 0), the wave loads one more row, the same rows
-  // in every lane, and each lane picks its window.
+  // in every lane, and each lane picks its window.  Equal shifts (entries
+  // that differ in alpha only) and wider spreads take the general body.
   const int32_t s = a.s_tab[t];
   const int32_t s0 = __builtin_amdgcn_readfirstlane(s);
   const int32_t N = a.N;
   const int32_t up = s0 + 1 == N ? 0 : s0 + 1;
   const int32_t dn = s0 == 0 ? N - 1 : s0 - 1;
-  if (__all(s == s0 || s == up))
-    strided_body<K, TIER, L, NDMAX, NT, 1>(a, ilow, chunk, ihigh, t, up, s == s0, q, qe, slot,
+  const bool two_up = __all(s == s0 || s == up);
+  const bool two = !__all(s == s0) && (two_up || __all(s == s0 || s == dn));
+  if (two) {
+    const int32_t shi = two_up ? up : s0;                // the larger of the two
+    strided_body<K, TIER, L, NDMAX, NT, 1>(a, ilow, chunk, ihigh, t, shi, s != shi, q, qe, slot,
                                            active);
-  else if (__all(s == s0 || s == dn))
-    strided_body<K, TIER, L, NDMAX, NT, 1>(a, ilow, chunk, ihigh, t, s0, s == dn, q, qe, slot,
-                                           active);
-  else
+  } else {
     strided_body<K, TIER, L, NDMAX, NT>(a, ilow, chunk, ihigh, t, s, false, q, qe, slot, active);
+  }
 }
 
 // Lane form of a sweep along any dimension: one output cell per lane,
