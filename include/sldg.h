@@ -21,8 +21,9 @@
  * mode in FP64 while the others are narrower is the paper's mixed-precision
  * scheme (section II-A, the paragraph on the storage of c_0; section III-A); it
  * conserves the total mass to FP64 rounding.  Larger ndouble keeps more
- * leading coefficients in FP64 (the "number of doubles" of the paper's
- * section III-A and its tables); ndouble = 0 stores every mode narrow.
+ * leading coefficients in FP64 (the count of double-precision coefficients
+ * that section III-A and its tables vary); ndouble = 0 stores every mode
+ * narrow.
  *
  * All state pointers are device pointers (HIP device memory) owned by the
  * caller.  A plan owns only small device tables.  Functions never abort: they
