@@ -119,7 +119,8 @@ def test_graph_replays_match_eager_and_tuning_keeps_results(sl):
 def test_batch_lane_and_tiled_forms_agree_bitwise(sl, tier):
     """The lane form (rows 1 for the non-window dimension-0 classes, rows 0
     for the strided classes) and the tiled forms (4-cell groups, 8 rows per
-    thread), with one tuple or all per thread, give the same bits."""
+    thread), with one tuple or all per thread, give the same bits on every
+    cell (the second buffer starts as NaN)."""
     import torch
     probs = _problems()
     stream = torch.cuda.Stream()
@@ -137,6 +138,8 @@ def test_batch_lane_and_tiled_forms_agree_bitwise(sl, tier):
                 for i in range(len(probs)):
                     s0[i][0].copy_(init[i][0])
                     s0[i][1].copy_(init[i][1])
+                    s1[i][0].fill_(float("nan"))
+                    s1[i][1].fill_(float("nan"))
                 res = b.run(2)
                 stream.synchronize()
                 got = [download(*(s0, s1)[res][i]) for i in range(len(probs))]
