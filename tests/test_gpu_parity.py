@@ -519,6 +519,8 @@ TWO_SHIFT_CASES = [
     ((5, 7, 6), 2, 2, (0, 1), 1),
     ((16, 6, 5), 2, 2, (0, 1), 2),
     ((48, 4, 9, 10), 2, 3, (0, 1), 1),
+    ((40, 2, 3), 1, 1, (0,), 1),            # N = 2: rows wrap every other row
+    ((70, 3), 2, 1, (0,), 1),               # N = 3
 ]
 
 
