@@ -59,7 +59,7 @@ struct sldg_plan_s {
   // scaled FP16 storage
   int scale_headroom;     // binades between a plane's absmax and 2^15
   int32_t* d_hmode;       // [n_hi] mode id of every hi plane
-  int32_t* d_redo;        // [n_hi] planes to recompute after a scaled sweep
+  int32_t* d_redo;        // [n_hi] planes to recompute after a scaled sweep, then their count
   float* d_part;          // absmax partials, grown on demand
   int64_t part_cap;       // floats in d_part
   double* d_field;        // scratch of the field solve, grown on demand
@@ -525,7 +525,7 @@ sldg_status run_sweep(sldg_plan_s* p, int dim, const double* shift, uint32_t dep
   if (tst != SLDG_OK) return tst;
   if (scaled) {
     e = launch_scale_predict(p->n_hi, sin.exp, sin.amax, sout.exp, p->scale_headroom, p->d_part,
-                             p->n_hi * (int64_t)a.nslot, p->stream);
+                             p->n_hi * (int64_t)a.nslot, p->d_redo + p->n_hi, p->stream);
     if (e != hipSuccess) return device_error(e, "scale prediction launch");
   }
   e = launch_sweep(p->k, (int)p->tier, dim, a, p->stream);
@@ -534,9 +534,11 @@ sldg_status run_sweep(sldg_plan_s* p, int dim, const double* shift, uint32_t dep
   if (e != hipSuccess) return device_error(e, "sweep launch");
   if (scaled) {
     e = launch_scale_decide(p->n_hi, p->d_part, a.nslot, sout.exp, sout.amax, p->d_redo,
+                            p->d_redo + p->n_hi,
                             p->stream);
     if (e != hipSuccess) return device_error(e, "scale decision launch");
-    e = launch_scale_redo(p->k, dim, a, p->n_hi, p->d_redo, p->d_hmode, p->stream);
+    e = launch_scale_redo(p->k, dim, a, p->n_hi, p->d_redo, p->d_redo + p->n_hi, p->d_hmode,
+                          p->stream);
     if (e != hipSuccess) return device_error(e, "scale repair launch");
   }
   return timing_end(p, timed, dim);
@@ -792,7 +794,7 @@ sldg_status sldg_plan_ex(sldg_plan_t* out, int ndim, const int64_t* ncells, int 
     for (int64_t m = 0; m < p->modes; ++m)
       if (p->h_pmap[m] >= 0) hmode[(size_t)p->h_pmap[m]] = (int32_t)m;
     e = dev_malloc(&p->d_hmode, sizeof(int32_t) * p->n_hi);
-    if (e == hipSuccess) e = dev_malloc(&p->d_redo, sizeof(int32_t) * p->n_hi);
+    if (e == hipSuccess) e = dev_malloc(&p->d_redo, sizeof(int32_t) * (p->n_hi + 1));
     if (e == hipSuccess)
       e = hipMemcpy(p->d_hmode, hmode.data(), sizeof(int32_t) * p->n_hi, hipMemcpyHostToDevice);
   }

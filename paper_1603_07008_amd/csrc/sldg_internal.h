@@ -171,18 +171,20 @@ int sweep_form(int dim, const SweepArgs& a);
 // Scaled FP16 storage (sldg_kernels.hip).  A scale block holds int32 exp[n_hi]
 // followed by float amax[n_hi].
 //   predict: out exp from the input's absmax (or the input exp when that is
-//            0) with `headroom` binades; zeroes the partials.
+//            0) with `headroom` binades; zeroes the partials and the count of
+//            planes to redo.
 //   decide:  out amax = max of the partials; a plane whose absmax reaches
 //            2^15 at its predicted exponent gets the exponent of its absmax
-//            with one binade of headroom and is flagged in redo[].
+//            with one binade of headroom, is flagged in redo[] and counted.
 //   redo:    recomputes the flagged planes with their final exponents.
 hipError_t launch_scale_predict(int64_t n_hi, const int32_t* in_exp, const float* in_amax,
                                 int32_t* out_exp, int headroom, float* part, int64_t npart,
-                                hipStream_t st);
+                                int32_t* nredo, hipStream_t st);
 hipError_t launch_scale_decide(int64_t n_hi, const float* part, int32_t nslot, int32_t* out_exp,
-                               float* out_amax, int32_t* redo, hipStream_t st);
+                               float* out_amax, int32_t* redo, int32_t* nredo, hipStream_t st);
 hipError_t launch_scale_redo(int k, int dim, const SweepArgs& a, int64_t n_hi,
-                             const int32_t* redo, const int32_t* hi_mode, hipStream_t st);
+                             const int32_t* redo, const int32_t* nredo, const int32_t* hi_mode,
+                             hipStream_t st);
 // import: absmax and exponent of every plane of an FP64 array [n_hi][cells],
 // then the scaled RNE conversion to FP16.  export: the values the FP16 planes
 // represent, in FP64.

@@ -331,9 +331,11 @@ __global__ __launch_bounds__(256) void scale_predict_kernel(int64_t n_hi,
                                                             int32_t* __restrict__ out_exp,
                                                             int headroom,
                                                             float* __restrict__ part,
-                                                            int64_t npart) {
+                                                            int64_t npart,
+                                                            int32_t* __restrict__ nredo) {
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (i0 == 0) *nredo = 0;
   for (int64_t p = i0; p < n_hi; p += stride)
     out_exp[p] = storage_exponent(in_amax[p], headroom, in_exp[p]);
   for (int64_t i = i0; i < npart; i += stride) part[i] = 0.0f;
@@ -341,11 +343,11 @@ __global__ __launch_bounds__(256) void scale_predict_kernel(int64_t n_hi,
 
 hipError_t launch_scale_predict(int64_t n_hi, const int32_t* in_exp, const float* in_amax,
                                 int32_t* out_exp, int headroom, float* part, int64_t npart,
-                                hipStream_t st) {
+                                int32_t* nredo, hipStream_t st) {
   const int64_t need = std::max(n_hi, npart);
   const unsigned blocks = (unsigned)std::min<int64_t>(2048, std::max<int64_t>(1, (need + 255) / 256));
   scale_predict_kernel<<<blocks, 256, 0, st>>>(n_hi, in_exp, in_amax, out_exp, headroom, part,
-                                               npart);
+                                               npart, nredo);
   return hipGetLastError();
 }
 
@@ -365,7 +367,7 @@ constexpr int kDecideThreads = 1024;
 
 __global__ __launch_bounds__(kDecideThreads) void scale_decide_kernel(
     const float* __restrict__ part, int32_t nslot, int32_t* __restrict__ out_exp,
-    float* __restrict__ out_amax, int32_t* __restrict__ redo) {
+    float* __restrict__ out_amax, int32_t* __restrict__ redo, int32_t* __restrict__ nredo) {
   __shared__ float sh[kDecideThreads / 64];
   const int64_t p = blockIdx.x;
   const float* q = part + p * nslot;
@@ -390,14 +392,15 @@ __global__ __launch_bounds__(kDecideThreads) void scale_decide_kernel(
     }
     out_amax[p] = m;
     redo[p] = fix;
+    if (fix) atomicAdd(nredo, 1);
   }
 }
 
 hipError_t launch_scale_decide(int64_t n_hi, const float* part, int32_t nslot, int32_t* out_exp,
-                               float* out_amax, int32_t* redo, hipStream_t st) {
+                               float* out_amax, int32_t* redo, int32_t* nredo, hipStream_t st) {
   if (n_hi <= 0) return hipSuccess;
   scale_decide_kernel<<<(unsigned)n_hi, kDecideThreads, 0, st>>>(part, nslot, out_exp, out_amax,
-                                                                 redo);
+                                                                 redo, nredo);
   return hipGetLastError();
 }
 
@@ -409,11 +412,15 @@ hipError_t launch_scale_decide(int64_t n_hi, const float* part, int32_t nslot, i
 template <int K>
 __global__ __launch_bounds__(256) void scale_redo_kernel(SweepArgs a, int32_t n_hi,
                                                          const int32_t* __restrict__ redo,
+                                                         const int32_t* __restrict__ nredo,
                                                          const int32_t* __restrict__ hi_mode) {
   constexpr int O = K + 1;
   constexpr int kList = 4096;          // >= the most narrow planes of a plan (4^6 - 1)
   __shared__ int32_t list[kList];
   __shared__ int32_t count;
+  // the decision kernel counted the flagged planes: usually none, and then
+  // every workgroup leaves after one load
+  if (__builtin_amdgcn_readfirstlane(*nredo) == 0) return;
   if (threadIdx.x == 0) count = 0;
   __syncthreads();
   for (int32_t p = threadIdx.x; p < n_hi; p += blockDim.x)
@@ -477,14 +484,14 @@ __global__ __launch_bounds__(256) void scale_redo_kernel(SweepArgs a, int32_t n_
 }
 
 hipError_t launch_scale_redo(int k, int dim, const SweepArgs& a, int64_t n_hi,
-                             const int32_t* redo, const int32_t* hi_mode, hipStream_t st) {
+                             const int32_t* redo, const int32_t* nredo, const int32_t* hi_mode, hipStream_t st) {
   (void)dim;
   if (n_hi <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, (a.cells + 255) / 256));
   switch (k) {
-    case 1: scale_redo_kernel<1><<<blocks, 256, 0, st>>>(a, (int32_t)n_hi, redo, hi_mode); break;
-    case 2: scale_redo_kernel<2><<<blocks, 256, 0, st>>>(a, (int32_t)n_hi, redo, hi_mode); break;
-    case 3: scale_redo_kernel<3><<<blocks, 256, 0, st>>>(a, (int32_t)n_hi, redo, hi_mode); break;
+    case 1: scale_redo_kernel<1><<<blocks, 256, 0, st>>>(a, (int32_t)n_hi, redo, nredo, hi_mode); break;
+    case 2: scale_redo_kernel<2><<<blocks, 256, 0, st>>>(a, (int32_t)n_hi, redo, nredo, hi_mode); break;
+    case 3: scale_redo_kernel<3><<<blocks, 256, 0, st>>>(a, (int32_t)n_hi, redo, nredo, hi_mode); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

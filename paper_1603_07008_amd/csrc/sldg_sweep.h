@@ -369,13 +369,13 @@ struct Planes {
 // each narrow output plane goes to slot `slot` of that plane's partials.
 // Every lane of the wave must be here (lanes beyond the grid work on a
 // duplicate of a valid cell and do not store).
-// Every lane stores the wave's maximum (a wave-uniform value) to the same
-// address, one write.  The store is a buffer store, and without partials
-// (unscaled FP16) it goes to an empty buffer and touches no memory: the
-// tuple loops then issue the same memory operations on every path, and the
-// waits for the next tuple's loads do not wait for the stores issued after
-// them (one counter covers loads and stores).  The host keeps the partials
-// below 2^31 bytes.
+// One buffer store per tuple: lane j writes the maximum of the tuple's j-th
+// narrow plane (wave-uniform values) and the other lanes an offset past the
+// buffer, which writes nothing.  Without partials (unscaled FP16) the store
+// goes to an empty buffer and touches no memory: the tuple loops then issue
+// the same memory operations on every path, and the waits for the next
+// tuple's loads do not wait for the stores issued after them (one counter
+// covers loads and stores).  The host keeps the partials below 2^31 - 4 bytes.
 template <int K, int TIER, int ND>
 __device__ __forceinline__ void flush_amax(const SweepArgs& a, const Planes<K, TIER, ND>& pl,
                                            const float (&am)[K + 1], int32_t slot) {
@@ -383,13 +383,18 @@ __device__ __forceinline__ void flush_amax(const SweepArgs& a, const Planes<K, T
     const bool on = a.amax_part != nullptr;
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         a.amax_part, (short)0, on ? 0x7fffffff : 0, 0x00020000);
+    const int32_t lane = (int32_t)(threadIdx.x & 63);
+    float mv = 0.0f;
+    int32_t off = 0x7fffffff;                  // past the buffer: no write
 #pragma unroll
     for (int l = ND; l < K + 1; ++l) {
       const float m = on ? wave_max(am[l]) : 0.0f;
-      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, m), rs,
-                                            (int32_t)(((int64_t)pl.hp[l] * a.nslot + slot) * 4),
-                                            0, 0);
+      if (lane == l - ND) {
+        mv = m;
+        off = (int32_t)(((int64_t)pl.hp[l] * a.nslot + slot) * 4);
+      }
     }
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, mv), rs, off, 0, 0);
   }
 }
 
